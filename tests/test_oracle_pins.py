@@ -1,0 +1,477 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside the oracle itself.
+
+Each test checks the oracle against something other than its own formulas:
+worked examples printed in the paper, closed-form Poisson eigenpairs, dense
+direct solves and eigendecompositions (numpy/scipy), the defining property of
+IC(0), and invariants of the projected iteration.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from paper_2203_08498_amd import problems as P
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense(p):
+    return P.csr_to_dense(p.rowptr, p.col, p.val)
+
+
+def small3d(N=6, seed_cfg=2):
+    return P.config2(N=N, nsph=1, radius=2.0, cfg=seed_cfg)
+
+
+# ---------------------------------------------------------------- sampling A
+
+def test_sampling_method_a_worked_examples():
+    """Sec. 4.3 example (m=4, N=1000) and the commented variant (m=4, N=5000)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "sampling_method_a.txt")) if l[0] != "#"]
+    assert len(rows) == 2
+    for r in rows:
+        m, N = int(r[0]), int(r[1])
+        want = sorted(int(t) for t in r[2:])
+        got = sorted(O.sample_schedule(m, N).tolist())
+        assert got == want
+
+
+def test_sampling_partial_and_brute_force_properties():
+    # fewer iterations than slots: only the filled slots survive, never x_0
+    got = O.sample_schedule(4, 3)
+    assert sorted(t for t in got if t > 0) == [1, 2]
+    # kept iterations are multiples of the final interval h and distinct
+    for m in (2, 4, 8, 16):
+        for N in (37, 200, 1023, 4097):
+            kept = [int(t) for t in O.sample_schedule(m, N) if t > 0]
+            assert len(kept) == len(set(kept)) == min(m, N - 1)
+            assert max(kept) < N
+
+
+def test_sampling_solve_matches_schedule():
+    p = P.config1()
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    o.arm_sampling(8)
+    x, info = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE)
+    sched = O.sample_schedule(8, info.iters)
+    assert np.array_equal(np.sort(o.samples(8)), np.sort(sched.astype(np.int32)))
+
+
+# ---------------------------------------------------------------- permutation, SpMV
+
+def test_permutation_is_stable_colour_sort():
+    p = small3d(6)
+    o = O.Oracle.from_problem(p)
+    assert np.array_equal(o.perm, np.argsort(p.colors, kind="stable").astype(np.int32))
+    rp, c, v = o.permuted_csr()
+    A = dense(p)
+    Ap = P.csr_to_dense(rp, c, v)
+    pm = o.perm
+    assert np.array_equal(Ap, A[np.ix_(pm, pm)])
+
+
+def test_spmv_matches_dense():
+    p = small3d(7)
+    o = O.Oracle.from_problem(p)
+    x = np.random.default_rng(0).standard_normal(p.n)
+    assert np.abs(o.spmv(x) - dense(p) @ x).max() < 1e-14
+
+
+# ---------------------------------------------------------------- IC(0)
+
+def _ic0_dense_kij(A, pattern):
+    """Right-looking (kij) incomplete Cholesky with fill dropped outside ``pattern``."""
+    n = A.shape[0]
+    L = np.tril(A).copy()
+    for k in range(n):
+        L[k, k] = np.sqrt(L[k, k])
+        for i in range(k + 1, n):
+            if pattern[i, k]:
+                L[i, k] /= L[k, k]
+        for j in range(k + 1, n):
+            for i in range(j, n):
+                if pattern[i, j] and pattern[i, k] and pattern[j, k]:
+                    L[i, j] -= L[i, k] * L[j, k]
+    return np.tril(L)
+
+
+@pytest.mark.parametrize("kind", ["fv7", "q1"])
+def test_ic0_defining_property_and_dense_kij(kind):
+    p = small3d(5) if kind == "fv7" else P.config4(Ne=6, nblk=1, blk=2)
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    rp, c, v = o.factor_csr()
+    L = P.csr_to_dense(rp, c, v)
+    arp, ac, av = o.permuted_csr()
+    Ap = P.csr_to_dense(arp, ac, av)
+    pat = P.csr_to_dense(arp, ac, np.ones_like(av)) != 0
+    # L is lower triangular with positive diagonal on the lower stored pattern
+    assert np.all(np.triu(L, 1) == 0) and np.all(np.diag(L) > 0)
+    assert np.all((L != 0) <= np.tril(pat))
+    # IC(0): (L L^T)_ij = a_ij on every stored position
+    R = L @ L.T
+    assert np.abs((R - Ap)[pat]).max() < 1e-13
+    # same factor as an independent (right-looking) formulation
+    assert np.abs(L - _ic0_dense_kij(Ap, pat)).max() < 1e-13
+
+
+def test_ic0_five_point_only_changes_the_diagonal():
+    """No triangles in the 5-point graph: l_ij = a_ij / l_jj, d_i = a_ii - sum a_ij^2 / d_j."""
+    p = P.config1()
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    rp, c, v = o.factor_csr()
+    d = np.zeros(p.n)
+    for i in range(p.n):
+        s = 1.0
+        for k in range(p.rowptr[i], p.rowptr[i + 1]):
+            j = p.col[k]
+            if j < i:
+                s -= p.val[k] ** 2 / d[j]
+        d[i] = s
+    diagL = v[rp[1:] - 1]
+    assert np.abs(diagL ** 2 - d).max() < 1e-14
+    for i in range(0, p.n, 61):
+        for k in range(rp[i], rp[i + 1] - 1):
+            j = c[k]
+            a = p.val[p.rowptr[i] + np.searchsorted(p.col[p.rowptr[i]:p.rowptr[i + 1]], j)]
+            assert abs(v[k] - a / np.sqrt(d[j])) < 1e-15
+
+
+def test_ic0_breakdown_on_indefinite_matrix():
+    # 2x2 [[1, 2], [2, 1]] is symmetric indefinite: the second pivot is 1 - 4 < 0
+    rp = np.array([0, 2, 4]); c = np.array([0, 1, 0, 1]); v = np.array([1.0, 2.0, 2.0, 1.0])
+    o = O.Oracle(rp, c, v)
+    assert o.factor_ic0() == O.ENOTSPD
+
+
+def test_prec_apply_is_inverse_of_LLt():
+    p = small3d(6)
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    rp, c, v = o.factor_csr()
+    L = P.csr_to_dense(rp, c, v)
+    r = np.random.default_rng(1).standard_normal(p.n)
+    z = o.prec(r)
+    pm = o.perm
+    zp = np.linalg.solve(L @ L.T, r[pm])
+    assert np.abs(z[pm] - zp).max() < 1e-12 * np.abs(zp).max()
+
+
+# ---------------------------------------------------------------- CG / ICCG
+
+def test_unpreconditioned_cg_matches_scipy_cg():
+    """With M = I the iteration is textbook CG: same iterates as scipy's CG."""
+    p = P.poisson((20, 17))
+    o = O.Oracle.from_problem(p)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n, p.n))
+    x, info = o.solve(p.f, tol=1e-10, maxit=2000, flags=O.NOPREC)
+    its = []
+    xs, st = spla.cg(A, p.f, rtol=1e-10, atol=0.0, maxiter=2000, callback=lambda xk: its.append(1))
+    assert st == 0
+    assert abs(info.iters - len(its)) <= 1
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("ordered", [False, True])
+def test_iccg_solution_against_dense_solve(ordered):
+    p = small3d(7)
+    colors = p.colors if ordered else None
+    o = O.Oracle(p.rowptr, p.col, p.val, colors)
+    o.factor_ic0()
+    x, info = o.solve(p.f, tol=1e-10, maxit=1000)
+    A = dense(p)
+    xs = np.linalg.solve(A, p.f)
+    kappa = np.linalg.cond(A)
+    assert info.converged and info.relres <= 1e-10
+    assert abs(info.true_relres - info.relres) <= 1e-12
+    assert np.linalg.norm(x - xs) <= kappa * 1e-10 * np.linalg.norm(xs)
+
+
+def test_zero_rhs_takes_zero_iterations():
+    p = small3d(5)
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    x, info = o.solve(np.zeros(p.n), tol=1e-8, maxit=100)
+    assert info.iters == 0 and info.converged and np.all(x == 0)
+
+
+def test_not_converged_status():
+    p = small3d(7)
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    x, info = o.solve(p.f, tol=1e-12, maxit=3)
+    assert info.status == O.NOT_CONVERGED and info.iters == 3
+
+
+# ---------------------------------------------------------------- kappa K1 (Lanczos from CG coefficients)
+
+def test_kappa_from_cg_coefficients_matches_poisson_closed_form():
+    shape = (48, 40)
+    p = P.poisson(shape)
+    o = O.Oracle.from_problem(p)
+    x, info = o.solve(p.f, tol=1e-12, maxit=5000, flags=O.NOPREC)
+    lam = P.poisson_spectrum(shape)
+    assert abs(info.kappa / (lam[-1] / lam[0]) - 1) < 1e-6
+    assert abs(info.lanczos_max / lam[-1] - 1) < 1e-8
+
+
+def test_kappa_iccg_matches_generalised_dense_eig():
+    p = small3d(8)
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    # a random right-hand side carries every eigencomponent, so both extreme
+    # Lanczos values converge before the residual reaches the tolerance
+    b = np.random.default_rng(0).standard_normal(p.n)
+    x, info = o.solve(b, tol=1e-15, maxit=2000)
+    rp, c, v = o.factor_csr()
+    L = P.csr_to_dense(rp, c, v)
+    pm = o.perm
+    Ap = dense(p)[np.ix_(pm, pm)]
+    ev = sla.eigh(Ap, L @ L.T, eigvals_only=True)
+    assert abs(info.kappa / (ev[-1] / ev[0]) - 1) < 1e-6
+
+
+def test_lanczos_extremes_of_known_tridiagonal():
+    # constant coefficients alpha=1/2, beta=1/4 give T = tridiag(1/2 ... ) family; compare with eigh
+    rng = np.random.default_rng(3)
+    alpha = rng.uniform(0.5, 2.0, 30)
+    beta = rng.uniform(0.1, 0.9, 29)
+    d = 1 / alpha + np.concatenate([[0], beta / alpha[:-1]])
+    e = np.sqrt(beta) / alpha[:-1]
+    ev = sla.eigh_tridiagonal(d, e, eigvals_only=True)
+    tmin, tmax = O.lanczos_extremes(alpha, beta)
+    assert abs(tmin - ev[0]) < 1e-12 * abs(ev[-1]) and abs(tmax - ev[-1]) < 1e-12 * abs(ev[-1])
+
+
+# ---------------------------------------------------------------- small dense eigensolver
+
+def test_jacobi_eig_matches_numpy():
+    rng = np.random.default_rng(4)
+    for k in (1, 2, 5, 16, 40):
+        B = rng.standard_normal((k, k))
+        S = B + B.T
+        w, V = O.sym_eig(S)
+        assert np.abs(w - np.linalg.eigvalsh(S)).max() < 1e-12 * max(1, np.abs(w).max())
+        assert np.abs(V.T @ V - np.eye(k)).max() < 1e-12
+        assert np.abs(S @ V - V * w).max() < 1e-11 * max(1, np.abs(w).max())
+
+
+# ---------------------------------------------------------------- Rayleigh-Ritz on sampled errors
+
+def _sampled(p, m=8, flags=0, theta=1e-2):
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    o.arm_sampling(m)
+    x, info = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE | flags)
+    st, ritz, mb, mt = o.build_aux(theta)
+    return o, x, info, ritz, mb, mt
+
+
+def test_gram_schmidt_and_rayleigh_ritz():
+    p = P.config1()
+    o, x, info, ritz, mb, mt = _sampled(p, 8, theta=1e-2)
+    E, W, AW, Cm = o.aux()
+    A = dense(p)
+    assert mb == E.shape[1] and mb <= 8
+    assert np.abs(E.T @ E - np.eye(mb)).max() < 1e-14
+    # every error vector lies in span(E)
+    o2 = O.Oracle.from_problem(p); o2.factor_ic0(); o2.arm_sampling(8)
+    assert np.abs(np.sort(ritz) - ritz).max() == 0
+    G = E.T @ A @ E
+    assert np.abs(ritz - np.linalg.eigvalsh(0.5 * (G + G.T))).max() < 1e-12
+    lam = np.linalg.eigvalsh(A)
+    assert ritz[0] >= lam[0] * (1 - 1e-12)  # Courant-Fischer
+    assert mt == int(np.sum(ritz < 1e-2))
+    assert np.abs(W.T @ W - np.eye(mt)).max() < 1e-13
+    assert np.abs(W.T @ A @ W - np.diag(ritz[:mt])).max() < 1e-13
+    assert np.abs(AW - A @ W).max() < 1e-14
+    assert np.abs(Cm - W.T @ A @ W).max() < 1e-14
+
+
+def test_error_vectors_span_contains_errors():
+    p = P.config1()
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    o.arm_sampling(8)
+    xs = []
+    # replay with maxit equal to each sampled iteration to recover the sampled iterates
+    x, info = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE)
+    iters = sorted(t for t in o.samples(8) if t > 0)
+    for k in iters:
+        ok = O.Oracle.from_problem(p); ok.factor_ic0()
+        xk, _ = ok.solve(p.f, tol=1e-30, maxit=int(k))
+        xs.append(xk)
+    st, ritz, mb, mt = o.build_aux(1e-2)
+    E = o.aux()[0]
+    for xk in xs:
+        e = x - xk
+        assert np.linalg.norm(e - E @ (E.T @ e)) <= 1e-9 * np.linalg.norm(e)
+
+
+def test_ritz_values_approach_isolated_small_eigenvalues():
+    """Floating stiff blocks give isolated small eigenvalues that the sampled errors capture."""
+    p = P.config4(Ne=13, nblk=2, blk=3)
+    o, x, info, ritz, mb, mt = _sampled(p, 8, theta=1e-3)
+    lam = np.linalg.eigvalsh(dense(p))
+    assert mt >= 2
+    assert np.all(np.abs(ritz[:2] / lam[:2] - 1) < 1e-3)
+
+
+# ---------------------------------------------------------------- deflation and subspace correction
+
+def _poisson_with_exact_modes(shape, k):
+    p = P.poisson(shape)
+    lam = P.poisson_spectrum(shape)
+    assert lam[k - 1] < lam[k] * (1 - 1e-6)  # a gap after the k-th eigenvalue
+    # multi-indices of the k smallest eigenvalues
+    d = len(shape)
+    idx = np.indices(shape).reshape(d, -1).T + 1
+    vals = np.array([1 - sum(np.cos(j[a] * np.pi / (shape[a] + 1)) for a in range(d)) / d for j in idx])
+    order = np.argsort(vals, kind="stable")[:k]
+    lams, V = P.poisson_eigvec(shape, [tuple(idx[t]) for t in order])
+    return p, lam, lams, V
+
+
+def test_deflation_with_exact_eigenvectors_removes_those_modes():
+    shape = (30, 23)
+    k = 6
+    p, lam, lams, V = _poisson_with_exact_modes(shape, k)
+    A = dense(p)
+    o = O.Oracle.from_problem(p)
+    o.set_aux(V)
+    x, info = o.solve(p.f, tol=1e-12, maxit=5000, mode=O.DEFLATED, flags=O.NOPREC)
+    # P A u_s = 0 for the deflated modes  (P = I - W C^{-1} (AW)^T)
+    Cm = V.T @ A @ V
+    Pm = np.eye(p.n) - V @ np.linalg.solve(Cm, (A @ V).T)
+    assert np.abs(Pm @ (A @ V)).max() < 1e-12
+    # CG on P^T A sees only the remaining spectrum: kappa -> lambda_max / lambda_{k+1}
+    assert abs(info.kappa / (lam[-1] / lam[k]) - 1) < 1e-6
+    assert np.linalg.norm(x - np.linalg.solve(A, p.f)) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_subspace_correction_with_exact_eigenvectors_shifts_modes_by_one():
+    shape = (30, 23)
+    k = 6
+    p, lam, lams, V = _poisson_with_exact_modes(shape, k)
+    o = O.Oracle.from_problem(p)
+    o.set_aux(V)
+    x, info = o.solve(p.f, tol=1e-12, maxit=5000, mode=O.SUBSPACE, flags=O.NOPREC)
+    spec = np.concatenate([lam[:k] + 1, lam[k:]])
+    assert abs(info.kappa / (spec.max() / spec.min()) - 1) < 1e-6
+
+
+def test_deflated_iterates_stay_W_orthogonal_and_final_correction():
+    p = P.config1()
+    o, x1, info, ritz, mb, mt = _sampled(p, 8, theta=1e-2)
+    assert mt > 0
+    E, W, AW, Cm = o.aux()
+    A = dense(p)
+    b = P.sequence_rhs(p.f, x1)
+    for k in (1, 5, 17, 40):
+        xk, ik = o.solve(b, tol=1e-30, maxit=k, mode=O.DEFLATED)
+        r = b - A @ xk
+        # the final assembly makes the true residual the deflated recurrence residual: W^T r = 0
+        # (rounding in b - A x is relative to ||b||; a missing projection would leave
+        # W^T r of the size of r itself)
+        bn = np.linalg.norm(b)
+        assert np.linalg.norm(W.T @ r) <= 1e-12 * bn
+        assert np.linalg.norm(W.T @ r) <= 1e-6 * np.linalg.norm(r)
+        assert abs(np.linalg.norm(r) / bn - ik.relres) <= 1e-12
+    x, info2 = o.solve(b, tol=1e-10, maxit=2000, mode=O.DEFLATED)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= np.linalg.cond(A) * 1e-10 * np.linalg.norm(xs)
+
+
+def test_deflation_and_sc_invariant_under_basis_change():
+    p = P.config1()
+    o, x1, info, ritz, mb, mt = _sampled(p, 8, theta=1e-2)
+    W = o.aux()[1]
+    b = P.sequence_rhs(p.f, x1)
+    G = np.random.default_rng(7).standard_normal((mt, mt)) + 3 * np.eye(mt)
+    for mode in (O.DEFLATED, O.SUBSPACE):
+        xa, ia = o.solve(b, tol=1e-9, maxit=2000, mode=mode)
+        o2 = O.Oracle.from_problem(p); o2.factor_ic0(); o2.set_aux(W @ G)
+        xb, ib = o2.solve(b, tol=1e-9, maxit=2000, mode=mode)
+        assert ia.iters == ib.iters
+        assert np.linalg.norm(xa - xb) <= 1e-10 * np.linalg.norm(xa)
+
+
+def test_accelerated_solvers_reduce_iterations_config1():
+    p = P.config1()
+    o, x1, info, ritz, mb, mt = _sampled(p, 8, theta=1e-2)
+    b = P.sequence_rhs(p.f, x1)
+    _, ip = o.solve(b, tol=1e-8, maxit=2000, mode=O.PLAIN)
+    _, idf = o.solve(b, tol=1e-8, maxit=2000, mode=O.DEFLATED)
+    _, isc = o.solve(b, tol=1e-8, maxit=2000, mode=O.SUBSPACE)
+    assert idf.iters < ip.iters and isc.iters < ip.iters
+    assert abs(idf.iters - isc.iters) <= 0.15 * ip.iters  # SC and deflation behave alike
+
+
+def test_theta_below_all_ritz_values_falls_back_to_plain():
+    p = P.config1()
+    o, x1, info, ritz, mb, mt = _sampled(p, 8, theta=1e-6)
+    assert mt == 0
+    x, i2 = o.solve(p.f, tol=1e-8, maxit=2000, mode=O.DEFLATED)
+    assert i2.status == O.AUX_EMPTY and i2.converged
+
+
+# ---------------------------------------------------------------- kappa K2 (paper's estimator)
+
+def test_paper_kappa_estimate_is_inside_the_true_range():
+    """Power-method lambda_max <= true, smallest Ritz >= true (the sign pattern of Table con1)."""
+    p = P.config4(Ne=13, nblk=2, blk=3)
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    o.arm_sampling(8)
+    o.set_power_start(P.power_start(4, p.n))
+    x, info = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE | O.POWER)
+    st, ritz, mb, mt = o.build_aux(1e-3)
+    x2, info2 = o.solve(P.sequence_rhs(p.f, x), tol=1e-8, maxit=5000, mode=O.DEFLATED, flags=O.POWER)
+    lam = np.linalg.eigvalsh(dense(p))
+    assert info2.lambda_max <= lam[-1] * (1 + 1e-12)
+    assert info2.lambda_min_ritz >= lam[0] * (1 - 1e-12)
+    assert info2.kappa_es <= lam[-1] / lam[0] * (1 + 1e-12)
+    assert info2.kappa_es >= 0.9 * lam[-1] / lam[0]  # isolated small modes: close
+
+
+# ---------------------------------------------------------------- adjoint gradient
+
+def test_adjoint_gradient_against_central_differences():
+    p = P.config5_dense(N=5)
+    o = O.Oracle.from_problem(p)
+    o.factor_ic0()
+    xt = P.rng_for(5, P.STREAM_XT).standard_normal(p.n)
+    b = p.f
+    x, _ = o.solve(b, tol=1e-14, maxit=5000)
+    lam_, _ = o.solve(x - xt, tol=1e-14, maxit=5000)
+    g = o.grad_values(lam_, x)
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    rng = P.rng_for(5, P.STREAM_FD)
+    h = 1e-6
+    for t in range(4):
+        # symmetric direction on the stored pattern
+        d = rng.standard_normal(p.nnz)
+        Dm = sp.csr_matrix((d, p.col, p.rowptr), shape=(p.n, p.n))
+        Ds = 0.5 * (Dm + Dm.T)
+        ds = np.asarray(Ds[rows, p.col]).ravel()
+
+        def loss(s):
+            oo = O.Oracle(p.rowptr, p.col, p.val + s * h * ds, p.colors)
+            assert oo.factor_ic0() == 0
+            xx, _ = oo.solve(b, tol=1e-15, maxit=5000)
+            return 0.5 * np.sum((xx - xt) ** 2)
+
+        fd = (loss(1) - loss(-1)) / (2 * h)
+        an = g @ ds
+        assert abs(fd - an) <= 1e-6 * abs(an)
+    # dense reference: dL/dA = -lambda x^T on the pattern
+    A = dense(p)
+    lam_d = np.linalg.solve(A, np.linalg.solve(A, b) - xt)
+    G = -np.outer(lam_d, np.linalg.solve(A, b))
+    assert np.abs(g - G[rows, p.col]).max() <= 1e-8 * np.abs(G).max()
