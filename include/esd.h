@@ -1,0 +1,186 @@
+/*
+ * esd.h - C ABI of the MI355X (gfx950) error-vector-sampling accelerated ICCG
+ * solver for a sequence of SPD systems A x_k = b_k sharing one matrix
+ * (Iwashita, Ikehara, Fukaya, Mifune, arXiv 2203.08498).
+ *
+ * Problem statement (Sec. 2, eqs. (ak2), (ak3)): A is symmetric positive
+ * definite and identical for every k; b_k depends on earlier solutions, so the
+ * systems are solved in order.  During the first solve approximate solutions
+ * are sampled (Sec. 4.2-4.3); afterwards an auxiliary matrix W is built from
+ * the sampled error vectors by Gram-Schmidt and Rayleigh-Ritz (eqs. (ek)-(bk))
+ * and later solves are accelerated by deflation (Sec. 3.3, Alg. "Deflated PCG
+ * method") or by the additive subspace-correction preconditioner (Sec. 3.2,
+ * eq. (mc)).  Each solve returns a condition-number estimate (Sec. 5.4).
+ *
+ * Conventions for every entry point
+ *   - (h) marks a host pointer, (d) a device pointer on the context's device.
+ *     Device buffers passed in or out are owned by the caller (e.g. torch
+ *     tensors); the library never frees them and never keeps them after the
+ *     call returns.  All device memory the library needs for its own state
+ *     (permuted matrix, factor, auxiliary space, work vectors) is allocated by
+ *     esd_setup / esd_build_aux and released by esd_destroy.
+ *   - Vectors (b, x0, x, lambda, v0, W) are float64 in the caller's row order;
+ *     the library permutes internally.
+ *   - Work is enqueued on the stream given to esd_setup.  Calls that return
+ *     host-side results (solve, build_aux, factor_ic0) synchronise that stream
+ *     before returning; their device outputs are then valid.
+ *   - Return value: ESD_OK (0); a positive value is a warning and the outputs
+ *     are valid; a negative value is an error, the outputs are undefined and
+ *     esd_last_error() describes it.  No C++ exception crosses this ABI.  A NULL
+ *     context or an out-of-range argument returns ESD_EINVAL.
+ *   - One context must not be used from two threads at once.
+ */
+#ifndef ESD_H
+#define ESD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esd_ctx esd_ctx;
+
+typedef enum {
+    ESD_OK = 0,
+    ESD_NOT_CONVERGED = 1, /* maxit reached (or inner stagnation); x = last iterate */
+    ESD_AUX_EMPTY = 2,     /* no Ritz value below theta / no W: solved as plain ICCG */
+    ESD_EINVAL = -1,       /* bad argument or call order */
+    ESD_ENOTSPD = -2,      /* IC(0) pivot <= 0 (matrix not SPD or IC(0) breakdown) */
+    ESD_EHIP = -3,         /* HIP runtime error */
+    ESD_ENUMERIC = -4,     /* NaN/Inf in the iteration */
+    ESD_ENOAUX = -5,       /* accelerated mode requested before build_aux/set_aux */
+    ESD_ENOSAMPLES = -6    /* build_aux without a sampling solve */
+} esd_status;
+
+/* solver modes (Sec. 5.2: ICCG, ES-D-ICCG, ES-SC-ICCG) */
+#define ESD_PLAIN 0    /* IC(0)-preconditioned CG */
+#define ESD_DEFLATED 1 /* deflated PCG, Alg. "Deflated PCG method" */
+#define ESD_SUBSPACE 2 /* PCG with M_sc^{-1} = M^{-1} + W (W^T A W)^{-1} W^T, eq. (mc) */
+
+/* solve flags */
+#define ESD_FLAG_NOPREC 1 /* M = I (unpreconditioned CG), used for closed-form checks */
+#define ESD_FLAG_POWER 2  /* power iteration fused into the SpMV, (q v) = A (p v) (Alg. PCG-con) */
+#define ESD_FLAG_MIXED 4  /* FP32 inner solves inside an FP64 iterative-refinement loop */
+#define ESD_FLAG_SYNC_EVERY 8 /* check convergence after every iteration (no speculative chunk) */
+#define ESD_FLAG_TIMING 16    /* hipEvents around the SpMV, update and sweep launches of every executed iteration */
+
+typedef struct {
+    int32_t iters;        /* CG iterations (mixed: total inner iterations) */
+    int32_t outer_iters;  /* refinement steps (1 for FP64 solves) */
+    int32_t converged;    /* 1 if ||r||_2 <= tol ||b||_2 */
+    int32_t m_tilde;      /* columns of W used by this solve (0 for PLAIN) */
+    int32_t nsamples;     /* sampling stores made during this solve */
+    int32_t mode_used;    /* ESD_PLAIN if an accelerated mode fell back */
+    double relres;        /* recurrence residual norm / ||b|| at exit */
+    double true_relres;   /* ||b - A x||_2 / ||b||_2 recomputed in FP64 */
+    double kappa;         /* K1: extreme Lanczos values from the CG alpha/beta */
+    double kappa_es;      /* K2: power-method lambda_max / smallest Ritz value (Sec. 5.4) */
+    double lambda_max;    /* (v, A v) of the power iteration (0 without ESD_FLAG_POWER) */
+    double lambda_min_ritz; /* smallest Ritz value of the last build_aux (0 if none) */
+    double lanczos_min, lanczos_max; /* extreme eigenvalues of the Lanczos matrix */
+    double seconds;       /* wall time of the solve on the stream (hipEvent) */
+} esd_info;
+
+/*
+ * esd_setup - take one SPD matrix and an ordering; build the device formats.
+ *   n, rowptr(h) int64[n+1], col(h) int32[nnz], val(h) float64[nnz]: the full
+ *     symmetric CSR of A (both triangles, diagonal stored, columns sorted).
+ *     The paper's test matrices are diagonally scaled beforehand (Sec. 5.1);
+ *     the library solves the matrix it is given.
+ *   colors(h) int32[n] or NULL: NULL keeps the natural order; otherwise rows
+ *     are ordered by a stable sort on colour, which fixes the IC(0) factor.
+ *     Rows of one colour must not be coupled (checked: ESD_EINVAL).
+ *   hip_stream: a hipStream_t (NULL = default stream) all work is queued on.
+ *   m_max: largest number of sample vectors a later esd_sample_errors may ask
+ *     for (<= 64).
+ * The caller may free its CSR arrays after the call.
+ */
+esd_status esd_setup(esd_ctx **ctx, void *hip_stream, int64_t n, const int64_t *rowptr,
+                     const int32_t *col, const double *val, const int32_t *colors, int32_t m_max);
+
+/* esd_factor_ic0 - IC(0) on the stored lower pattern in the chosen order (the
+ * paper's IC preconditioner, Sec. 4.4).  FP64 factor plus an FP32 copy.
+ * ESD_ENOTSPD on a non-positive pivot. */
+esd_status esd_factor_ic0(esd_ctx *ctx);
+
+/* esd_sample_errors - arm sampling method A (Appendix A) with m slots for the
+ * next solve: x_i is stored in slot (sum_l (-1)^l floor((i-1)/m^l)) mod m when
+ * i mod h == 0, h doubling at i = h m; only iterations that did not meet the
+ * stop test are sampled.  1 <= m <= m_max. */
+esd_status esd_sample_errors(esd_ctx *ctx, int32_t m);
+
+/* esd_build_aux - after a sampling solve: error vectors e = x_1 - x~ (eq.
+ * (ek)), classical Gram-Schmidt applied twice with drop tolerance 1e-10
+ * (eq. (ekd)), Ritz pairs of E^T A E (eq. (Rayleigh-Ritz)), W from the Ritz
+ * vectors with Ritz value < theta (eq. (bk)), AW = A W, C = W^T A W and its
+ * Cholesky factor.
+ *   ritz(h) float64[m] out: all m_bar Ritz values ascending (may be NULL).
+ *   m_bar(h), m_tilde(h) out: orthonormal basis size and selected columns.
+ * ESD_AUX_EMPTY (warning) when m_tilde = 0; ESD_ENOSAMPLES without samples. */
+esd_status esd_build_aux(esd_ctx *ctx, double theta, double *ritz, int32_t *m_bar,
+                         int32_t *m_tilde);
+
+/* esd_set_aux - use a caller-given auxiliary matrix W(d): n x k, column-major,
+ * float64, user row order, full column rank, 1 <= k <= 64.  Replaces any W. */
+esd_status esd_set_aux(esd_ctx *ctx, const double *W, int32_t k);
+
+/* esd_get_aux - copy out W(d) (n x m_tilde, column-major, user order; NULL to
+ * skip) and C = W^T A W (h, m_tilde x m_tilde row-major; NULL to skip). */
+esd_status esd_get_aux(esd_ctx *ctx, double *W, double *C);
+
+/* esd_set_power_start - unit start vector v0(d) of the power iteration
+ * (Alg. PCG-con, "a unit random vector").  The iterate is carried across
+ * solves that pass ESD_FLAG_POWER. */
+esd_status esd_set_power_start(esd_ctx *ctx, const double *v0);
+
+/* esd_set_mixed_params - inner relative tolerance of each FP32 inner solve
+ * (default 1e-4) and the maximum number of FP64 refinement steps (default 30). */
+esd_status esd_set_mixed_params(esd_ctx *ctx, double inner_tol, int32_t max_outer);
+
+/*
+ * esd_solve - solve A x = b.
+ *   b(d) float64[n]; x0(d) float64[n] or NULL (zero start); x(d) out.
+ *   tol: stop when ||r_i||_2 <= tol ||b||_2 (Alg. "Deflated PCG method" loop
+ *     test; for ESD_FLAG_MIXED the FP64 true residual is tested).
+ *   maxit: iteration cap (mixed: total inner iterations).
+ *   mode: ESD_PLAIN / ESD_DEFLATED / ESD_SUBSPACE; flags: ESD_FLAG_*.
+ *   info(h) out (may be NULL).
+ * A sampling solve is the first solve after esd_sample_errors.
+ * Returns ESD_NOT_CONVERGED (warning) at maxit, ESD_AUX_EMPTY (warning) when an
+ * accelerated mode had no W, ESD_ENOAUX if no aux space was ever built. */
+esd_status esd_solve(esd_ctx *ctx, const double *b, const double *x0, double tol, int32_t maxit,
+                     int32_t mode, int32_t flags, double *x, esd_info *info);
+
+/* esd_grad_values - gradient of a loss through x = A^{-1} b with respect to
+ * every stored value: gval[k] = -lam[row k] * x[col k] in the caller's CSR
+ * order, where lam = A^{-1} (dL/dx) is the adjoint solution.
+ * lam(d), x(d) float64[n]; gval(d) float64[nnz] out. */
+esd_status esd_grad_values(esd_ctx *ctx, const double *lam, const double *x, double *gval);
+
+/* Inspection entry points (used by tests and the benchmark). */
+esd_status esd_spmv(esd_ctx *ctx, const double *x, double *y);       /* y = A x, FP64, (d) */
+esd_status esd_prec_apply(esd_ctx *ctx, const double *r, double *z); /* z = (L L^T)^{-1} r, (d) */
+esd_status esd_get_perm(esd_ctx *ctx, int32_t *perm);  /* (h) int32[n]: logical position -> user row */
+esd_status esd_get_factor_diag(esd_ctx *ctx, double *ldiag); /* (h) float64[n] l_ii, user row order */
+/* (h) alpha[cap], beta[cap] of the last solve (mixed: the first inner solve);
+ * returns the count of alphas through *count; beta has count-1 entries. */
+esd_status esd_get_history(esd_ctx *ctx, double *alpha, double *beta, int32_t cap, int32_t *count);
+/* (h) int32[m]: iteration stored in each sampling slot (0 = empty) */
+esd_status esd_get_samples(esd_ctx *ctx, int32_t *iters_by_slot);
+/* (h) int32[4]: n, nnz, number of sweep levels, number of colours */
+esd_status esd_get_layout(esd_ctx *ctx, int32_t *out4);
+/* (h) double[4] from the last solve run with ESD_FLAG_TIMING: average ms per
+ * executed iteration of out[0] the SpMV launch, out[1] all sweep launches,
+ * out[2] the vector-update launch; out[3] the number of timed iterations. */
+esd_status esd_get_timing(esd_ctx *ctx, double *out4);
+
+const char *esd_status_string(esd_status s);
+const char *esd_last_error(const esd_ctx *ctx);
+void esd_destroy(esd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESD_H */

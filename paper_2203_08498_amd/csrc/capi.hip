@@ -1,0 +1,996 @@
+// C ABI of the esd library: context, setup, factorisation, the solve loops
+// (FP64 and FP32-inner / FP64-refinement), auxiliary-space construction and
+// inspection entry points.  All per-iteration arithmetic happens in the
+// kernels of kernels.hip; this file only sequences launches and reads back a
+// small status block once per chunk of iterations.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/esd.h"
+#include "esd_internal.h"
+#include "kernels.h"
+
+using esd::Ell;
+using esd::Red;
+using esd::Scal;
+
+namespace {
+
+struct DevEll {
+    int64_t *sptr = nullptr;
+    int32_t *col = nullptr;
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+    int64_t size = 0;
+    Ell<double> e64() const { return {sptr, col, v64}; }
+    Ell<float> e32() const { return {sptr, col, v32}; }
+};
+
+template <typename T> struct VecSet {
+    T *x, *r, *z, *zsc, *y, *q, *p[2], *v[2];
+    const T *W, *AW, *dinv;
+    Ell<T> A, L, U;
+};
+
+constexpr int kFlagTiming = ESD_FLAG_TIMING;
+
+} // namespace
+
+struct esd_ctx {
+    hipStream_t stream = nullptr;
+    std::string err;
+    int64_t n = 0, nnz = 0;
+    int ncolors = 1;
+    int m_max = 0;
+    std::vector<int64_t> lvl;
+    std::vector<int32_t> p2u_h, lperm_h;
+    DevEll A, L, U;
+    int64_t *u_from_l = nullptr;
+    double *adiag = nullptr, *ldiag = nullptr, *dinv = nullptr;
+    float *dinv32 = nullptr;
+    int32_t *p2u = nullptr;
+    int64_t *urp = nullptr;
+    int32_t *ucol = nullptr;
+    int *bad = nullptr;
+    // FP64 vectors (n + 1 entries, zero at n)
+    double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *zsc = nullptr, *y = nullptr,
+           *q = nullptr, *p[2] = {nullptr, nullptr}, *t = nullptr, *v[2] = {nullptr, nullptr};
+    // FP32 vectors
+    float *r32 = nullptr, *z32 = nullptr, *zsc32 = nullptr, *y32 = nullptr, *q32 = nullptr,
+          *p32[2] = {nullptr, nullptr}, *d32 = nullptr, *v32[2] = {nullptr, nullptr};
+    Red red{};
+    Scal *S = nullptr;
+    Scal *Sh = nullptr; // pinned host mirror
+    // sampling
+    int m_req = 0;
+    bool armed = false;
+    double *slots = nullptr;
+    int32_t *slot_table = nullptr;
+    int64_t slot_table_cap = 0;
+    std::vector<int32_t> table_h;
+    std::vector<int32_t> slot_iter;
+    int nsamples = 0;
+    double *xN = nullptr;
+    bool have_samples = false;
+    // auxiliary space
+    bool aux_built = false;
+    int m_bar = 0, m_tilde = 0;
+    double *E = nullptr, *AE = nullptr, *W = nullptr, *AW = nullptr;
+    float *W32 = nullptr, *AW32 = nullptr;
+    double *Cinv = nullptr, *gram_part = nullptr, *G = nullptr, *Tm = nullptr;
+    std::vector<double> Ch, ritz;
+    // power iteration state
+    bool have_v = false;
+    int vb64 = 0, vb32 = 0;
+    double vs64 = 1.0, vs32 = 1.0;
+    // history of the last solve
+    double *ha = nullptr, *hb = nullptr;
+    int64_t hcap = 0;
+    std::vector<double> ha_h, hb_h;
+    std::vector<std::pair<int, int>> segments; // (base, count) of every Krylov run
+    // mixed precision parameters
+    double inner_tol = 1e-4;
+    int max_outer = 30;
+    int stag_window = 50;
+    bool factored = false;
+    // kernel timing
+    std::vector<hipEvent_t> ev;
+    double t_spmv = 0, t_sweep = 0, t_upd = 0;
+    int t_count = 0;
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            c->err = std::string(#expr) + ": " + hipGetErrorString(e_);                            \
+            return ESD_EHIP;                                                                       \
+        }                                                                                          \
+    } while (0)
+
+template <typename T> hipError_t dalloc(T **p, int64_t count) {
+    if (count <= 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)count);
+}
+
+esd_status fail(esd_ctx *c, esd_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+esd_status upload_ell(esd_ctx *c, DevEll &D, const esd::HostEll &H) {
+    D.size = (int64_t)H.col.size();
+    HIPCHK(dalloc(&D.sptr, (int64_t)H.sptr.size()));
+    HIPCHK(dalloc(&D.col, D.size));
+    HIPCHK(dalloc(&D.v64, D.size));
+    HIPCHK(dalloc(&D.v32, D.size));
+    HIPCHK(hipMemcpyAsync(D.sptr, H.sptr.data(), sizeof(int64_t) * H.sptr.size(), hipMemcpyHostToDevice, c->stream));
+    if (D.size) {
+        HIPCHK(hipMemcpyAsync(D.col, H.col.data(), sizeof(int32_t) * D.size, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(D.v64, H.val.data(), sizeof(double) * D.size, hipMemcpyHostToDevice, c->stream));
+    }
+    esd::launch_cast(D.size, D.v64, D.v32, c->stream);
+    return ESD_OK;
+}
+
+void free_ell(DevEll &D) {
+    (void)hipFree(D.sptr); (void)hipFree(D.col); (void)hipFree(D.v64); (void)hipFree(D.v32);
+    D = DevEll();
+}
+
+int grid_n(const esd_ctx *c) { return esd::grid_for(c->n); }
+
+esd_status sync_read(esd_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->Sh, c->S, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ESD_OK;
+}
+
+esd_status put_scal(esd_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->S, c->Sh, sizeof(Scal), hipMemcpyHostToDevice, c->stream));
+    return ESD_OK;
+}
+
+template <typename T> VecSet<T> vecs(esd_ctx *c);
+template <> VecSet<double> vecs<double>(esd_ctx *c) {
+    VecSet<double> V;
+    V.x = c->x; V.r = c->r; V.z = c->z; V.zsc = c->zsc; V.y = c->y; V.q = c->q;
+    V.p[0] = c->p[0]; V.p[1] = c->p[1]; V.v[0] = c->v[0]; V.v[1] = c->v[1];
+    V.W = c->W; V.AW = c->AW; V.dinv = c->dinv;
+    V.A = c->A.e64(); V.L = c->L.e64(); V.U = c->U.e64();
+    return V;
+}
+template <> VecSet<float> vecs<float>(esd_ctx *c) {
+    VecSet<float> V;
+    V.x = c->d32; V.r = c->r32; V.z = c->z32; V.zsc = c->zsc32; V.y = c->y32; V.q = c->q32;
+    V.p[0] = c->p32[0]; V.p[1] = c->p32[1]; V.v[0] = c->v32[0]; V.v[1] = c->v32[1];
+    V.W = c->W32; V.AW = c->AW32; V.dinv = c->dinv32;
+    V.A = c->A.e32(); V.L = c->L.e32(); V.U = c->U.e32();
+    return V;
+}
+
+// One application of the preconditioner (all sweep launches).  kind 2 adds
+// W u (subspace correction).  The final launch reduces (r, z) and forms beta.
+template <typename T>
+void launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, int hist_base) {
+    esd::Sweep<T> s{};
+    s.n = (int)c->n;
+    s.S = c->S;
+    s.red = c->red;
+    s.dinv = V.dinv;
+    s.r = V.r;
+    s.y = V.y;
+    s.z = V.z;
+    s.zsc = sc ? V.zsc : V.z;
+    s.W = V.W;
+    s.m = sc ? c->m_tilde : 0;
+    s.hist_beta = c->ha ? c->hb : nullptr;
+    s.hist_base = hist_base;
+    if (noprec) {
+        s.r0 = 0; s.r1 = (int)c->n; s.final_ = 1;
+        esd::launch_copyz(s, sc, grid_n(c), c->stream);
+        return;
+    }
+    const int nl = (int)c->lvl.size() - 1;
+    s.M = V.L;
+    for (int l = 0; l < nl; ++l) {
+        s.r0 = (int)c->lvl[l]; s.r1 = (int)c->lvl[l + 1];
+        const bool last = (l == nl - 1);
+        s.final_ = last && nl == 1;
+        esd::launch_fwd(s, last, sc, esd::grid_for(s.r1 - s.r0), c->stream);
+    }
+    s.M = V.U;
+    for (int l = nl - 2; l >= 0; --l) {
+        s.r0 = (int)c->lvl[l]; s.r1 = (int)c->lvl[l + 1];
+        s.final_ = (l == 0);
+        esd::launch_bwd(s, sc, esd::grid_for(s.r1 - s.r0), c->stream);
+    }
+}
+
+struct KrylovOpts {
+    int kind = 0;        // 0 plain, 1 deflated, 2 subspace correction
+    bool noprec = false;
+    bool power = false;
+    bool sampling = false;
+    bool sync_every = false;
+    bool timing = false;
+    int hist_base = 0;
+    int sample_base = 0;
+    const double *xbase = nullptr;
+    double xscale = 1.0;
+};
+
+// Runs the CG loop from the state prepared by the caller (x, r, S with
+// tol2/maxit/done set, (W^T r -> u) for subspace correction).  Returns the
+// number of completed iterations through *iters and the exit code in Sh->done.
+template <typename T>
+esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iters, int *vbase) {
+    const int n = (int)c->n;
+    const int m = (o.kind != 0) ? c->m_tilde : 0;
+    const bool sc = (o.kind == 2);
+    const int g = grid_n(c);
+    // z_0 = M^{-1} r_0 (+ W u), rho_0
+    launch_prec<T>(c, V, o.noprec, sc, o.hist_base);
+    esd::SpmvIt<T> sa{};
+    sa.n = n; sa.S = c->S; sa.red = c->red; sa.A = V.A;
+    sa.z = sc ? V.zsc : V.z;
+    sa.W = (o.kind == 1) ? V.W : nullptr;
+    sa.m = (o.kind == 1) ? m : 0;
+    sa.Cinv = c->Cinv;
+    sa.hist_alpha = c->ha;
+    sa.hist_base = o.hist_base;
+    sa.slot_table = o.sampling ? c->slot_table : nullptr;
+    sa.sample_base = o.sample_base;
+    sa.slots = c->slots;
+    sa.xit = V.x;
+    sa.xbase = o.xbase;
+    sa.xscale = o.xscale;
+    esd::UpdIt<T> ua{};
+    ua.n = n; ua.S = c->S; ua.red = c->red; ua.q = V.q; ua.x = V.x; ua.r = V.r;
+    ua.AW = V.AW; ua.W = V.W; ua.m = m; ua.Cinv = c->Cinv;
+    int launched = 0;
+    int chunk = o.sync_every ? 1 : 8;
+    const bool timing = o.timing;
+    for (;;) {
+        for (int j = 0; j < chunk; ++j) {
+            const int it = launched + j;
+            sa.pold = V.p[it & 1];
+            sa.pnew = V.p[(it + 1) & 1];
+            sa.vold = V.v[(*vbase + it) & 1];
+            sa.vnew = V.v[(*vbase + it + 1) & 1];
+            sa.q = V.q;
+            ua.p = V.p[(it + 1) & 1];
+            if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 0], c->stream));
+            esd::launch_spmv_it(sa, sa.m, o.power, g, c->stream);
+            if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 1], c->stream));
+            esd::launch_update_it(ua, m, o.kind, g, c->stream);
+            if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 2], c->stream));
+            launch_prec<T>(c, V, o.noprec, sc, o.hist_base);
+            if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 3], c->stream));
+        }
+        HIPCHK(hipGetLastError());
+        esd_status st = sync_read(c);
+        if (st != ESD_OK) return st;
+        if (timing) {
+            const int executed = std::min(chunk, std::max(0, c->Sh->iter - launched));
+            for (int j = 0; j < executed; ++j) {
+                float a = 0, b = 0, d = 0;
+                (void)hipEventElapsedTime(&a, c->ev[4 * j + 0], c->ev[4 * j + 1]);
+                (void)hipEventElapsedTime(&b, c->ev[4 * j + 1], c->ev[4 * j + 2]);
+                (void)hipEventElapsedTime(&d, c->ev[4 * j + 2], c->ev[4 * j + 3]);
+                c->t_spmv += a; c->t_upd += b; c->t_sweep += d; c->t_count++;
+            }
+        }
+        launched += chunk;
+        if (c->Sh->done) break;
+        if (!o.sync_every && chunk < 32) chunk *= 2;
+    }
+    *iters = c->Sh->iter;
+    *vbase = (*vbase + c->Sh->iter) & 1;
+    return ESD_OK;
+}
+
+void init_scal(esd_ctx *c, int maxit, double vscale, int stag) {
+    Scal &S = *c->Sh;
+    std::memset(&S, 0, sizeof(Scal));
+    S.maxit = maxit;
+    S.done = (maxit <= 0) ? 2 : 0; // no iteration allowed: stop before the first one
+    S.vscale = vscale;
+    S.stag_window = stag;
+    S.rr_ref = 1e300;
+    S.rho = 1.0;
+}
+
+void fill_lanczos(esd_ctx *c, esd_info *info) {
+    double lo = 0, hi = 0;
+    bool any = false;
+    for (auto &sg : c->segments) {
+        if (sg.second <= 0) continue;
+        double a = 0, b = 0;
+        esd::tridiag_extremes(sg.second, c->ha_h.data() + sg.first, c->hb_h.data() + sg.first, &a, &b);
+        if (!any) { lo = a; hi = b; any = true; }
+        else { lo = std::min(lo, a); hi = std::max(hi, b); }
+    }
+    info->lanczos_min = lo;
+    info->lanczos_max = hi;
+    info->kappa = (any && lo > 0) ? hi / lo : 0.0;
+}
+
+esd_status read_history(esd_ctx *c, int total) {
+    c->ha_h.assign(std::max(total, 1), 0.0);
+    c->hb_h.assign(std::max(total, 1), 0.0);
+    if (total > 0) {
+        HIPCHK(hipMemcpyAsync(c->ha_h.data(), c->ha, sizeof(double) * total, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->hb_h.data(), c->hb, sizeof(double) * total, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return ESD_OK;
+}
+
+esd_status ensure_tables(esd_ctx *c, int maxit) {
+    const int64_t need = (int64_t)maxit + 4;
+    if (c->hcap < need) {
+        hipFree(c->ha); hipFree(c->hb);
+        c->ha = c->hb = nullptr;
+        HIPCHK(dalloc(&c->ha, need));
+        HIPCHK(dalloc(&c->hb, need));
+        c->hcap = need;
+    }
+    if (c->armed) {
+        esd::sampling_table(c->m_req, (int64_t)maxit + 2, c->table_h);
+        if (c->slot_table_cap < (int64_t)c->table_h.size()) {
+            hipFree(c->slot_table);
+            c->slot_table = nullptr;
+            HIPCHK(dalloc(&c->slot_table, (int64_t)c->table_h.size()));
+            c->slot_table_cap = (int64_t)c->table_h.size();
+        }
+        HIPCHK(hipMemcpyAsync(c->slot_table, c->table_h.data(), sizeof(int32_t) * c->table_h.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    }
+    if (!c->ev.empty() && (int)c->ev.size() >= 4 * 32) return ESD_OK;
+    c->ev.resize(4 * 32);
+    for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
+    return ESD_OK;
+}
+
+// iterations kept in every slot for a sampling solve that ran `iters`
+// iterations (`stopped_at_max`: the last iterate is sampled too)
+void record_samples(esd_ctx *c, int iters, bool last_sampled) {
+    c->slot_iter.assign(c->m_req, 0);
+    c->nsamples = 0;
+    const int upto = last_sampled ? iters : iters - 1;
+    for (int i = 1; i <= upto && i < (int)c->table_h.size(); ++i)
+        if (c->table_h[i] >= 0) {
+            c->slot_iter[c->table_h[i]] = i;
+            c->nsamples++;
+        }
+    c->have_samples = c->nsamples > 0;
+}
+
+esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol, int maxit, int kind,
+                      int flags, double *xout, esd_info *info) {
+    const int n = (int)c->n;
+    const int g = grid_n(c);
+    const int m = kind ? c->m_tilde : 0;
+    const bool sampling = c->armed;
+    const bool power = (flags & ESD_FLAG_POWER) != 0;
+    auto V = vecs<double>(c);
+    esd::launch_gather(n, c->p2u, b, c->b, c->stream);
+    if (x0) esd::launch_gather(n, c->p2u, x0, c->x, c->stream);
+    else esd::launch_fill(n, c->x, 0.0, c->stream);
+    init_scal(c, maxit, c->vs64, 0);
+    esd_status st = put_scal(c);
+    if (st) return st;
+    esd::launch_dot(n, c->b, c->b, &c->S->bnorm2, c->S, tol, c->red, g, c->stream);
+    // r_0 = b - A x_0; deflation: r_0 = P^T r_0 = r_0 - AW C^{-1} W^T r_0
+    double *coef = (kind == 1) ? c->S->mu : (kind == 2 ? c->S->u : nullptr);
+    esd::launch_resid(n, c->A.e64(), c->b, c->x, c->r, m ? c->W : nullptr, m, c->Cinv, coef, nullptr, c->S,
+                      kind != 1, c->red, g, c->stream);
+    if (kind == 1)
+        esd::launch_axpy_cols(n, c->r, c->AW, m, c->S->mu, -1.0, nullptr, c->S, 1, c->red, g, c->stream);
+    KrylovOpts o;
+    o.kind = kind;
+    o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
+    o.power = power;
+    o.sampling = sampling;
+    o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
+    o.timing = (flags & kFlagTiming) != 0;
+    int iters = 0;
+    st = krylov<double>(c, V, o, &iters, &c->vb64);
+    if (st) return st;
+    const int done = c->Sh->done;
+    c->segments.assign(1, {0, iters});
+    if (sampling && done == 2 && iters < (int)c->table_h.size() && c->table_h[iters] >= 0)
+        esd::launch_sample_store(n, c->slots + (size_t)c->table_h[iters] * n, c->x, c->stream);
+    if (kind == 1) {
+        // x = P x_i + W C^{-1} W^T b  ==  x_i + W C^{-1} W^T (b - A x_i)
+        esd::launch_resid(n, c->A.e64(), c->b, c->x, c->t, c->W, m, c->Cinv, c->S->mu, nullptr, c->S, 0, c->red,
+                          g, c->stream);
+        esd::launch_axpy_cols(n, c->x, c->W, m, c->S->mu, 1.0, nullptr, c->S, 0, c->red, g, c->stream);
+    }
+    esd::launch_resid(n, c->A.e64(), c->b, c->x, c->t, nullptr, 0, nullptr, nullptr, &c->S->out, c->S, 0, c->red,
+                      g, c->stream);
+    if (power) {
+        c->vs64 = c->Sh->vscale;
+        esd::launch_rayleigh(n, c->A.e64(), c->v[c->vb64], c->vs64 * c->vs64, c->S, c->red, g, c->stream);
+    }
+    esd::launch_scatter(n, c->p2u, c->x, xout, c->stream);
+    if (sampling) {
+        HIPCHK(hipMemcpyAsync(c->xN, c->x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        record_samples(c, iters, done == 2);
+        c->armed = false;
+    }
+    double rr = c->Sh->rr;
+    st = sync_read(c);
+    if (st) return st;
+    st = read_history(c, iters);
+    if (st) return st;
+    const double bn2 = c->Sh->bnorm2;
+    if (info) {
+        info->iters = iters;
+        info->outer_iters = 1;
+        info->converged = (done == 1);
+        info->m_tilde = m;
+        info->nsamples = sampling ? c->nsamples : 0;
+        info->mode_used = kind;
+        info->relres = bn2 > 0 ? std::sqrt(rr / bn2) : std::sqrt(rr);
+        info->true_relres = bn2 > 0 ? std::sqrt(c->Sh->out / bn2) : std::sqrt(c->Sh->out);
+        info->lambda_max = power ? c->Sh->lam : 0.0;
+        fill_lanczos(c, info);
+    }
+    if (done == 3) return fail(c, ESD_ENUMERIC, "non-finite value in the iteration");
+    return done == 1 ? ESD_OK : ESD_NOT_CONVERGED;
+}
+
+esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol, int maxit, int kind,
+                       int flags, double *xout, esd_info *info) {
+    const int n = (int)c->n;
+    const int g = grid_n(c);
+    const int m = kind ? c->m_tilde : 0;
+    const bool sampling = c->armed;
+    const bool power = (flags & ESD_FLAG_POWER) != 0;
+    auto V = vecs<float>(c);
+    esd::launch_gather(n, c->p2u, b, c->b, c->stream);
+    if (x0) esd::launch_gather(n, c->p2u, x0, c->x, c->stream);
+    else esd::launch_fill(n, c->x, 0.0, c->stream);
+    init_scal(c, maxit, c->vs32, 0);
+    esd_status st = put_scal(c);
+    if (st) return st;
+    esd::launch_dot(n, c->b, c->b, &c->S->bnorm2, c->S, tol, c->red, g, c->stream);
+    st = sync_read(c);
+    if (st) return st;
+    const double bn2 = c->Sh->bnorm2, tol2 = c->Sh->tol2;
+    int total = 0, outer = 0, done_in = 0;
+    bool converged = false;
+    double rn2 = 0.0;
+    c->segments.clear();
+    for (outer = 0; outer <= c->max_outer; ++outer) {
+        // FP64 true residual; deflation: coarse correction x += W C^{-1} W^T r
+        esd::launch_resid(n, c->A.e64(), c->b, c->x, c->r, m && kind == 1 ? c->W : nullptr, kind == 1 ? m : 0,
+                          c->Cinv, c->S->mu, &c->S->out, c->S, 0, c->red, g, c->stream);
+        if (kind == 1) {
+            esd::launch_axpy_cols(n, c->x, c->W, m, c->S->mu, 1.0, nullptr, c->S, 0, c->red, g, c->stream);
+            esd::launch_axpy_cols(n, c->r, c->AW, m, c->S->mu, -1.0, &c->S->out, c->S, 0, c->red, g, c->stream);
+        }
+        st = sync_read(c);
+        if (st) return st;
+        rn2 = c->Sh->out;
+        if (!(rn2 <= 1e300)) return fail(c, ESD_ENUMERIC, "non-finite residual");
+        if (rn2 <= tol2) { converged = true; break; }
+        if (total >= maxit || outer == c->max_outer) break;
+        const double rn = std::sqrt(rn2);
+        esd::launch_cast_scale(n, c->r, c->r32, 1.0 / rn, c->stream);
+        esd::launch_fill(n, c->d32, 0.0f, c->stream);
+        // inner relative target: the refinement tolerance, or just what is still missing
+        const double want = std::max(c->inner_tol, 0.3 * std::sqrt(tol2) / rn);
+        init_scal(c, maxit - total, c->vs32, c->stag_window);
+        c->Sh->tol2 = want * want;
+        c->Sh->bnorm2 = bn2;
+        st = put_scal(c);
+        if (st) return st;
+        if (kind == 2) {
+            // u = C^{-1} W^T r / ||r|| for the first preconditioned inner residual
+            esd::launch_tsdot(n, c->W, m, c->r, c->S, c->red, g, c->stream);
+            esd::launch_coarse(m, c->Cinv, c->S->svec, 1.0 / rn, c->S->u, c->stream);
+        }
+        KrylovOpts o;
+        o.kind = kind;
+        o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
+        o.power = power;
+        o.sampling = sampling;
+        o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
+        o.timing = (flags & kFlagTiming) != 0;
+        o.hist_base = total;
+        o.sample_base = total;
+        o.xbase = c->x;
+        o.xscale = rn;
+        int it_in = 0;
+        st = krylov<float>(c, V, o, &it_in, &c->vb32);
+        if (st) return st;
+        done_in = c->Sh->done;
+        c->segments.push_back({total, it_in});
+        total += it_in;
+        if (power) c->vs32 = c->Sh->vscale;
+        esd::launch_add_scaled(n, c->x, c->d32, rn, c->stream);
+        if (done_in == 3) return fail(c, ESD_ENUMERIC, "non-finite value in the inner iteration");
+    }
+    esd::launch_resid(n, c->A.e64(), c->b, c->x, c->t, nullptr, 0, nullptr, nullptr, &c->S->out, c->S, 0, c->red,
+                      g, c->stream);
+    if (power) esd::launch_rayleigh(n, c->A.e32(), c->v32[c->vb32], c->vs32 * c->vs32, c->S, c->red, g, c->stream);
+    esd::launch_scatter(n, c->p2u, c->x, xout, c->stream);
+    if (sampling) {
+        HIPCHK(hipMemcpyAsync(c->xN, c->x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        // inner iterates followed by another inner iteration were sampled
+        c->slot_iter.assign(c->m_req, 0);
+        c->nsamples = 0;
+        for (auto &sg : c->segments)
+            for (int i = 1; i < sg.second; ++i) {
+                const int tot = sg.first + i;
+                if (tot < (int)c->table_h.size() && c->table_h[tot] >= 0) {
+                    c->slot_iter[c->table_h[tot]] = tot;
+                    c->nsamples++;
+                }
+            }
+        c->have_samples = c->nsamples > 0;
+        c->armed = false;
+    }
+    st = sync_read(c);
+    if (st) return st;
+    st = read_history(c, total);
+    if (st) return st;
+    if (info) {
+        info->iters = total;
+        info->outer_iters = outer + 1;
+        info->converged = converged;
+        info->m_tilde = m;
+        info->nsamples = sampling ? c->nsamples : 0;
+        info->mode_used = kind;
+        info->relres = bn2 > 0 ? std::sqrt(rn2 / bn2) : std::sqrt(rn2);
+        info->true_relres = bn2 > 0 ? std::sqrt(c->Sh->out / bn2) : std::sqrt(c->Sh->out);
+        fill_lanczos(c, info);
+    }
+    return converged ? ESD_OK : ESD_NOT_CONVERGED;
+}
+
+
+// C = W^T (A W) on the matrix cores, symmetrised; C^{-1} from its Cholesky
+// factor (host, FP64); FP32 copies of W and AW for the mixed inner loop.
+esd_status finish_aux(esd_ctx *c, int k) {
+    const int n = (int)c->n;
+    esd::launch_gram(n, c->W, k, c->AW, k, c->gram_part, c->G, esd::gram_grid(n), c->stream);
+    std::vector<double> C((size_t)k * k), Cinv;
+    HIPCHK(hipMemcpyAsync(C.data(), c->G, sizeof(double) * k * k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double s = 0.5 * (C[(size_t)i * k + j] + C[(size_t)j * k + i]);
+            C[(size_t)i * k + j] = C[(size_t)j * k + i] = s;
+        }
+    if (!esd::cholesky_inverse(k, C, Cinv)) return fail(c, ESD_ENOTSPD, "W^T A W is not positive definite");
+    c->Ch = C;
+    HIPCHK(hipMemcpyAsync(c->Cinv, Cinv.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, c->stream));
+    esd::launch_cast((int64_t)k * n, c->W, c->W32, c->stream);
+    esd::launch_cast((int64_t)k * n, c->AW, c->AW32, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->m_tilde = k;
+    c->aux_built = true;
+    return ESD_OK;
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *esd_status_string(esd_status s) {
+    switch (s) {
+    case ESD_OK: return "ok";
+    case ESD_NOT_CONVERGED: return "not converged";
+    case ESD_AUX_EMPTY: return "auxiliary space empty; solved as plain ICCG";
+    case ESD_EINVAL: return "invalid argument";
+    case ESD_ENOTSPD: return "IC(0) breakdown (matrix not SPD?)";
+    case ESD_EHIP: return "HIP runtime error";
+    case ESD_ENUMERIC: return "non-finite value";
+    case ESD_ENOAUX: return "no auxiliary space built";
+    case ESD_ENOSAMPLES: return "no samples";
+    }
+    return "unknown status";
+}
+
+const char *esd_last_error(const esd_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void esd_destroy(esd_ctx *c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    free_ell(c->A); free_ell(c->L); free_ell(c->U);
+    void *ptrs[] = {c->u_from_l, c->adiag, c->ldiag, c->dinv, c->dinv32, c->p2u, c->urp, c->ucol, c->bad,
+                    c->b, c->x, c->r, c->z, c->zsc, c->y, c->q, c->p[0], c->p[1], c->t, c->v[0], c->v[1],
+                    c->r32, c->z32, c->zsc32, c->y32, c->q32, c->p32[0], c->p32[1], c->d32, c->v32[0], c->v32[1],
+                    c->red.part, c->red.gpart, c->red.tick, c->S, c->slots, c->slot_table, c->xN,
+                    c->E, c->AE, c->W, c->AW, c->W32, c->AW32, c->Cinv, c->gram_part, c->G, c->Tm, c->ha, c->hb};
+    for (void *p : ptrs) if (p) hipFree(p);
+    if (c->Sh) hipHostFree(c->Sh);
+    for (auto &e : c->ev) hipEventDestroy(e);
+    delete c;
+}
+
+esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr, const int32_t *col,
+                     const double *val, const int32_t *colors, int32_t m_max) {
+    if (!out || !rowptr || !col || !val || n <= 0 || m_max < 0 || m_max > esd::kMaxCols) return ESD_EINVAL;
+    *out = nullptr;
+    esd_ctx *c = new (std::nothrow) esd_ctx();
+    if (!c) return ESD_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    c->m_max = m_max;
+    esd::HostLayout H;
+    std::string why = esd::build_layout(n, rowptr, col, val, colors, H);
+    if (!why.empty()) {
+        fprintf(stderr, "esd_setup: %s\n", why.c_str());
+        delete c;
+        return ESD_EINVAL;
+    }
+    c->n = n;
+    c->nnz = H.nnz;
+    c->ncolors = H.ncolors;
+    c->lvl = H.lvl_ptr;
+    c->p2u_h = H.p2u;
+    c->lperm_h = H.lperm;
+    esd_status st;
+#define SETUP_CHK(x)                                                                               \
+    do {                                                                                           \
+        st = (x);                                                                                  \
+        if (st != ESD_OK) { esd_destroy(c); return st; }                                           \
+    } while (0)
+#define SETUP_HIP(x)                                                                               \
+    do {                                                                                           \
+        if ((x) != hipSuccess) { esd_destroy(c); return ESD_EHIP; }                                \
+    } while (0)
+    SETUP_CHK(upload_ell(c, c->A, H.A));
+    SETUP_CHK(upload_ell(c, c->L, H.L));
+    SETUP_CHK(upload_ell(c, c->U, H.U));
+    SETUP_HIP(dalloc(&c->u_from_l, (int64_t)H.u_from_l.size()));
+    if (!H.u_from_l.empty())
+        SETUP_HIP(hipMemcpyAsync(c->u_from_l, H.u_from_l.data(), sizeof(int64_t) * H.u_from_l.size(),
+                                 hipMemcpyHostToDevice, c->stream));
+    const int64_t nv = n + 64;
+    SETUP_HIP(dalloc(&c->adiag, nv));
+    SETUP_HIP(hipMemcpyAsync(c->adiag, H.adiag.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    SETUP_HIP(dalloc(&c->ldiag, nv));
+    SETUP_HIP(dalloc(&c->dinv, nv));
+    SETUP_HIP(dalloc(&c->dinv32, nv));
+    SETUP_HIP(dalloc(&c->p2u, nv));
+    SETUP_HIP(hipMemcpyAsync(c->p2u, H.p2u.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    SETUP_HIP(dalloc(&c->urp, n + 1));
+    SETUP_HIP(dalloc(&c->ucol, H.nnz));
+    SETUP_HIP(hipMemcpyAsync(c->urp, rowptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, c->stream));
+    SETUP_HIP(hipMemcpyAsync(c->ucol, col, sizeof(int32_t) * H.nnz, hipMemcpyHostToDevice, c->stream));
+    SETUP_HIP(dalloc(&c->bad, 1));
+    double **v64[] = {&c->b, &c->x, &c->r, &c->z, &c->zsc, &c->y, &c->q, &c->p[0], &c->p[1], &c->t, &c->v[0],
+                      &c->v[1]};
+    for (double **p : v64) {
+        SETUP_HIP(dalloc(p, nv));
+        esd::launch_fill((int)nv, *p, 0.0, c->stream);
+    }
+    float **v32[] = {&c->r32, &c->z32, &c->zsc32, &c->y32, &c->q32, &c->p32[0], &c->p32[1], &c->d32, &c->v32[0],
+                     &c->v32[1]};
+    for (float **p : v32) {
+        SETUP_HIP(dalloc(p, nv));
+        esd::launch_fill((int)nv, *p, 0.0f, c->stream);
+    }
+    const int ng = esd::kMaxGrid / esd::kGroup + 1;
+    SETUP_HIP(dalloc(&c->red.part, (int64_t)esd::kMaxGrid * esd::kMaxNV));
+    SETUP_HIP(dalloc(&c->red.gpart, (int64_t)ng * esd::kMaxNV));
+    SETUP_HIP(dalloc(&c->red.tick, ng + 1));
+    SETUP_HIP(hipMemsetAsync(c->red.tick, 0, sizeof(unsigned) * (ng + 1), c->stream));
+    SETUP_HIP(dalloc(&c->S, 1));
+    SETUP_HIP(hipMemsetAsync(c->S, 0, sizeof(Scal), c->stream));
+    SETUP_HIP(hipHostMalloc((void **)&c->Sh, sizeof(Scal), hipHostMallocDefault));
+    std::memset(c->Sh, 0, sizeof(Scal));
+    const int mm = std::max(1, m_max);
+    SETUP_HIP(dalloc(&c->slots, (int64_t)mm * n));
+    SETUP_HIP(dalloc(&c->xN, nv));
+    SETUP_HIP(dalloc(&c->E, (int64_t)mm * n));
+    SETUP_HIP(dalloc(&c->AE, (int64_t)mm * n));
+    SETUP_HIP(dalloc(&c->W, (int64_t)esd::kMaxCols * n));
+    SETUP_HIP(dalloc(&c->AW, (int64_t)esd::kMaxCols * n));
+    SETUP_HIP(dalloc(&c->W32, (int64_t)esd::kMaxCols * n));
+    SETUP_HIP(dalloc(&c->AW32, (int64_t)esd::kMaxCols * n));
+    SETUP_HIP(dalloc(&c->Cinv, 64 * 64));
+    SETUP_HIP(dalloc(&c->gram_part, (int64_t)esd::gram_grid((int)n) * 4096));
+    SETUP_HIP(dalloc(&c->G, 64 * 64));
+    SETUP_HIP(dalloc(&c->Tm, 64 * 64));
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
+        esd_destroy(c);
+        return ESD_EHIP;
+    }
+#undef SETUP_CHK
+#undef SETUP_HIP
+    *out = c;
+    return ESD_OK;
+}
+
+esd_status esd_factor_ic0(esd_ctx *c) {
+    if (!c) return ESD_EINVAL;
+    const int n = (int)c->n;
+    HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
+    // L values start as a_ij (uploaded); factor level by level
+    const int nl = (int)c->lvl.size() - 1;
+    Ell<double> L = c->L.e64();
+    for (int l = 0; l < nl; ++l)
+        esd::launch_factor_level((int)c->lvl[l], (int)c->lvl[l + 1], n, L, c->L.v64, c->adiag, c->ldiag, c->bad,
+                                 c->stream);
+    esd::launch_finish_factor(n, c->ldiag, c->dinv, c->dinv32, c->stream);
+    esd::launch_gather_u(c->U.size, c->u_from_l, c->L.v64, c->U.v64, c->stream);
+    esd::launch_cast(c->L.size, c->L.v64, c->L.v32, c->stream);
+    esd::launch_cast(c->U.size, c->U.v64, c->U.v32, c->stream);
+    HIPCHK(hipGetLastError());
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (bad) {
+        c->factored = false;
+        return fail(c, ESD_ENOTSPD, "IC(0) pivot <= 0");
+    }
+    c->factored = true;
+    return ESD_OK;
+}
+
+esd_status esd_sample_errors(esd_ctx *c, int32_t m) {
+    if (!c) return ESD_EINVAL;
+    if (m < 1 || m > c->m_max) return fail(c, ESD_EINVAL, "m must be in [1, m_max]");
+    c->m_req = m;
+    c->armed = true;
+    return ESD_OK;
+}
+
+esd_status esd_set_mixed_params(esd_ctx *c, double inner_tol, int32_t max_outer) {
+    if (!c || !(inner_tol > 0 && inner_tol < 1) || max_outer < 1) return ESD_EINVAL;
+    c->inner_tol = inner_tol;
+    c->max_outer = max_outer;
+    return ESD_OK;
+}
+
+esd_status esd_set_power_start(esd_ctx *c, const double *v0) {
+    if (!c || !v0) return ESD_EINVAL;
+    const int n = (int)c->n;
+    esd::launch_gather(n, c->p2u, v0, c->v[0], c->stream);
+    esd::launch_cast(n, c->v[0], c->v32[0], c->stream);
+    c->vb64 = c->vb32 = 0;
+    c->vs64 = c->vs32 = 1.0;
+    c->have_v = true;
+    HIPCHK(hipGetLastError());
+    return ESD_OK;
+}
+
+esd_status esd_solve(esd_ctx *c, const double *b, const double *x0, double tol, int32_t maxit, int32_t mode,
+                     int32_t flags, double *x, esd_info *info) {
+    if (!c || !b || !x || maxit < 0 || !(tol >= 0) || mode < 0 || mode > 2) return ESD_EINVAL;
+    if (!c->factored && !(flags & ESD_FLAG_NOPREC)) return fail(c, ESD_EINVAL, "factor_ic0 not called");
+    if ((flags & ESD_FLAG_POWER) && !c->have_v) return fail(c, ESD_EINVAL, "power start vector not set");
+    esd_status warn = ESD_OK;
+    int kind = mode;
+    if (mode != ESD_PLAIN) {
+        if (!c->aux_built) return fail(c, ESD_ENOAUX, "no auxiliary space: call build_aux or set_aux");
+        if (c->m_tilde == 0) { kind = ESD_PLAIN; warn = ESD_AUX_EMPTY; }
+    }
+    esd_status st = ensure_tables(c, maxit);
+    if (st) return st;
+    if (flags & kFlagTiming) { c->t_spmv = c->t_sweep = c->t_upd = 0; c->t_count = 0; }
+    esd_info tmp{};
+    esd_info *inf = info ? info : &tmp;
+    std::memset(inf, 0, sizeof(esd_info));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, c->stream));
+    if (flags & ESD_FLAG_MIXED) st = solve_mixed(c, b, x0, tol, maxit, kind, flags, x, inf);
+    else st = solve_fp64(c, b, x0, tol, maxit, kind, flags, x, inf);
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    inf->seconds = ms * 1e-3;
+    inf->lambda_max = (flags & ESD_FLAG_POWER) ? c->Sh->lam : 0.0;
+    inf->lambda_min_ritz = c->ritz.empty() ? 0.0 : c->ritz[0];
+    inf->kappa_es = (inf->lambda_min_ritz > 0 && inf->lambda_max > 0) ? inf->lambda_max / inf->lambda_min_ritz : 0.0;
+    if (st < 0) return st;
+    if (st == ESD_OK && warn != ESD_OK) return warn;
+    return st;
+}
+
+esd_status esd_grad_values(esd_ctx *c, const double *lam, const double *x, double *gval) {
+    if (!c || !lam || !x || !gval) return ESD_EINVAL;
+    esd::launch_grad((int)c->n, c->urp, c->ucol, lam, x, gval, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ESD_OK;
+}
+
+esd_status esd_spmv(esd_ctx *c, const double *x, double *y) {
+    if (!c || !x || !y) return ESD_EINVAL;
+    const int n = (int)c->n;
+    esd::launch_gather(n, c->p2u, x, c->t, c->stream);
+    esd::launch_spmv(n, c->A.e64(), c->t, c->q, c->stream);
+    esd::launch_scatter(n, c->p2u, c->q, y, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ESD_OK;
+}
+
+esd_status esd_prec_apply(esd_ctx *c, const double *r, double *z) {
+    if (!c || !r || !z) return ESD_EINVAL;
+    if (!c->factored) return fail(c, ESD_EINVAL, "factor_ic0 not called");
+    const int n = (int)c->n;
+    esd::launch_gather(n, c->p2u, r, c->r, c->stream);
+    init_scal(c, 1, 1.0, 0);
+    esd_status st = put_scal(c);
+    if (st) return st;
+    auto V = vecs<double>(c);
+    launch_prec<double>(c, V, false, false, 0);
+    esd::launch_scatter(n, c->p2u, c->z, z, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ESD_OK;
+}
+
+esd_status esd_get_perm(esd_ctx *c, int32_t *perm) {
+    if (!c || !perm) return ESD_EINVAL;
+    std::memcpy(perm, c->lperm_h.data(), sizeof(int32_t) * c->n);
+    return ESD_OK;
+}
+
+esd_status esd_get_factor_diag(esd_ctx *c, double *ldiag) {
+    if (!c || !ldiag) return ESD_EINVAL;
+    if (!c->factored) return fail(c, ESD_EINVAL, "factor_ic0 not called");
+    std::vector<double> tmp(c->n);
+    HIPCHK(hipMemcpy(tmp.data(), c->ldiag, sizeof(double) * c->n, hipMemcpyDeviceToHost));
+    // physical -> user row order
+    for (int64_t p = 0; p < c->n; ++p) ldiag[c->p2u_h[p]] = tmp[p];
+    return ESD_OK;
+}
+
+esd_status esd_get_history(esd_ctx *c, double *alpha, double *beta, int32_t cap, int32_t *count) {
+    if (!c) return ESD_EINVAL;
+    int k = c->segments.empty() ? 0 : c->segments[0].second;
+    if (count) *count = k;
+    const int na = std::min<int>(k, cap), nb = std::min<int>(std::max(k - 1, 0), cap);
+    if (alpha && na > 0) std::memcpy(alpha, c->ha_h.data(), sizeof(double) * na);
+    if (beta && nb > 0) std::memcpy(beta, c->hb_h.data(), sizeof(double) * nb);
+    return ESD_OK;
+}
+
+esd_status esd_get_samples(esd_ctx *c, int32_t *iters_by_slot) {
+    if (!c || !iters_by_slot) return ESD_EINVAL;
+    for (int s = 0; s < c->m_req; ++s) iters_by_slot[s] = s < (int)c->slot_iter.size() ? c->slot_iter[s] : 0;
+    return ESD_OK;
+}
+
+esd_status esd_get_layout(esd_ctx *c, int32_t *out4) {
+    if (!c || !out4) return ESD_EINVAL;
+    out4[0] = (int32_t)c->n;
+    out4[1] = (int32_t)c->nnz;
+    out4[2] = (int32_t)c->lvl.size() - 1;
+    out4[3] = c->ncolors;
+    return ESD_OK;
+}
+
+esd_status esd_get_timing(esd_ctx *c, double *out4) {
+    if (!c || !out4) return ESD_EINVAL;
+    const double k = c->t_count > 0 ? (double)c->t_count : 1.0;
+    out4[0] = c->t_spmv / k;
+    out4[1] = c->t_sweep / k;
+    out4[2] = c->t_upd / k;
+    out4[3] = (double)c->t_count;
+    return ESD_OK;
+}
+
+esd_status esd_build_aux(esd_ctx *c, double theta, double *ritz, int32_t *m_bar, int32_t *m_tilde) {
+    if (!c) return ESD_EINVAL;
+    if (!c->have_samples) return fail(c, ESD_ENOSAMPLES, "no sampling solve before build_aux");
+    const int n = (int)c->n, g = grid_n(c);
+    std::vector<int> order;
+    for (int s = 0; s < (int)c->slot_iter.size(); ++s)
+        if (c->slot_iter[s] > 0) order.push_back(s);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return c->slot_iter[a] < c->slot_iter[b]; });
+    c->aux_built = false;
+    c->m_tilde = 0;
+    int kept = 0;
+    esd_status st;
+    for (int s : order) {
+        double *v = c->E + (size_t)kept * n;
+        // eq. (ek): e = x_1 - x~, normalised, then classical Gram-Schmidt twice
+        esd::launch_sub(n, c->xN, c->slots + (size_t)s * n, v, c->stream);
+        esd::launch_dot(n, v, v, &c->S->out, c->S, -1.0, c->red, g, c->stream);
+        if ((st = sync_read(c))) return st;
+        double nv2 = c->Sh->out;
+        if (!(nv2 > 0.0)) continue;
+        esd::launch_scale_copy(n, v, v, 1.0 / std::sqrt(nv2), c->stream);
+        if (kept > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                esd::launch_tsdot(n, c->E, kept, v, c->S, c->red, g, c->stream);
+                esd::launch_axpy_cols(n, v, c->E, kept, c->S->svec, -1.0, &c->S->out, c->S, 0, c->red, g, c->stream);
+            }
+            if ((st = sync_read(c))) return st;
+            nv2 = c->Sh->out;
+        } else {
+            nv2 = 1.0;
+        }
+        if (!(std::sqrt(nv2) > 1e-10)) continue; // dependent sample: dropped
+        esd::launch_scale_copy(n, v, v, 1.0 / std::sqrt(nv2), c->stream);
+        ++kept;
+    }
+    c->m_bar = kept;
+    if (m_bar) *m_bar = kept;
+    if (m_tilde) *m_tilde = 0;
+    c->ritz.clear();
+    if (kept == 0) {
+        c->aux_built = true;
+        return ESD_AUX_EMPTY;
+    }
+    // Rayleigh-Ritz: G = E^T (A E), eigenpairs on the host
+    esd::launch_spmm(n, c->A.e64(), c->E, kept, c->AE, c->stream);
+    esd::launch_gram(n, c->E, kept, c->AE, kept, c->gram_part, c->G, esd::gram_grid(n), c->stream);
+    std::vector<double> G((size_t)kept * kept), w, V;
+    HIPCHK(hipMemcpyAsync(G.data(), c->G, sizeof(double) * kept * kept, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < kept; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double s = 0.5 * (G[(size_t)i * kept + j] + G[(size_t)j * kept + i]);
+            G[(size_t)i * kept + j] = G[(size_t)j * kept + i] = s;
+        }
+    esd::jacobi_eigh(kept, G, w, V);
+    c->ritz = w;
+    if (ritz) std::memcpy(ritz, w.data(), sizeof(double) * kept);
+    int sel = 0;
+    while (sel < kept && w[sel] < theta) ++sel; // eq. (bk): Ritz values below theta
+    if (m_tilde) *m_tilde = sel;
+    if (sel == 0) {
+        c->aux_built = true;
+        return ESD_AUX_EMPTY;
+    }
+    // W = E T, AW = (A E) T with the selected Ritz vectors T (kept x sel, column-major)
+    HIPCHK(hipMemcpyAsync(c->Tm, V.data(), sizeof(double) * kept * sel, hipMemcpyHostToDevice, c->stream));
+    esd::launch_tsgemm(n, c->E, kept, c->Tm, sel, c->W, c->stream);
+    esd::launch_tsgemm(n, c->AE, kept, c->Tm, sel, c->AW, c->stream);
+    HIPCHK(hipGetLastError());
+    return finish_aux(c, sel);
+}
+
+esd_status esd_set_aux(esd_ctx *c, const double *W, int32_t k) {
+    if (!c || !W || k < 1 || k > esd::kMaxCols) return ESD_EINVAL;
+    const int n = (int)c->n;
+    for (int j = 0; j < k; ++j) esd::launch_gather(n, c->p2u, W + (size_t)j * n, c->W + (size_t)j * n, c->stream);
+    esd::launch_spmm(n, c->A.e64(), c->W, k, c->AW, c->stream);
+    HIPCHK(hipGetLastError());
+    c->ritz.clear();
+    c->m_bar = k;
+    c->aux_built = false;
+    return finish_aux(c, k);
+}
+
+esd_status esd_get_aux(esd_ctx *c, double *W, double *C) {
+    if (!c) return ESD_EINVAL;
+    if (!c->aux_built) return fail(c, ESD_ENOAUX, "no auxiliary space");
+    const int n = (int)c->n, k = c->m_tilde;
+    if (W)
+        for (int j = 0; j < k; ++j) esd::launch_scatter(n, c->p2u, c->W + (size_t)j * n, W + (size_t)j * n, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (C && k > 0) std::memcpy(C, c->Ch.data(), sizeof(double) * k * k);
+    return ESD_OK;
+}
+
+} // extern "C"

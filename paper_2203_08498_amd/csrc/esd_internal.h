@@ -1,0 +1,51 @@
+// Internal structures of the esd library (not part of the public ABI).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace esd {
+
+constexpr int kSlice = 64;   // sliced-ELL slice height = wavefront size
+constexpr int kMaxCols = 64; // largest auxiliary-space dimension
+
+// Sliced-ELL matrix on the host while it is being built: slice s holds rows
+// [64 s, 64 s + 64); entry k of lane t sits at sptr[s] + 64 k + t.  Padding
+// entries carry value 0 and column n.
+struct HostEll {
+    std::vector<int64_t> sptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+};
+
+// Everything the host computes once per matrix (ordering, levels, formats).
+struct HostLayout {
+    int64_t n = 0, nnz = 0;
+    int ncolors = 0;
+    std::vector<int32_t> lperm;    // logical position -> user row
+    std::vector<int32_t> p2u;      // physical row -> user row
+    std::vector<int32_t> u2p;      // user row -> physical row
+    std::vector<int32_t> p2l;      // physical row -> logical position
+    std::vector<int64_t> lvl_ptr;  // physical row range of every level
+    HostEll A;                     // all entries, physical columns sorted
+    HostEll L;                     // strictly lower (logical) entries, sorted by logical column
+    HostEll U;                     // strictly upper (logical) entries
+    std::vector<int64_t> u_from_l; // position in L of the transposed entry of each U slot (-1 pad)
+    std::vector<double> adiag;     // a_ii per physical row
+};
+
+// Builds the layout; returns an empty string on success, else the reason.
+std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                         const int32_t *colors, HostLayout &out);
+
+// Sampling method A: slot of iteration i (>= 1) for m slots, and the table of
+// slots (or -1) for iterations 0..maxit.
+int sampling_slot(int64_t i, int m);
+void sampling_table(int m, int64_t maxit, std::vector<int32_t> &slot_of_iter);
+
+// Small dense kernels of the host side (own implementations).
+void jacobi_eigh(int k, std::vector<double> &a, std::vector<double> &w, std::vector<double> &V);
+bool cholesky_inverse(int k, const std::vector<double> &C, std::vector<double> &Cinv);
+void tridiag_extremes(int k, const double *alpha, const double *beta, double *tmin, double *tmax);
+
+} // namespace esd

@@ -1,0 +1,184 @@
+// Device-side data structures and kernel launchers of the esd library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace esd {
+
+constexpr int kBlock = 256;     // threads per block of every row kernel
+constexpr int kGroup = 32;      // blocks per first-level reduction group
+constexpr int kMaxGrid = 2048;  // largest grid of a reducing kernel
+constexpr int kMaxNV = 72;      // largest number of values reduced together
+
+// Solver scalars kept in device memory; every per-iteration quantity (rho,
+// alpha, beta, the coarse vectors) is produced and consumed on the device.
+struct Scal {
+    double rho;      // (r, z) of the current preconditioned residual
+    double rho_acc;  // partial (r, z) summed over the sweep launches of one application
+    double alpha, beta;
+    double rr;       // ||r||^2 of the recurrence residual
+    double tol2;     // tol^2 ||b||^2
+    double bnorm2;   // ||b||^2
+    double vscale;   // 1 / ||v|| of the power iterate
+    double out;      // generic reduction output (norms)
+    double lam;      // Rayleigh quotient of the power iterate
+    double rr_ref;   // stagnation reference
+    int32_t it_ref;
+    int32_t iter;    // completed iterations of the current solve
+    int32_t done;    // 0 running, 1 converged, 2 maxit, 3 non-finite, 4 stagnated
+    int32_t maxit;
+    int32_t stag_window; // 0 = off
+    int32_t pad;
+    double mu[64];   // C^{-1} W^T q (deflation) or generic coarse coefficients
+    double u[64];    // C^{-1} W^T r (subspace correction)
+    double svec[64]; // last tall-skinny product W^T v
+};
+
+struct Red {
+    double *part;   // [grid][kMaxNV]
+    double *gpart;  // [grid / kGroup][kMaxNV]
+    unsigned *tick; // [1 + grid / kGroup]
+};
+
+template <typename T> struct Ell {
+    const int64_t *sptr;
+    const int32_t *col;
+    const T *val;
+};
+
+// one iteration's SpMV: p_new = z + beta p_old (p_new = z on the first
+// iteration), q = A p_new, (p_new, q), W^T q -> mu -> alpha; optional power
+// iterate v_new = A v_old / ||v_old||; optional sampling store of the iterate.
+template <typename T> struct SpmvIt {
+    int n;
+    Scal *S;
+    Red red;
+    Ell<T> A;
+    const T *z, *pold;
+    T *pnew, *q;
+    const T *vold;
+    T *vnew;
+    const T *W;
+    int m;
+    const double *Cinv;
+    double *hist_alpha;
+    int hist_base;
+    const int32_t *slot_table;
+    int sample_base;
+    double *slots;
+    const T *xit;
+    const double *xbase;
+    double xscale;
+};
+
+// x += alpha p; r -= alpha w with w = q (plain, SC) or q - AW mu (deflated);
+// ||r||^2; W^T r -> u for subspace correction; stop test.
+template <typename T> struct UpdIt {
+    int n;
+    Scal *S;
+    Red red;
+    const T *p, *q;
+    T *x, *r;
+    const T *AW; // deflated
+    const T *W;  // subspace correction
+    int m;
+    const double *Cinv;
+};
+
+// one level of the forward (L y = r) or backward (L^T z = y) IC(0) sweep
+template <typename T> struct Sweep {
+    int r0, r1; // physical row range of the level
+    int n;
+    Scal *S;
+    Red red;
+    Ell<T> M;   // L (forward) or U = L^T (backward)
+    const T *dinv;
+    const T *r;
+    T *y, *z, *zsc;
+    const T *W;
+    int m;      // > 0: subspace correction adds W u to zsc
+    double *hist_beta;
+    int hist_base;
+    int final_;   // last launch of this preconditioner application
+};
+
+void launch_spmv_it(const SpmvIt<double> &a, int mt, bool power, int grid, hipStream_t s);
+void launch_spmv_it(const SpmvIt<float> &a, int mt, bool power, int grid, hipStream_t s);
+void launch_update_it(const UpdIt<double> &a, int mt, int kind, int grid, hipStream_t s);
+void launch_update_it(const UpdIt<float> &a, int mt, int kind, int grid, hipStream_t s);
+void launch_fwd(const Sweep<double> &a, bool last, bool sc, int grid, hipStream_t s);
+void launch_fwd(const Sweep<float> &a, bool last, bool sc, int grid, hipStream_t s);
+void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
+void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
+void launch_copyz(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
+void launch_copyz(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
+
+// ---- per-solve and setup kernels (FP64 unless stated) ----
+void launch_gather(int n, const int32_t *idx, const double *src, double *dst, hipStream_t s);
+void launch_scatter(int n, const int32_t *idx, const double *src, double *dst, hipStream_t s);
+void launch_fill(int n, double *dst, double v, hipStream_t s);
+void launch_fill(int n, float *dst, float v, hipStream_t s);
+// out = a.b; if tol >= 0 also S->bnorm2 = out, S->tol2 = tol^2 out
+void launch_dot(int n, const double *a, const double *b, double *out, Scal *S, double tol, Red red,
+                int grid, hipStream_t s);
+// t = b - A x (A in FP64); *out = ||t||^2; W^T t -> coef = C^{-1} W^T t when W;
+// check: S->rr = ||t||^2 and S->done = (||t||^2 <= S->tol2)
+void launch_resid(int n, Ell<double> A, const double *b, const double *x, double *t, const double *W,
+                  int m, const double *Cinv, double *coef, double *out, Scal *S, int check, Red red,
+                  int grid, hipStream_t s);
+// y += sign * M coef (M: n x m column-major); *out = ||y||^2 when out;
+// check as in launch_resid
+void launch_axpy_cols(int n, double *y, const double *M, int m, const double *coef, double sign,
+                      double *out, Scal *S, int check, Red red, int grid, hipStream_t s);
+// tall-skinny W^T v -> S->svec (and nothing else)
+void launch_tsdot(int n, const double *W, int m, const double *v, Scal *S, Red red, int grid,
+                  hipStream_t s);
+// y = A x (FP64 or FP32 values; FP64 vectors)
+void launch_spmv(int n, Ell<double> A, const double *x, double *y, hipStream_t s);
+// S->lam = (v, A v) * scale^2 with v of type T
+void launch_rayleigh(int n, Ell<double> A, const double *v, double scale2, Scal *S, Red red, int grid,
+                     hipStream_t s);
+void launch_rayleigh(int n, Ell<float> A, const float *v, double scale2, Scal *S, Red red, int grid,
+                     hipStream_t s);
+// out[k] = scale * sum_j Cinv[k m + j] s[j] (one block)
+void launch_coarse(int m, const double *Cinv, const double *s, double scale, double *out, hipStream_t st);
+// sample store of the iterate (used when a solve stops at maxit)
+void launch_sample_store(int n, double *slot, const double *x, hipStream_t s);
+// casts
+void launch_cast_scale(int n, const double *src, float *dst, double scale, hipStream_t s);
+void launch_cast(int64_t n, const double *src, float *dst, hipStream_t s);
+void launch_add_scaled(int n, double *x, const float *d, double scale, hipStream_t s);
+void launch_sub(int n, const double *a, const double *b, double *dst, hipStream_t s);
+void launch_scale_copy(int n, const double *src, double *dst, double scale, hipStream_t s);
+
+// IC(0) factor of one level (FP64, in place on the L values; writes ldiag)
+void launch_factor_level(int r0, int r1, int n, Ell<double> L, double *lval, const double *adiag,
+                         double *ldiag, int *bad, hipStream_t s);
+void launch_finish_factor(int n, const double *ldiag, double *dinv, float *dinv32, hipStream_t s);
+void launch_gather_u(int64_t cnt, const int64_t *map, const double *lval, double *uval,
+                     hipStream_t s);
+
+// A E for m columns (column-major, FP64)
+void launch_spmm(int n, Ell<double> A, const double *E, int m, double *AE, hipStream_t s);
+// block partials of E^T F (E: n x ma, F: n x mb, column-major) with FP64 MFMA;
+// then the deterministic sum over blocks into G (ma x mb, row-major)
+int gram_grid(int n);
+void launch_gram(int n, const double *E, int ma, const double *F, int mb, double *part, double *G,
+                 int grid, hipStream_t s);
+// Y = X T (X: n x ma col-major, T: ma x mb col-major on device)
+void launch_tsgemm(int n, const double *X, int ma, const double *T, int mb, double *Y, hipStream_t s);
+
+// gradient with respect to stored values: g[k] = -lam[row k] x[col k] (user CSR)
+void launch_grad(int n, const int64_t *rowptr, const int32_t *col, const double *lam,
+                 const double *x, double *g, hipStream_t s);
+
+inline int grid_for(int64_t rows) {
+    int64_t g = (rows + kBlock - 1) / kBlock;
+    if (g > kMaxGrid) g = kMaxGrid;
+    if (g > 8) g = (g + 7) / 8 * 8; // whole XCD rounds
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+} // namespace esd

@@ -1,0 +1,887 @@
+// gfx950 kernels of the esd library.
+//
+// Row kernels use 256-thread blocks; a block walks a contiguous run of
+// 256-row tiles, and block ids are remapped so that each of the eight XCDs
+// (which receive hardware blocks round-robin) owns one contiguous eighth of
+// the rows.  Matrices are sliced-ELL with slice height 64, so the 64 lanes of
+// a wavefront read 64 consecutive values / column indices per entry slot.
+// Padding slots point at column n, and every vector that is gathered has a
+// zero at index n.
+//
+// Reductions are deterministic: each block reduces its values with wavefront
+// butterflies and LDS, writes them to a fixed slot, and the last block of
+// each group of 32 (ticket counter) sums its group in slot order; the last
+// group reducer sums the groups in order and runs the kernel's scalar epilogue
+// (alpha, beta, the coarse solve, the stop test) on the device.
+#include <cfloat>
+
+#include "kernels.h"
+
+namespace esd {
+namespace {
+
+__device__ __forceinline__ int xcd_block() {
+    const int b = blockIdx.x, G = gridDim.x;
+    if (G >= 16 && (G & 7) == 0) return (b & 7) * (G >> 3) + (b >> 3);
+    return b;
+}
+
+struct Tiles {
+    int t0, t1;
+};
+
+__device__ __forceinline__ Tiles my_tiles(int rows) {
+    const int nt = (rows + kBlock - 1) / kBlock;
+    const int G = gridDim.x;
+    const int per = (nt + G - 1) / G;
+    const int t0 = xcd_block() * per;
+    return {t0, min(nt, t0 + per)};
+}
+
+__device__ __forceinline__ double ld_agent(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Deterministic grid reduction of NV doubles.  Returns true in the one block
+// that holds the totals (in tot[], shared), after a __syncthreads.
+template <int NV>
+__device__ bool reduce_last(double (&v)[NV], const Red &red, double *tot) {
+    __shared__ double lds[kBlock / 64][NV];
+    __shared__ int flag;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) lds[wid][k] = x;
+    }
+    __syncthreads();
+    const int G = gridDim.x, b = blockIdx.x;
+    const int g = b / kGroup, ng = (G + kGroup - 1) / kGroup;
+    const int gs = min(kGroup, G - g * kGroup);
+    for (int k = threadIdx.x; k < NV; k += kBlock) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += lds[w][k];
+        red.part[(size_t)b * kMaxNV + k] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) flag = (atomicAdd(&red.tick[1 + g], 1u) == (unsigned)(gs - 1));
+    __syncthreads();
+    if (!flag) return false;
+    __threadfence();
+    for (int k = threadIdx.x; k < NV; k += kBlock) {
+        double s = 0.0;
+        for (int j = 0; j < gs; ++j) s += ld_agent(&red.part[(size_t)(g * kGroup + j) * kMaxNV + k]);
+        red.gpart[(size_t)g * kMaxNV + k] = s;
+    }
+    if (threadIdx.x == 0) red.tick[1 + g] = 0;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) flag = (atomicAdd(&red.tick[0], 1u) == (unsigned)(ng - 1));
+    __syncthreads();
+    if (!flag) return false;
+    __threadfence();
+    for (int k = threadIdx.x; k < NV; k += kBlock) {
+        double s = 0.0;
+        for (int j = 0; j < ng; ++j) s += ld_agent(&red.gpart[(size_t)j * kMaxNV + k]);
+        tot[k] = s;
+    }
+    if (threadIdx.x == 0) red.tick[0] = 0;
+    __syncthreads();
+    return true;
+}
+
+// coef[k] = sum_j Cinv[k m + j] s[j] for k < m (threads k), into dst and sh
+__device__ __forceinline__ void coarse_apply(const double *Cinv, int m, const double *s, double *dst,
+                                             double *sh) {
+    if ((int)threadIdx.x < m) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += Cinv[threadIdx.x * m + j] * s[j];
+        dst[threadIdx.x] = acc;
+        if (sh) sh[threadIdx.x] = acc;
+    }
+}
+
+// ------------------------------------------------------------------------
+// per-iteration kernels
+// ------------------------------------------------------------------------
+
+template <typename T, int MT, bool POW>
+__global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
+    Scal *S = a.S;
+    if (S->done) return;
+    const int iter = S->iter;
+    const bool first = (iter == 0);
+    const T beta = first ? T(0) : (T)S->beta;
+    const T vs = POW ? (T)S->vscale : T(0);
+    int slot = -1;
+    if (a.slot_table && iter >= 1) slot = a.slot_table[a.sample_base + iter];
+    constexpr int NV = 1 + MT + (POW ? 1 : 0);
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    const int n = a.n, m = a.m;
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        const int lane = i & 63;
+        const int64_t base = a.A.sptr[i >> 6];
+        const int w = (int)((a.A.sptr[(i >> 6) + 1] - base) >> 6);
+        T sum = T(0), vsum = T(0);
+        for (int k = 0; k < w; ++k) {
+            const int64_t pos = base + (int64_t)k * 64 + lane;
+            const int c = a.A.col[pos];
+            const T av = a.A.val[pos];
+            const T pj = first ? a.z[c] : a.z[c] + beta * a.pold[c];
+            sum += av * pj;
+            if constexpr (POW) vsum += av * a.vold[c];
+        }
+        const T pi = first ? a.z[i] : a.z[i] + beta * a.pold[i];
+        a.pnew[i] = pi;
+        a.q[i] = sum;
+        acc[0] += (double)pi * (double)sum;
+        if constexpr (MT > 0) {
+#pragma unroll
+            for (int k = 0; k < MT; ++k)
+                if (k < m) acc[1 + k] += (double)a.W[(size_t)k * n + i] * (double)sum;
+        }
+        if constexpr (POW) {
+            const T vn = vsum * vs;
+            a.vnew[i] = vn;
+            acc[NV - 1] += (double)vn * (double)vn;
+        }
+        if (slot >= 0)
+            a.slots[(size_t)slot * n + i] =
+                a.xbase ? a.xbase[i] + a.xscale * (double)a.xit[i] : (double)a.xit[i];
+    }
+    __shared__ double tot[NV];
+    if (!reduce_last<NV>(acc, a.red, tot)) return;
+    __shared__ double mus[MT > 0 ? MT : 1];
+    if constexpr (MT > 0) {
+        coarse_apply(a.Cinv, m, tot + 1, S->mu, mus);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double denom = tot[0];
+        if constexpr (MT > 0)
+            for (int k = 0; k < m; ++k) denom -= tot[1 + k] * mus[k];
+        const double alpha = S->rho / denom;
+        S->alpha = alpha;
+        if (a.hist_alpha) a.hist_alpha[a.hist_base + iter] = alpha;
+        if (!isfinite(alpha)) S->done = 3;
+        if constexpr (POW) S->vscale = 1.0 / sqrt(tot[NV - 1]);
+    }
+}
+
+// KIND: 0 plain, 1 deflated (w = q - AW mu), 2 subspace correction (W^T r)
+template <typename T, int MT, int KIND>
+__global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
+    Scal *S = a.S;
+    if (S->done) return;
+    const T ta = (T)S->alpha;
+    constexpr int NV = 1 + (KIND == 2 ? MT : 0);
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    const int n = a.n, m = a.m;
+    double mu[KIND == 1 ? MT : 1];
+    if constexpr (KIND == 1) {
+#pragma unroll
+        for (int k = 0; k < MT; ++k) mu[k] = (k < m) ? S->mu[k] : 0.0;
+    }
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        T wi = a.q[i];
+        if constexpr (KIND == 1) {
+            double s = (double)wi;
+#pragma unroll
+            for (int k = 0; k < MT; ++k)
+                if (k < m) s -= (double)a.AW[(size_t)k * n + i] * mu[k];
+            wi = (T)s;
+        }
+        a.x[i] += ta * a.p[i];
+        const T ri = a.r[i] - ta * wi;
+        a.r[i] = ri;
+        acc[0] += (double)ri * (double)ri;
+        if constexpr (KIND == 2) {
+#pragma unroll
+            for (int k = 0; k < MT; ++k)
+                if (k < m) acc[1 + k] += (double)a.W[(size_t)k * n + i] * (double)ri;
+        }
+    }
+    __shared__ double tot[NV];
+    if (!reduce_last<NV>(acc, a.red, tot)) return;
+    if constexpr (KIND == 2) coarse_apply(a.Cinv, m, tot + 1, S->u, nullptr);
+    if (threadIdx.x == 0) {
+        const double rr = tot[0];
+        const int it = S->iter + 1;
+        S->iter = it;
+        S->rr = rr;
+        int d = 0;
+        if (!(rr <= DBL_MAX)) d = 3;
+        else if (rr <= S->tol2) d = 1;
+        else if (it >= S->maxit) d = 2;
+        else if (S->stag_window > 0) {
+            if (rr < 0.81 * S->rr_ref) {
+                S->rr_ref = rr;
+                S->it_ref = it;
+            } else if (it - S->it_ref >= S->stag_window) {
+                d = 4;
+            }
+        }
+        S->done = d;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void finish_rho(const Sweep<T> &a, double (&acc)[1]) {
+    __shared__ double tot[1];
+    if (!reduce_last<1>(acc, a.red, tot)) return;
+    if (threadIdx.x == 0) {
+        Scal *S = a.S;
+        if (!a.final_) {
+            S->rho_acc += tot[0];
+        } else {
+            const double rn = S->rho_acc + tot[0];
+            S->rho_acc = 0.0;
+            if (S->iter > 0) {
+                const double b = rn / S->rho;
+                S->beta = b;
+                if (a.hist_beta) a.hist_beta[a.hist_base + S->iter - 1] = b;
+            }
+            S->rho = rn;
+            if (!isfinite(rn)) S->done = 3;
+        }
+    }
+}
+
+template <typename T, bool SC>
+__device__ __forceinline__ T add_coarse(const Sweep<T> &a, int i, T zi) {
+    if constexpr (!SC) {
+        return zi;
+    } else {
+        double s = (double)zi;
+        for (int k = 0; k < a.m; ++k) s += (double)a.W[(size_t)k * a.n + i] * a.S->u[k];
+        return (T)s;
+    }
+}
+
+template <typename T, bool LAST, bool SC>
+__global__ __launch_bounds__(kBlock) void k_fwd(Sweep<T> a) {
+    if (a.S->done) return;
+    double acc[1] = {0.0};
+    const Tiles tl = my_tiles(a.r1 - a.r0);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = a.r0 + t * kBlock + threadIdx.x;
+        if (i >= a.r1) continue;
+        const int lane = i & 63;
+        const int64_t base = a.M.sptr[i >> 6];
+        const int w = (int)((a.M.sptr[(i >> 6) + 1] - base) >> 6);
+        const T ri = a.r[i];
+        T s = ri;
+        for (int k = 0; k < w; ++k) {
+            const int64_t pos = base + (int64_t)k * 64 + lane;
+            s -= a.M.val[pos] * a.y[a.M.col[pos]];
+        }
+        const T yi = s * a.dinv[i];
+        if constexpr (!LAST) {
+            a.y[i] = yi;
+        } else {
+            // no logically-later neighbour: the backward solve of this row is immediate
+            const T zi = yi * a.dinv[i];
+            a.z[i] = zi;
+            const T zs = add_coarse<T, SC>(a, i, zi);
+            if constexpr (SC) a.zsc[i] = zs;
+            acc[0] += (double)ri * (double)zs;
+        }
+    }
+    if constexpr (LAST) finish_rho(a, acc);
+}
+
+template <typename T, bool SC>
+__global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
+    if (a.S->done) return;
+    double acc[1] = {0.0};
+    const Tiles tl = my_tiles(a.r1 - a.r0);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = a.r0 + t * kBlock + threadIdx.x;
+        if (i >= a.r1) continue;
+        const int lane = i & 63;
+        const int64_t base = a.M.sptr[i >> 6];
+        const int w = (int)((a.M.sptr[(i >> 6) + 1] - base) >> 6);
+        T s = a.y[i];
+        for (int k = 0; k < w; ++k) {
+            const int64_t pos = base + (int64_t)k * 64 + lane;
+            s -= a.M.val[pos] * a.z[a.M.col[pos]];
+        }
+        const T zi = s * a.dinv[i];
+        a.z[i] = zi;
+        const T zs = add_coarse<T, SC>(a, i, zi);
+        if constexpr (SC) a.zsc[i] = zs;
+        acc[0] += (double)a.r[i] * (double)zs;
+    }
+    finish_rho(a, acc);
+}
+
+// M = I: z = r (+ W u for subspace correction)
+template <typename T, bool SC>
+__global__ __launch_bounds__(kBlock) void k_copyz(Sweep<T> a) {
+    if (a.S->done) return;
+    double acc[1] = {0.0};
+    const Tiles tl = my_tiles(a.r1 - a.r0);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = a.r0 + t * kBlock + threadIdx.x;
+        if (i >= a.r1) continue;
+        const T ri = a.r[i];
+        a.z[i] = ri;
+        const T zs = add_coarse<T, SC>(a, i, ri);
+        if constexpr (SC) a.zsc[i] = zs;
+        acc[0] += (double)ri * (double)zs;
+    }
+    finish_rho(a, acc);
+}
+
+// ------------------------------------------------------------------------
+// per-solve kernels
+// ------------------------------------------------------------------------
+
+__global__ void k_gather(int n, const int32_t *idx, const double *src, double *dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+__global__ void k_scatter(int n, const int32_t *idx, const double *src, double *dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[idx[i]] = src[i];
+}
+template <typename T> __global__ void k_fill(int n, T *dst, T v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+__global__ void k_cast_scale(int n, const double *src, float *dst, double scale) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)(src[i] * scale);
+}
+__global__ void k_cast(int64_t n, const double *src, float *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+__global__ void k_add_scaled(int n, double *x, const float *d, double scale) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += scale * (double)d[i];
+}
+__global__ void k_sub(int n, const double *a, const double *b, double *dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = a[i] - b[i];
+}
+__global__ void k_scale_copy(int n, const double *src, double *dst, double scale) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i] * scale;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(int n, const double *x, const double *y, double *out,
+                                                Scal *S, double tol, Red red) {
+    double acc[1] = {0.0};
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i < n) acc[0] += x[i] * y[i];
+    }
+    __shared__ double tot[1];
+    if (!reduce_last<1>(acc, red, tot)) return;
+    if (threadIdx.x == 0) {
+        *out = tot[0];
+        if (tol >= 0.0) {
+            S->bnorm2 = tot[0];
+            S->tol2 = tol * tol * tot[0];
+        }
+    }
+}
+
+template <int MT>
+__global__ __launch_bounds__(kBlock) void k_resid(int n, Ell<double> A, const double *b,
+                                                  const double *x, double *t, const double *W, int m,
+                                                  const double *Cinv, double *coef, double *out,
+                                                  Scal *S, int check, Red red) {
+    constexpr int NV = 1 + MT;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    const Tiles tl = my_tiles(n);
+    for (int tt = tl.t0; tt < tl.t1; ++tt) {
+        const int i = tt * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        const int lane = i & 63;
+        const int64_t base = A.sptr[i >> 6];
+        const int w = (int)((A.sptr[(i >> 6) + 1] - base) >> 6);
+        double s = 0.0;
+        for (int k = 0; k < w; ++k) {
+            const int64_t pos = base + (int64_t)k * 64 + lane;
+            s += A.val[pos] * x[A.col[pos]];
+        }
+        const double ri = b[i] - s;
+        t[i] = ri;
+        acc[0] += ri * ri;
+        if constexpr (MT > 0) {
+#pragma unroll
+            for (int k = 0; k < MT; ++k)
+                if (k < m) acc[1 + k] += W[(size_t)k * n + i] * ri;
+        }
+    }
+    __shared__ double tot[NV];
+    if (!reduce_last<NV>(acc, red, tot)) return;
+    if constexpr (MT > 0) {
+        if ((int)threadIdx.x < m) S->svec[threadIdx.x] = tot[1 + threadIdx.x];
+        if (coef) coarse_apply(Cinv, m, tot + 1, coef, nullptr);
+    }
+    if (threadIdx.x == 0) {
+        if (out) *out = tot[0];
+        if (check) {
+            S->rr = tot[0];
+            if (tot[0] <= S->tol2) S->done = 1;
+        }
+    }
+}
+
+template <int MT>
+__global__ __launch_bounds__(kBlock) void k_axpy_cols(int n, double *y, const double *M, int m,
+                                                      const double *coef, double sign, double *out,
+                                                      Scal *S, int check, Red red) {
+    double acc[1] = {0.0};
+    double c[MT];
+#pragma unroll
+    for (int k = 0; k < MT; ++k) c[k] = (k < m) ? sign * coef[k] : 0.0;
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        double s = y[i];
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < m) s += M[(size_t)k * n + i] * c[k];
+        y[i] = s;
+        acc[0] += s * s;
+    }
+    if (!out && !check) return;
+    __shared__ double tot[1];
+    if (!reduce_last<1>(acc, red, tot)) return;
+    if (threadIdx.x == 0) {
+        if (out) *out = tot[0];
+        if (check) {
+            S->rr = tot[0];
+            if (tot[0] <= S->tol2) S->done = 1;
+        }
+    }
+}
+
+template <int MT>
+__global__ __launch_bounds__(kBlock) void k_tsdot(int n, const double *W, int m, const double *v,
+                                                  Scal *S, Red red) {
+    double acc[MT];
+#pragma unroll
+    for (int k = 0; k < MT; ++k) acc[k] = 0.0;
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        const double vi = v[i];
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < m) acc[k] += W[(size_t)k * n + i] * vi;
+    }
+    __shared__ double tot[MT];
+    if (!reduce_last<MT>(acc, red, tot)) return;
+    if ((int)threadIdx.x < m) S->svec[threadIdx.x] = tot[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_spmv(int n, Ell<double> A, const double *x, double *y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int lane = i & 63;
+    const int64_t base = A.sptr[i >> 6];
+    const int w = (int)((A.sptr[(i >> 6) + 1] - base) >> 6);
+    double s = 0.0;
+    for (int k = 0; k < w; ++k) {
+        const int64_t pos = base + (int64_t)k * 64 + lane;
+        s += A.val[pos] * x[A.col[pos]];
+    }
+    y[i] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rayleigh(int n, Ell<T> A, const T *v, double scale2, Scal *S,
+                                                     Red red) {
+    double acc[1] = {0.0};
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        const int lane = i & 63;
+        const int64_t base = A.sptr[i >> 6];
+        const int w = (int)((A.sptr[(i >> 6) + 1] - base) >> 6);
+        double s = 0.0;
+        for (int k = 0; k < w; ++k) {
+            const int64_t pos = base + (int64_t)k * 64 + lane;
+            s += (double)A.val[pos] * (double)v[A.col[pos]];
+        }
+        acc[0] += (double)v[i] * s;
+    }
+    __shared__ double tot[1];
+    if (!reduce_last<1>(acc, red, tot)) return;
+    if (threadIdx.x == 0) S->lam = tot[0] * scale2;
+}
+
+__global__ void k_coarse(int m, const double *Cinv, const double *s, double scale, double *out) {
+    const int k = threadIdx.x;
+    if (k < m) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += Cinv[k * m + j] * s[j];
+        out[k] = scale * acc;
+    }
+}
+
+// ------------------------------------------------------------------------
+// IC(0) factor, one level of rows at a time
+// ------------------------------------------------------------------------
+
+__global__ void k_factor_level(int r0, int r1, int n, Ell<double> L, double *lval, const double *adiag,
+                               double *ldiag, int *bad) {
+    const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= r1) return;
+    const int lane = i & 63;
+    const int64_t base = L.sptr[i >> 6];
+    const int w = (int)((L.sptr[(i >> 6) + 1] - base) >> 6);
+    double dsum = 0.0;
+    for (int e = 0; e < w; ++e) {
+        const int64_t pe = base + (int64_t)e * 64 + lane;
+        const int j = L.col[pe];
+        if (j >= n) break; // padding sits after the row's entries
+        double s = lval[pe];
+        const int64_t bj = L.sptr[j >> 6];
+        const int wj = (int)((L.sptr[(j >> 6) + 1] - bj) >> 6);
+        const int lj = j & 63;
+        // entries k of row i that precede j (logically) and also appear in row j
+        for (int t = 0; t < e; ++t) {
+            const int64_t pt = base + (int64_t)t * 64 + lane;
+            const int k = L.col[pt];
+            for (int b = 0; b < wj; ++b) {
+                const int64_t pb = bj + (int64_t)b * 64 + lj;
+                if (L.col[pb] == k) {
+                    s -= lval[pt] * lval[pb];
+                    break;
+                }
+            }
+        }
+        s /= ldiag[j];
+        lval[pe] = s;
+        dsum += s * s;
+    }
+    double d = adiag[i] - dsum;
+    if (!(d > 0.0)) {
+        *bad = 1;
+        d = 1.0;
+    }
+    ldiag[i] = sqrt(d);
+}
+
+__global__ void k_finish_factor(int n, const double *ldiag, double *dinv, float *dinv32) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double d = 1.0 / ldiag[i];
+        dinv[i] = d;
+        dinv32[i] = (float)d;
+    }
+}
+
+__global__ void k_gather_u(int64_t cnt, const int64_t *map, const double *lval, double *uval) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) {
+        const int64_t s = map[i];
+        uval[i] = s >= 0 ? lval[s] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------
+// auxiliary-space construction
+// ------------------------------------------------------------------------
+
+// AE = A E for m columns (column-major), 16 columns per pass over the row
+__global__ __launch_bounds__(kBlock) void k_spmm(int n, Ell<double> A, const double *E, int m, double *AE) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int lane = i & 63;
+    const int64_t base = A.sptr[i >> 6];
+    const int w = (int)((A.sptr[(i >> 6) + 1] - base) >> 6);
+    for (int k0 = 0; k0 < m; k0 += 16) {
+        double acc[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+        for (int e = 0; e < w; ++e) {
+            const int64_t pos = base + (int64_t)e * 64 + lane;
+            const int c = A.col[pos];
+            if (c >= n) continue;
+            const double av = A.val[pos];
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k0 + k < m) acc[k] += av * E[(size_t)(k0 + k) * n + c];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k0 + k < m) AE[(size_t)(k0 + k) * n + i] = acc[k];
+    }
+}
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// Block partial of G = E^T F (E: n x ma, F: n x mb, column-major, ma, mb <= 64)
+// with the FP64 matrix cores.  v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; the 4 accumulator values of lane l are D[4(l/16)+r][l%16].
+// Each of the 4 wavefronts owns up to 4 of the 16 output tiles.
+__global__ __launch_bounds__(256) void k_gram_part(int n, const double *E, int ma, const double *F, int mb,
+                                                   double *part) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int ta = (ma + 15) / 16, tb = (mb + 15) / 16, ntile = ta * tb;
+    const int G = gridDim.x;
+    const int chunk = ((n + G - 1) / G + 3) / 4 * 4;
+    const int row0 = blockIdx.x * chunk, row1 = min(n, row0 + chunk);
+    double4_t acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+    const int li = lane & 15, lk = lane >> 4;
+    for (int r = row0; r < row1; r += 4) {
+        const int row = r + lk;
+        const bool ok = row < row1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int tile = wid + 4 * q;
+            if (tile >= ntile) break;
+            const int a0 = (tile / tb) * 16, b0 = (tile % tb) * 16;
+            const int ca = a0 + li, cb = b0 + li;
+            const double av = (ok && ca < ma) ? E[(size_t)ca * n + row] : 0.0;
+            const double bv = (ok && cb < mb) ? F[(size_t)cb * n + row] : 0.0;
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+        }
+    }
+    double *out = part + (size_t)blockIdx.x * 64 * 64;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int tile = wid + 4 * q;
+        if (tile >= ntile) break;
+        const int a0 = (tile / tb) * 16, b0 = (tile % tb) * 16;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int ii = a0 + 4 * lk + rr, jj = b0 + li;
+            out[ii * 64 + jj] = acc[q][rr];
+        }
+    }
+}
+
+__global__ void k_gram_sum(int nblk, const double *part, int ma, int mb, double *G) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ma * mb) return;
+    const int a = e / mb, b = e % mb;
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += part[(size_t)k * 4096 + a * 64 + b];
+    G[e] = s;
+}
+
+// Y = X T (X: n x ma column-major; T: ma x mb column-major)
+__global__ __launch_bounds__(kBlock) void k_tsgemm(int n, const double *X, int ma, const double *T, int mb,
+                                                   double *Y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x[64];
+#pragma unroll
+    for (int a = 0; a < 64; ++a) x[a] = (a < ma) ? X[(size_t)a * n + i] : 0.0;
+    for (int j = 0; j < mb; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < 64; ++a)
+            if (a < ma) s += x[a] * T[(size_t)j * ma + a];
+        Y[(size_t)j * n + i] = s;
+    }
+}
+
+__global__ void k_grad(int n, const int64_t *rowptr, const int32_t *col, const double *lam, const double *x,
+                       double *g) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double li = lam[i];
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) g[k] = -li * x[col[k]];
+}
+
+inline int blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+inline int mt_bucket(int m) {
+    if (m <= 0) return 0;
+    if (m <= 8) return 8;
+    if (m <= 16) return 16;
+    if (m <= 32) return 32;
+    return 64;
+}
+
+} // namespace
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+
+#define ESD_MT_SWITCH(mt, CALL)                                                                    \
+    switch (mt_bucket(mt)) {                                                                       \
+    case 0: { constexpr int MTV = 0; CALL; } break;                                                \
+    case 8: { constexpr int MTV = 8; CALL; } break;                                                \
+    case 16: { constexpr int MTV = 16; CALL; } break;                                              \
+    case 32: { constexpr int MTV = 32; CALL; } break;                                              \
+    default: { constexpr int MTV = 64; CALL; } break;                                              \
+    }
+
+template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, int mt, bool power, int grid, hipStream_t s) {
+    if (power) {
+        ESD_MT_SWITCH(mt, (k_spmv_it<T, MTV, true><<<grid, kBlock, 0, s>>>(a)));
+    } else {
+        ESD_MT_SWITCH(mt, (k_spmv_it<T, MTV, false><<<grid, kBlock, 0, s>>>(a)));
+    }
+}
+void launch_spmv_it(const SpmvIt<double> &a, int mt, bool power, int grid, hipStream_t s) {
+    spmv_it_impl(a, mt, power, grid, s);
+}
+void launch_spmv_it(const SpmvIt<float> &a, int mt, bool power, int grid, hipStream_t s) {
+    spmv_it_impl(a, mt, power, grid, s);
+}
+
+template <typename T> static void update_it_impl(const UpdIt<T> &a, int mt, int kind, int grid, hipStream_t s) {
+    if (kind == 1) {
+        ESD_MT_SWITCH(mt, (k_update_it<T, (MTV > 0 ? MTV : 8), 1><<<grid, kBlock, 0, s>>>(a)));
+    } else if (kind == 2) {
+        ESD_MT_SWITCH(mt, (k_update_it<T, (MTV > 0 ? MTV : 8), 2><<<grid, kBlock, 0, s>>>(a)));
+    } else {
+        k_update_it<T, 0, 0><<<grid, kBlock, 0, s>>>(a);
+    }
+}
+void launch_update_it(const UpdIt<double> &a, int mt, int kind, int grid, hipStream_t s) {
+    update_it_impl(a, mt, kind, grid, s);
+}
+void launch_update_it(const UpdIt<float> &a, int mt, int kind, int grid, hipStream_t s) {
+    update_it_impl(a, mt, kind, grid, s);
+}
+
+template <typename T> static void fwd_impl(const Sweep<T> &a, bool last, bool sc, int grid, hipStream_t s) {
+    if (!last) k_fwd<T, false, false><<<grid, kBlock, 0, s>>>(a);
+    else if (sc) k_fwd<T, true, true><<<grid, kBlock, 0, s>>>(a);
+    else k_fwd<T, true, false><<<grid, kBlock, 0, s>>>(a);
+}
+void launch_fwd(const Sweep<double> &a, bool last, bool sc, int grid, hipStream_t s) { fwd_impl(a, last, sc, grid, s); }
+void launch_fwd(const Sweep<float> &a, bool last, bool sc, int grid, hipStream_t s) { fwd_impl(a, last, sc, grid, s); }
+
+template <typename T> static void bwd_impl(const Sweep<T> &a, bool sc, int grid, hipStream_t s) {
+    if (sc) k_bwd<T, true><<<grid, kBlock, 0, s>>>(a);
+    else k_bwd<T, false><<<grid, kBlock, 0, s>>>(a);
+}
+void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
+void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
+
+template <typename T> static void copyz_impl(const Sweep<T> &a, bool sc, int grid, hipStream_t s) {
+    if (sc) k_copyz<T, true><<<grid, kBlock, 0, s>>>(a);
+    else k_copyz<T, false><<<grid, kBlock, 0, s>>>(a);
+}
+void launch_copyz(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { copyz_impl(a, sc, grid, s); }
+void launch_copyz(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { copyz_impl(a, sc, grid, s); }
+
+void launch_gather(int n, const int32_t *idx, const double *src, double *dst, hipStream_t s) {
+    k_gather<<<blocks(n), kBlock, 0, s>>>(n, idx, src, dst);
+}
+void launch_scatter(int n, const int32_t *idx, const double *src, double *dst, hipStream_t s) {
+    k_scatter<<<blocks(n), kBlock, 0, s>>>(n, idx, src, dst);
+}
+void launch_fill(int n, double *dst, double v, hipStream_t s) { k_fill<double><<<blocks(n), kBlock, 0, s>>>(n, dst, v); }
+void launch_fill(int n, float *dst, float v, hipStream_t s) { k_fill<float><<<blocks(n), kBlock, 0, s>>>(n, dst, v); }
+void launch_dot(int n, const double *a, const double *b, double *out, Scal *S, double tol, Red red, int grid,
+                hipStream_t s) {
+    k_dot<<<grid, kBlock, 0, s>>>(n, a, b, out, S, tol, red);
+}
+void launch_resid(int n, Ell<double> A, const double *b, const double *x, double *t, const double *W, int m,
+                  const double *Cinv, double *coef, double *out, Scal *S, int check, Red red, int grid,
+                  hipStream_t s) {
+    if (!W) m = 0;
+    ESD_MT_SWITCH(m, (k_resid<MTV><<<grid, kBlock, 0, s>>>(n, A, b, x, t, W, m, Cinv, coef, out, S, check, red)));
+}
+void launch_axpy_cols(int n, double *y, const double *M, int m, const double *coef, double sign, double *out,
+                      Scal *S, int check, Red red, int grid, hipStream_t s) {
+    ESD_MT_SWITCH(m, (k_axpy_cols<(MTV > 0 ? MTV : 8)><<<grid, kBlock, 0, s>>>(n, y, M, m, coef, sign, out, S,
+                                                                              check, red)));
+}
+void launch_tsdot(int n, const double *W, int m, const double *v, Scal *S, Red red, int grid, hipStream_t s) {
+    ESD_MT_SWITCH(m, (k_tsdot<(MTV > 0 ? MTV : 8)><<<grid, kBlock, 0, s>>>(n, W, m, v, S, red)));
+}
+void launch_spmv(int n, Ell<double> A, const double *x, double *y, hipStream_t s) {
+    k_spmv<<<blocks(n), kBlock, 0, s>>>(n, A, x, y);
+}
+void launch_rayleigh(int n, Ell<double> A, const double *v, double scale2, Scal *S, Red red, int grid,
+                     hipStream_t s) {
+    k_rayleigh<double><<<grid, kBlock, 0, s>>>(n, A, v, scale2, S, red);
+}
+void launch_rayleigh(int n, Ell<float> A, const float *v, double scale2, Scal *S, Red red, int grid,
+                     hipStream_t s) {
+    k_rayleigh<float><<<grid, kBlock, 0, s>>>(n, A, v, scale2, S, red);
+}
+void launch_coarse(int m, const double *Cinv, const double *s, double scale, double *out, hipStream_t st) {
+    if (m > 0) k_coarse<<<1, 64, 0, st>>>(m, Cinv, s, scale, out);
+}
+void launch_sample_store(int n, double *slot, const double *x, hipStream_t s) {
+    k_scale_copy<<<blocks(n), kBlock, 0, s>>>(n, x, slot, 1.0);
+}
+void launch_cast_scale(int n, const double *src, float *dst, double scale, hipStream_t s) {
+    k_cast_scale<<<blocks(n), kBlock, 0, s>>>(n, src, dst, scale);
+}
+void launch_cast(int64_t n, const double *src, float *dst, hipStream_t s) {
+    if (n > 0) k_cast<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, src, dst);
+}
+void launch_add_scaled(int n, double *x, const float *d, double scale, hipStream_t s) {
+    k_add_scaled<<<blocks(n), kBlock, 0, s>>>(n, x, d, scale);
+}
+void launch_sub(int n, const double *a, const double *b, double *dst, hipStream_t s) {
+    k_sub<<<blocks(n), kBlock, 0, s>>>(n, a, b, dst);
+}
+void launch_scale_copy(int n, const double *src, double *dst, double scale, hipStream_t s) {
+    k_scale_copy<<<blocks(n), kBlock, 0, s>>>(n, src, dst, scale);
+}
+void launch_factor_level(int r0, int r1, int n, Ell<double> L, double *lval, const double *adiag, double *ldiag,
+                         int *bad, hipStream_t s) {
+    // padding slots carry column n
+    const int rows = r1 - r0;
+    k_factor_level<<<blocks(rows), kBlock, 0, s>>>(r0, r1, n, L, lval, adiag, ldiag, bad);
+}
+void launch_finish_factor(int n, const double *ldiag, double *dinv, float *dinv32, hipStream_t s) {
+    k_finish_factor<<<blocks(n), kBlock, 0, s>>>(n, ldiag, dinv, dinv32);
+}
+void launch_gather_u(int64_t cnt, const int64_t *map, const double *lval, double *uval, hipStream_t s) {
+    if (cnt > 0) k_gather_u<<<(unsigned)((cnt + kBlock - 1) / kBlock), kBlock, 0, s>>>(cnt, map, lval, uval);
+}
+void launch_spmm(int n, Ell<double> A, const double *E, int m, double *AE, hipStream_t s) {
+    k_spmm<<<blocks(n), kBlock, 0, s>>>(n, A, E, m, AE);
+}
+int gram_grid(int n) {
+    int g = (n + 4095) / 4096;
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+    return g;
+}
+void launch_gram(int n, const double *E, int ma, const double *F, int mb, double *part, double *G, int grid,
+                 hipStream_t s) {
+    k_gram_part<<<grid, 256, 0, s>>>(n, E, ma, F, mb, part);
+    k_gram_sum<<<(ma * mb + 255) / 256, 256, 0, s>>>(grid, part, ma, mb, G);
+}
+void launch_tsgemm(int n, const double *X, int ma, const double *T, int mb, double *Y, hipStream_t s) {
+    k_tsgemm<<<blocks(n), kBlock, 0, s>>>(n, X, ma, T, mb, Y);
+}
+void launch_grad(int n, const int64_t *rowptr, const int32_t *col, const double *lam, const double *x, double *g,
+                 hipStream_t s) {
+    k_grad<<<blocks(n), kBlock, 0, s>>>(n, rowptr, col, lam, x, g);
+}
+
+} // namespace esd

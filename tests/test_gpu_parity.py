@@ -1,0 +1,255 @@
+"""GPU path (libesd.so through the C ABI) against the FP64 CPU oracle.
+
+Bars: integer/index results bit-exact; FP64 solutions within 1e-10 relative
+error and iteration counts within +-2 at tolerance; CG coefficients 1e-12 and
+kappa 1e-6 at matched iterations; Ritz values 1e-8 relative; the mixed solver
+reaches an FP64 true relative residual of 1e-8.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2203_08498_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(p, m_max=16):
+    from paper_2203_08498_amd import esd
+
+    return esd.Solver.from_problem(p, m_max=m_max)
+
+
+def _oracle(p):
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    return o
+
+
+def _relerr(a, b):
+    a = a.cpu().numpy() if hasattr(a, "cpu") else a
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _cases():
+    return {
+        "fv2d_natural": P.config1(N=40, nbox=2, box=6),
+        "fv3d_colors": P.config2(N=13, nsph=2, radius=2.5),   # 2197 rows: several tiles, ragged tail
+        "q1_colors": P.config4(Ne=11, nblk=2, blk=3),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    p = CASES[request.param]
+    print("case", request.param, "n", p.n, "nnz", p.nnz, flush=True)
+    s = _solver(p)
+    s.factor_ic0()
+    o = _oracle(p)
+    yield request.param, p, s, o
+    s.close()
+
+
+def test_permutation_bitexact(case):
+    name, p, s, o = case
+    assert np.array_equal(s.perm(), o.perm)
+
+
+def test_spmv(case):
+    name, p, s, o = case
+    x = np.random.default_rng(1).standard_normal(p.n)
+    y = s.spmv(x).cpu().numpy()
+    assert _relerr(y, o.spmv(x)) <= 1e-14
+
+
+def test_ic0_factor_diagonal(case):
+    name, p, s, o = case
+    rp, c, v = o.factor_csr()
+    dperm = v[rp[1:] - 1]  # oracle: logical order
+    d_user = np.empty(p.n)
+    d_user[o.perm] = dperm
+    assert np.abs(s.factor_diag() - d_user).max() <= 1e-13 * np.abs(d_user).max()
+
+
+def test_preconditioner(case):
+    name, p, s, o = case
+    r = np.random.default_rng(2).standard_normal(p.n)
+    assert _relerr(s.prec(r), o.prec(r)) <= 1e-12
+
+
+def test_iccg_at_tolerance_and_matched(case):
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    x, info = s.solve(p.f, tol=1e-8, maxit=5000)
+    y, oi = o.solve(p.f, tol=1e-8, maxit=5000)
+    assert info["status"] == 0 and info["converged"]
+    assert abs(info["iters"] - oi.iters) <= 2
+    assert _relerr(x, y) <= 1e-10
+    assert info["true_relres"] <= 1.01e-8
+    # matched iterations: same alpha/beta sequence, same kappa estimate
+    y2, oi2 = o.solve(p.f, tol=0.0, maxit=info["iters"])
+    a, b = s.history()
+    oa, ob = o.history()
+    assert len(a) == len(oa)
+    assert np.max(np.abs(a - oa) / np.abs(oa)) <= 1e-12
+    assert np.max(np.abs(b - ob) / np.abs(ob)) <= 1e-12
+    assert abs(info["kappa"] / oi2.kappa - 1) <= 1e-6
+    assert _relerr(x, y2) <= 1e-10
+    assert info["status"] != esd.NOT_CONVERGED
+
+
+def test_sampling_build_aux_and_accelerated_solves(case):
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    m, theta = 8, 1e-2
+    s.sample_errors(m)
+    x1, i1 = s.solve(p.f, tol=1e-8, maxit=5000)
+    o.arm_sampling(m)
+    y1, j1 = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE)
+    assert i1["iters"] == j1.iters  # needed for identical sample iterations
+    assert np.array_equal(s.samples(m), o.samples(m))
+    st, ritz, mb, mt = s.build_aux(theta)
+    ost, oritz, omb, omt = o.build_aux(theta)
+    assert (mb, mt) == (omb, omt)
+    assert np.max(np.abs(ritz - oritz) / np.abs(oritz)) <= 1e-8
+    if mt == 0:
+        pytest.skip("no Ritz value below theta for this case")
+    W, Cm = s.get_aux()
+    E, Wo, AWo, Co = o.aux()
+    # W is defined up to a rotation inside clusters: compare the projectors
+    Wn = W.cpu().numpy()
+    assert np.abs(Wn @ Wn.T - Wo @ Wo.T).max() <= 1e-8
+    assert np.abs(np.diag(Cm) - np.diag(Co)).max() <= 1e-8 * np.abs(np.diag(Co)).max()
+    b = P.sequence_rhs(p.f, y1)
+    for mode, omode in ((esd.DEFLATED, O.DEFLATED), (esd.SUBSPACE, O.SUBSPACE)):
+        x, info = s.solve(b, tol=1e-8, maxit=5000, mode=mode)
+        y, oi = o.solve(b, tol=1e-8, maxit=5000, mode=omode)
+        print(name, "mode", mode, "its", info["iters"], oi.iters, flush=True)
+        assert info["status"] == 0 and abs(info["iters"] - oi.iters) <= 2
+        assert _relerr(x, y) <= 1e-10
+        assert info["true_relres"] <= 1.01e-8
+        y2, oi2 = o.solve(b, tol=0.0, maxit=info["iters"], mode=omode)
+        assert abs(info["kappa"] / oi2.kappa - 1) <= 1e-6
+
+
+def test_power_iteration_kappa_es(case):
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    v0 = P.power_start(7, p.n)
+    s.set_power_start(v0)
+    o.set_power_start(v0)
+    s.sample_errors(8)
+    o.arm_sampling(8)
+    x, info = s.solve(p.f, tol=1e-8, maxit=5000, flags=esd.FLAG_POWER)
+    y, oi = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE | O.POWER)
+    assert info["iters"] == oi.iters
+    assert abs(info["lambda_max"] / oi.lambda_max - 1) <= 1e-10
+    s.build_aux(1e-2)
+    o.build_aux(1e-2)
+    b = P.sequence_rhs(p.f, y)
+    x2, i2 = s.solve(b, tol=1e-8, maxit=5000, flags=esd.FLAG_POWER)
+    y2, j2 = o.solve(b, tol=1e-8, maxit=5000, flags=O.POWER)
+    assert i2["iters"] == j2.iters
+    assert abs(i2["kappa_es"] / j2.kappa_es - 1) <= 1e-6
+
+
+def test_mixed_precision_meets_fp64_tolerance(case):
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    for mode in (esd.PLAIN, esd.DEFLATED, esd.SUBSPACE):
+        if mode != esd.PLAIN and getattr(s, "m_tilde", 0) == 0:
+            continue
+        x, info = s.solve(p.f, tol=1e-8, maxit=20000, mode=mode, flags=esd.FLAG_MIXED)
+        y, _ = o.solve(p.f, tol=1e-12, maxit=20000)
+        print(name, "mixed mode", mode, "its", info["iters"], "outer", info["outer_iters"],
+              "relres", info["true_relres"], "err", _relerr(x, y), flush=True)
+        assert info["converged"] and info["true_relres"] <= 1e-8
+        assert _relerr(x, y) <= 1e-5
+
+
+def test_gradient_values(case):
+    name, p, s, o = case
+    rng = np.random.default_rng(5)
+    lam = rng.standard_normal(p.n)
+    x = rng.standard_normal(p.n)
+    g = s.grad_values(lam, x).cpu().numpy()
+    assert np.array_equal(g, o.grad_values(lam, x))
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_zero_rhs_and_maxit():
+    from paper_2203_08498_amd import esd
+
+    p = CASES["fv3d_colors"]
+    s = _solver(p)
+    s.factor_ic0()
+    x, info = s.solve(np.zeros(p.n), tol=1e-8, maxit=100)
+    assert info["iters"] == 0 and info["converged"] and float(x.abs().max()) == 0.0
+    x, info = s.solve(p.f, tol=1e-14, maxit=3)
+    assert info["status"] == esd.NOT_CONVERGED and info["iters"] == 3
+    o = _oracle(p)
+    y, oi = o.solve(p.f, tol=1e-14, maxit=3)
+    assert _relerr(x, y) <= 1e-12
+    x, info = s.solve(p.f, tol=1e-8, maxit=0)
+    assert info["iters"] == 0 and info["status"] == esd.NOT_CONVERGED
+    s.close()
+
+
+def test_errors_and_fallbacks():
+    from paper_2203_08498_amd import esd
+
+    p = CASES["fv2d_natural"]
+    s = _solver(p)
+    with pytest.raises(esd.EsdError):
+        s.solve(p.f, mode=esd.PLAIN)  # not factored
+    s.factor_ic0()
+    with pytest.raises(esd.EsdError) as e:
+        s.solve(p.f, mode=esd.DEFLATED)
+    assert e.value.status == esd.ENOAUX
+    with pytest.raises(esd.EsdError):
+        s.build_aux(1e-2)  # no samples yet
+    s.sample_errors(8)
+    s.solve(p.f, tol=1e-8)
+    st, ritz, mb, mt = s.build_aux(1e-9)
+    assert st == esd.AUX_EMPTY and mt == 0
+    x, info = s.solve(p.f, tol=1e-8, mode=esd.DEFLATED)
+    assert info["status"] == esd.AUX_EMPTY and info["converged"] and info["mode_used"] == esd.PLAIN
+    s.close()
+    # indefinite matrix: IC(0) breakdown is reported
+    rp = np.array([0, 2, 4]); c = np.array([0, 1, 0, 1]); v = np.array([1.0, 2.0, 2.0, 1.0])
+    s2 = esd.Solver(rp, c, v, m_max=1)
+    with pytest.raises(esd.EsdError) as e:
+        s2.factor_ic0()
+    assert e.value.status == esd.ENOTSPD
+    s2.close()
+
+
+def test_exact_eigenvectors_closed_form_on_gpu():
+    """Deflating exact Poisson eigenvectors (M = I) leaves kappa = lambda_max / lambda_{k+1}."""
+    from paper_2203_08498_amd import esd
+
+    shape = (30, 23)
+    k = 6
+    p = P.poisson(shape)
+    lam = P.poisson_spectrum(shape)
+    d = len(shape)
+    idx = np.indices(shape).reshape(d, -1).T + 1
+    vals = np.array([1 - sum(np.cos(j[a] * np.pi / (shape[a] + 1)) for a in range(d)) / d for j in idx])
+    order = np.argsort(vals, kind="stable")[:k]
+    _, V = P.poisson_eigvec(shape, [tuple(idx[t]) for t in order])
+    s = _solver(p, m_max=8)
+    s.set_aux(V)
+    x, info = s.solve(p.f, tol=1e-12, maxit=5000, mode=esd.DEFLATED, flags=esd.FLAG_NOPREC)
+    assert abs(info["kappa"] / (lam[-1] / lam[k]) - 1) < 1e-6
+    x, info = s.solve(p.f, tol=1e-12, maxit=5000, mode=esd.SUBSPACE, flags=esd.FLAG_NOPREC)
+    spec = np.concatenate([lam[:k] + 1, lam[k:]])
+    assert abs(info["kappa"] / (spec.max() / spec.min()) - 1) < 1e-6
+    s.close()
