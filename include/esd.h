@@ -111,6 +111,12 @@ esd_status esd_factor_ic0(esd_ctx *ctx);
  * stop test are sampled.  1 <= m <= m_max. */
 esd_status esd_sample_errors(esd_ctx *ctx, int32_t m);
 
+/* esd_load_samples - install k approximate solutions X(d) (n x k, column-major,
+ * float64, user order; taken as sampled at iterations 1..k) and the final
+ * solution xN(d) in place of a sampling solve, e.g. to resume from saved
+ * samples; the next esd_build_aux uses them.  1 <= k <= m_max. */
+esd_status esd_load_samples(esd_ctx *ctx, const double *X, int32_t k, const double *xN);
+
 /* esd_build_aux - after a sampling solve: error vectors e = x_1 - x~ (eq.
  * (ek)), classical Gram-Schmidt applied twice with drop tolerance 1e-10
  * (eq. (ekd)), Ritz pairs of E^T A E (eq. (Rayleigh-Ritz)), W from the Ritz

@@ -53,6 +53,7 @@ def lib():
         L.orc_prec_apply.argtypes = [P, P, P]
         L.orc_sample_schedule.argtypes = [C.c_int, i64, P]
         L.orc_arm_sampling.argtypes = [P, C.c_int]
+        L.orc_load_samples.argtypes = [P, P, C.c_int, P]
         L.orc_sym_eig.argtypes = [C.c_int, P, P, P]
         L.orc_build_aux.argtypes = [P, dbl, P, P, P]
         L.orc_set_aux.argtypes = [P, P, C.c_int]
@@ -168,6 +169,14 @@ class Oracle:
         st = lib().orc_arm_sampling(self.h, m)
         if st != 0:
             raise ValueError("bad m")
+
+    def load_samples(self, X, xN):
+        """X: n x k approximate solutions (taken as iterations 1..k), xN: final solution."""
+        X = np.asfortranarray(X, dtype=np.float64)
+        xN = np.ascontiguousarray(xN, dtype=np.float64)
+        st = lib().orc_load_samples(self.h, X.ctypes.data_as(C.c_void_p), X.shape[1], _p(xN))
+        if st != 0:
+            raise ValueError("bad samples")
 
     def set_power_start(self, v):
         v = np.ascontiguousarray(v, dtype=np.float64)

@@ -330,6 +330,25 @@ int orc_sample_schedule(int m, int64_t N, int64_t *iters_by_slot) {
     return filled;
 }
 
+/* Install k approximate solutions X (n x k, column-major, user order) as if a
+ * sampling solve had stored them at iterations 1..k, and x_N as its final
+ * solution (checkpoint/resume of the sampling step). */
+int orc_load_samples(orc *o, const double *X_user, int k, const double *xN_user) {
+    if (k <= 0 || k > 4096) return OR_EINVAL;
+    o->m_req = k;
+    free(o->slots); free(o->slot_iter); free(o->xN);
+    o->slots = malloc((size_t)k * o->n * sizeof(double));
+    o->slot_iter = calloc(k, sizeof(int32_t));
+    o->xN = malloc(o->n * sizeof(double));
+    for (int s = 0; s < k; ++s) {
+        to_perm(o, X_user + (int64_t)s * o->n, o->slots + (int64_t)s * o->n);
+        o->slot_iter[s] = s + 1;
+    }
+    to_perm(o, xN_user, o->xN);
+    o->nsamples = k;
+    return OR_OK;
+}
+
 int orc_arm_sampling(orc *o, int m) {
     if (m <= 0 || m > 4096) return OR_EINVAL;
     o->m_req = m;

@@ -16,7 +16,6 @@
 #include "kernels.h"
 
 using esd::Ell;
-using esd::Red;
 using esd::Scal;
 
 namespace {
@@ -63,7 +62,8 @@ struct esd_ctx {
     // FP32 vectors
     float *r32 = nullptr, *z32 = nullptr, *zsc32 = nullptr, *y32 = nullptr, *q32 = nullptr,
           *p32[2] = {nullptr, nullptr}, *d32 = nullptr, *v32[2] = {nullptr, nullptr};
-    Red red{};
+    double *part_spmv = nullptr, *part_upd = nullptr, *part_gen = nullptr, *part_sweep = nullptr;
+    int64_t sweep_cap = 0;
     Scal *S = nullptr;
     Scal *Sh = nullptr; // pinned host mirror
     // sampling
@@ -176,14 +176,14 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
     return V;
 }
 
-// One application of the preconditioner (all sweep launches).  kind 2 adds
-// W u (subspace correction).  The final launch reduces (r, z) and forms beta.
+// One application of the preconditioner (all sweep launches).  With sc the
+// coarse term W u is added into zsc.  Every launch that finishes rows of z
+// writes one (r, z) partial per block; returns the number of partial slots.
 template <typename T>
-void launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, int hist_base) {
+int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc) {
     esd::Sweep<T> s{};
     s.n = (int)c->n;
     s.S = c->S;
-    s.red = c->red;
     s.dinv = V.dinv;
     s.r = V.r;
     s.y = V.y;
@@ -191,27 +191,101 @@ void launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, int hist_
     s.zsc = sc ? V.zsc : V.z;
     s.W = V.W;
     s.m = sc ? c->m_tilde : 0;
-    s.hist_beta = c->ha ? c->hb : nullptr;
-    s.hist_base = hist_base;
     if (noprec) {
-        s.r0 = 0; s.r1 = (int)c->n; s.final_ = 1;
-        esd::launch_copyz(s, sc, grid_n(c), c->stream);
-        return;
+        s.r0 = 0; s.r1 = (int)c->n;
+        s.part = c->part_sweep;
+        const int g = esd::grid_red(c->n, 1);
+        esd::launch_copyz(s, sc, g, c->stream);
+        return g;
     }
+    int off = 0;
     const int nl = (int)c->lvl.size() - 1;
     s.M = V.L;
     for (int l = 0; l < nl; ++l) {
         s.r0 = (int)c->lvl[l]; s.r1 = (int)c->lvl[l + 1];
         const bool last = (l == nl - 1);
-        s.final_ = last && nl == 1;
-        esd::launch_fwd(s, last, sc, esd::grid_for(s.r1 - s.r0), c->stream);
+        const int g = esd::grid_red(s.r1 - s.r0, 1);
+        s.part = c->part_sweep + off;
+        esd::launch_fwd(s, last, sc, g, c->stream);
+        if (last) off += g;
     }
     s.M = V.U;
     for (int l = nl - 2; l >= 0; --l) {
         s.r0 = (int)c->lvl[l]; s.r1 = (int)c->lvl[l + 1];
-        s.final_ = (l == 0);
-        esd::launch_bwd(s, sc, esd::grid_for(s.r1 - s.r0), c->stream);
+        const int g = esd::grid_red(s.r1 - s.r0, 1);
+        s.part = c->part_sweep + off;
+        esd::launch_bwd(s, sc, g, c->stream);
+        off += g;
     }
+    return off;
+}
+
+esd::FinGen fin_gen(esd_ctx *c, int nblk, int stride, int ncol) {
+    esd::FinGen f{};
+    f.S = c->S;
+    f.part = c->part_gen;
+    f.nblk = nblk;
+    f.stride = stride;
+    f.ncol = ncol;
+    f.scale0 = 1.0;
+    f.settol = -1.0;
+    f.cscale = 1.0;
+    return f;
+}
+
+// ||v||^2 -> *out (device)
+void dev_norm2(esd_ctx *c, const double *v, double *out) {
+    int nb = 0;
+    esd::launch_dot((int)c->n, v, v, c->part_gen, &nb, c->stream);
+    esd::FinGen f = fin_gen(c, nb, 1, 1);
+    f.out0 = out;
+    esd::launch_fin_gen(f, c->stream);
+}
+
+// t = b - A x; optionally coef = C^{-1} W^T t (m columns), *out = ||t||^2,
+// stop check against S->tol2
+void dev_resid(esd_ctx *c, const double *b, const double *x, double *t, const double *W, int m, double *coef,
+               double *out, int check) {
+    int nb = 0, st = 0;
+    esd::launch_resid((int)c->n, c->A.e64(), b, x, t, W, W ? m : 0, c->part_gen, &nb, &st, c->stream);
+    esd::FinGen f = fin_gen(c, nb, st, 1 + (W ? m : 0));
+    f.out0 = out;
+    f.check = check;
+    if (W && m > 0) {
+        f.vcol0 = 1;
+        f.m = m;
+        f.Cinv = c->Cinv;
+        f.coef = coef;
+    }
+    esd::launch_fin_gen(f, c->stream);
+}
+
+// y += sign * M coef; optional *out = ||y||^2 and stop check
+void dev_axpy(esd_ctx *c, double *y, const double *M, int m, const double *coef, double sign, double *out,
+              int check) {
+    const bool red = out || check;
+    int nb = 0;
+    esd::launch_axpy_cols((int)c->n, y, M, m, coef, sign, red ? c->part_gen : nullptr, &nb, c->stream);
+    if (red) {
+        esd::FinGen f = fin_gen(c, nb, 1, 1);
+        f.out0 = out;
+        f.check = check;
+        esd::launch_fin_gen(f, c->stream);
+    }
+}
+
+// S->svec = W^T v (m columns); optionally coef = cscale C^{-1} W^T v
+void dev_tsdot(esd_ctx *c, const double *W, int m, const double *v, double *coef, double cscale) {
+    int nb = 0, st = 0;
+    esd::launch_tsdot((int)c->n, W, m, v, c->part_gen, &nb, &st, c->stream);
+    esd::FinGen f = fin_gen(c, nb, st, m);
+    f.vcol0 = 0;
+    f.m = m;
+    f.store_svec = 1;
+    f.Cinv = c->Cinv;
+    f.coef = coef;
+    f.cscale = cscale;
+    esd::launch_fin_gen(f, c->stream);
 }
 
 struct KrylovOpts {
@@ -228,33 +302,46 @@ struct KrylovOpts {
 };
 
 // Runs the CG loop from the state prepared by the caller (x, r, S with
-// tol2/maxit/done set, (W^T r -> u) for subspace correction).  Returns the
+// tol2/maxit/done set; u = C^{-1} W^T r for subspace correction).  Returns the
 // number of completed iterations through *iters and the exit code in Sh->done.
 template <typename T>
 esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iters, int *vbase) {
     const int n = (int)c->n;
     const int m = (o.kind != 0) ? c->m_tilde : 0;
     const bool sc = (o.kind == 2);
-    const int g = grid_n(c);
     // z_0 = M^{-1} r_0 (+ W u), rho_0
-    launch_prec<T>(c, V, o.noprec, sc, o.hist_base);
+    {
+        const int ns = launch_prec<T>(c, V, o.noprec, sc);
+        esd::FinRho fr{};
+        fr.S = c->S; fr.part_sweep = c->part_sweep; fr.nsweep = ns; fr.init = 1;
+        esd::launch_fin_rho(fr, c->stream);
+    }
+    const int ms = (o.kind == 1) ? m : 0;
+    const int sstride = esd::spmv_stride(ms, o.power);
+    const int gs = esd::grid_red(n, sstride);
+    const int ustride = esd::update_stride(m, o.kind);
+    const int gu = esd::grid_red(n, ustride);
     esd::SpmvIt<T> sa{};
-    sa.n = n; sa.S = c->S; sa.red = c->red; sa.A = V.A;
+    sa.n = n; sa.S = c->S; sa.part = c->part_spmv; sa.A = V.A;
     sa.z = sc ? V.zsc : V.z;
     sa.W = (o.kind == 1) ? V.W : nullptr;
-    sa.m = (o.kind == 1) ? m : 0;
-    sa.Cinv = c->Cinv;
-    sa.hist_alpha = c->ha;
-    sa.hist_base = o.hist_base;
+    sa.m = ms;
     sa.slot_table = o.sampling ? c->slot_table : nullptr;
     sa.sample_base = o.sample_base;
     sa.slots = c->slots;
     sa.xit = V.x;
     sa.xbase = o.xbase;
     sa.xscale = o.xscale;
+    sa.q = V.q;
+    esd::FinAlpha fa{};
+    fa.S = c->S; fa.part = c->part_spmv; fa.nblk = gs; fa.stride = sstride; fa.m = ms; fa.power = o.power;
+    fa.Cinv = c->Cinv; fa.hist_alpha = c->ha; fa.hist_base = o.hist_base;
     esd::UpdIt<T> ua{};
-    ua.n = n; ua.S = c->S; ua.red = c->red; ua.q = V.q; ua.x = V.x; ua.r = V.r;
-    ua.AW = V.AW; ua.W = V.W; ua.m = m; ua.Cinv = c->Cinv;
+    ua.n = n; ua.S = c->S; ua.part = c->part_upd; ua.q = V.q; ua.x = V.x; ua.r = V.r;
+    ua.AW = V.AW; ua.W = V.W; ua.m = m;
+    esd::FinRho fr{};
+    fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = ustride;
+    fr.part_sweep = c->part_sweep; fr.hist_beta = c->hb; fr.hist_base = o.hist_base; fr.init = 0;
     int launched = 0;
     int chunk = o.sync_every ? 1 : 8;
     const bool timing = o.timing;
@@ -265,15 +352,17 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             sa.pnew = V.p[(it + 1) & 1];
             sa.vold = V.v[(*vbase + it) & 1];
             sa.vnew = V.v[(*vbase + it + 1) & 1];
-            sa.q = V.q;
             ua.p = V.p[(it + 1) & 1];
             if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 0], c->stream));
-            esd::launch_spmv_it(sa, sa.m, o.power, g, c->stream);
+            esd::launch_spmv_it(sa, ms, o.power, gs, c->stream);
             if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 1], c->stream));
-            esd::launch_update_it(ua, m, o.kind, g, c->stream);
+            esd::launch_fin_alpha(fa, c->stream);
+            esd::launch_update_it(ua, m, o.kind, gu, c->stream);
+            if (sc) esd::launch_fin_u(c->S, c->part_upd, gu, ustride, m, c->Cinv, c->stream);
             if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 2], c->stream));
-            launch_prec<T>(c, V, o.noprec, sc, o.hist_base);
+            fr.nsweep = launch_prec<T>(c, V, o.noprec, sc);
             if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 3], c->stream));
+            esd::launch_fin_rho(fr, c->stream);
         }
         HIPCHK(hipGetLastError());
         esd_status st = sync_read(c);
@@ -337,7 +426,8 @@ esd_status read_history(esd_ctx *c, int total) {
 esd_status ensure_tables(esd_ctx *c, int maxit) {
     const int64_t need = (int64_t)maxit + 4;
     if (c->hcap < need) {
-        hipFree(c->ha); hipFree(c->hb);
+        (void)hipFree(c->ha);
+        (void)hipFree(c->hb);
         c->ha = c->hb = nullptr;
         HIPCHK(dalloc(&c->ha, need));
         HIPCHK(dalloc(&c->hb, need));
@@ -346,7 +436,7 @@ esd_status ensure_tables(esd_ctx *c, int maxit) {
     if (c->armed) {
         esd::sampling_table(c->m_req, (int64_t)maxit + 2, c->table_h);
         if (c->slot_table_cap < (int64_t)c->table_h.size()) {
-            hipFree(c->slot_table);
+            (void)hipFree(c->slot_table);
             c->slot_table = nullptr;
             HIPCHK(dalloc(&c->slot_table, (int64_t)c->table_h.size()));
             c->slot_table_cap = (int64_t)c->table_h.size();
@@ -354,14 +444,15 @@ esd_status ensure_tables(esd_ctx *c, int maxit) {
         HIPCHK(hipMemcpyAsync(c->slot_table, c->table_h.data(), sizeof(int32_t) * c->table_h.size(),
                               hipMemcpyHostToDevice, c->stream));
     }
-    if (!c->ev.empty() && (int)c->ev.size() >= 4 * 32) return ESD_OK;
+    if ((int)c->ev.size() >= 4 * 32) return ESD_OK;
     c->ev.resize(4 * 32);
     for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
     return ESD_OK;
 }
 
 // iterations kept in every slot for a sampling solve that ran `iters`
-// iterations (`stopped_at_max`: the last iterate is sampled too)
+// iterations (`last_sampled`: the solve stopped at maxit, so its last iterate
+// was sampled too)
 void record_samples(esd_ctx *c, int iters, bool last_sampled) {
     c->slot_iter.assign(c->m_req, 0);
     c->nsamples = 0;
@@ -377,7 +468,6 @@ void record_samples(esd_ctx *c, int iters, bool last_sampled) {
 esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol, int maxit, int kind,
                       int flags, double *xout, esd_info *info) {
     const int n = (int)c->n;
-    const int g = grid_n(c);
     const int m = kind ? c->m_tilde : 0;
     const bool sampling = c->armed;
     const bool power = (flags & ESD_FLAG_POWER) != 0;
@@ -388,13 +478,18 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
     init_scal(c, maxit, c->vs64, 0);
     esd_status st = put_scal(c);
     if (st) return st;
-    esd::launch_dot(n, c->b, c->b, &c->S->bnorm2, c->S, tol, c->red, g, c->stream);
-    // r_0 = b - A x_0; deflation: r_0 = P^T r_0 = r_0 - AW C^{-1} W^T r_0
+    {
+        int nb = 0;
+        esd::launch_dot(n, c->b, c->b, c->part_gen, &nb, c->stream);
+        esd::FinGen f = fin_gen(c, nb, 1, 1);
+        f.settol = tol;
+        esd::launch_fin_gen(f, c->stream);
+    }
+    // r_0 = b - A x_0; deflation: r_0 = P^T r_0 = r_0 - AW C^{-1} W^T r_0;
+    // subspace correction: u = C^{-1} W^T r_0 for z_0
     double *coef = (kind == 1) ? c->S->mu : (kind == 2 ? c->S->u : nullptr);
-    esd::launch_resid(n, c->A.e64(), c->b, c->x, c->r, m ? c->W : nullptr, m, c->Cinv, coef, nullptr, c->S,
-                      kind != 1, c->red, g, c->stream);
-    if (kind == 1)
-        esd::launch_axpy_cols(n, c->r, c->AW, m, c->S->mu, -1.0, nullptr, c->S, 1, c->red, g, c->stream);
+    dev_resid(c, c->b, c->x, c->r, m ? c->W : nullptr, m, coef, nullptr, kind != 1);
+    if (kind == 1) dev_axpy(c, c->r, c->AW, m, c->S->mu, -1.0, nullptr, 1);
     KrylovOpts o;
     o.kind = kind;
     o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
@@ -406,20 +501,24 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
     st = krylov<double>(c, V, o, &iters, &c->vb64);
     if (st) return st;
     const int done = c->Sh->done;
+    const double rr = c->Sh->rr;
     c->segments.assign(1, {0, iters});
     if (sampling && done == 2 && iters < (int)c->table_h.size() && c->table_h[iters] >= 0)
         esd::launch_sample_store(n, c->slots + (size_t)c->table_h[iters] * n, c->x, c->stream);
     if (kind == 1) {
         // x = P x_i + W C^{-1} W^T b  ==  x_i + W C^{-1} W^T (b - A x_i)
-        esd::launch_resid(n, c->A.e64(), c->b, c->x, c->t, c->W, m, c->Cinv, c->S->mu, nullptr, c->S, 0, c->red,
-                          g, c->stream);
-        esd::launch_axpy_cols(n, c->x, c->W, m, c->S->mu, 1.0, nullptr, c->S, 0, c->red, g, c->stream);
+        dev_resid(c, c->b, c->x, c->t, c->W, m, c->S->mu, nullptr, 0);
+        dev_axpy(c, c->x, c->W, m, c->S->mu, 1.0, nullptr, 0);
     }
-    esd::launch_resid(n, c->A.e64(), c->b, c->x, c->t, nullptr, 0, nullptr, nullptr, &c->S->out, c->S, 0, c->red,
-                      g, c->stream);
+    dev_resid(c, c->b, c->x, c->t, nullptr, 0, nullptr, &c->S->out, 0);
     if (power) {
         c->vs64 = c->Sh->vscale;
-        esd::launch_rayleigh(n, c->A.e64(), c->v[c->vb64], c->vs64 * c->vs64, c->S, c->red, g, c->stream);
+        int nb = 0;
+        esd::launch_rayleigh(n, c->A.e64(), c->v[c->vb64], c->part_gen, &nb, c->stream);
+        esd::FinGen f = fin_gen(c, nb, 1, 1);
+        f.out0 = &c->S->lam;
+        f.scale0 = c->vs64 * c->vs64;
+        esd::launch_fin_gen(f, c->stream);
     }
     esd::launch_scatter(n, c->p2u, c->x, xout, c->stream);
     if (sampling) {
@@ -427,7 +526,6 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
         record_samples(c, iters, done == 2);
         c->armed = false;
     }
-    double rr = c->Sh->rr;
     st = sync_read(c);
     if (st) return st;
     st = read_history(c, iters);
@@ -452,7 +550,6 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
 esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol, int maxit, int kind,
                        int flags, double *xout, esd_info *info) {
     const int n = (int)c->n;
-    const int g = grid_n(c);
     const int m = kind ? c->m_tilde : 0;
     const bool sampling = c->armed;
     const bool power = (flags & ESD_FLAG_POWER) != 0;
@@ -463,7 +560,13 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     init_scal(c, maxit, c->vs32, 0);
     esd_status st = put_scal(c);
     if (st) return st;
-    esd::launch_dot(n, c->b, c->b, &c->S->bnorm2, c->S, tol, c->red, g, c->stream);
+    {
+        int nb = 0;
+        esd::launch_dot(n, c->b, c->b, c->part_gen, &nb, c->stream);
+        esd::FinGen f = fin_gen(c, nb, 1, 1);
+        f.settol = tol;
+        esd::launch_fin_gen(f, c->stream);
+    }
     st = sync_read(c);
     if (st) return st;
     const double bn2 = c->Sh->bnorm2, tol2 = c->Sh->tol2;
@@ -473,11 +576,12 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     c->segments.clear();
     for (outer = 0; outer <= c->max_outer; ++outer) {
         // FP64 true residual; deflation: coarse correction x += W C^{-1} W^T r
-        esd::launch_resid(n, c->A.e64(), c->b, c->x, c->r, m && kind == 1 ? c->W : nullptr, kind == 1 ? m : 0,
-                          c->Cinv, c->S->mu, &c->S->out, c->S, 0, c->red, g, c->stream);
         if (kind == 1) {
-            esd::launch_axpy_cols(n, c->x, c->W, m, c->S->mu, 1.0, nullptr, c->S, 0, c->red, g, c->stream);
-            esd::launch_axpy_cols(n, c->r, c->AW, m, c->S->mu, -1.0, &c->S->out, c->S, 0, c->red, g, c->stream);
+            dev_resid(c, c->b, c->x, c->r, c->W, m, c->S->mu, nullptr, 0);
+            dev_axpy(c, c->x, c->W, m, c->S->mu, 1.0, nullptr, 0);
+            dev_axpy(c, c->r, c->AW, m, c->S->mu, -1.0, &c->S->out, 0);
+        } else {
+            dev_resid(c, c->b, c->x, c->r, nullptr, 0, nullptr, &c->S->out, 0);
         }
         st = sync_read(c);
         if (st) return st;
@@ -495,11 +599,8 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         c->Sh->bnorm2 = bn2;
         st = put_scal(c);
         if (st) return st;
-        if (kind == 2) {
-            // u = C^{-1} W^T r / ||r|| for the first preconditioned inner residual
-            esd::launch_tsdot(n, c->W, m, c->r, c->S, c->red, g, c->stream);
-            esd::launch_coarse(m, c->Cinv, c->S->svec, 1.0 / rn, c->S->u, c->stream);
-        }
+        // u = C^{-1} W^T r / ||r|| for the first preconditioned inner residual
+        if (kind == 2) dev_tsdot(c, c->W, m, c->r, c->S->u, 1.0 / rn);
         KrylovOpts o;
         o.kind = kind;
         o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
@@ -521,9 +622,15 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         esd::launch_add_scaled(n, c->x, c->d32, rn, c->stream);
         if (done_in == 3) return fail(c, ESD_ENUMERIC, "non-finite value in the inner iteration");
     }
-    esd::launch_resid(n, c->A.e64(), c->b, c->x, c->t, nullptr, 0, nullptr, nullptr, &c->S->out, c->S, 0, c->red,
-                      g, c->stream);
-    if (power) esd::launch_rayleigh(n, c->A.e32(), c->v32[c->vb32], c->vs32 * c->vs32, c->S, c->red, g, c->stream);
+    dev_resid(c, c->b, c->x, c->t, nullptr, 0, nullptr, &c->S->out, 0);
+    if (power) {
+        int nb = 0;
+        esd::launch_rayleigh(n, c->A.e32(), c->v32[c->vb32], c->part_gen, &nb, c->stream);
+        esd::FinGen f = fin_gen(c, nb, 1, 1);
+        f.out0 = &c->S->lam;
+        f.scale0 = c->vs32 * c->vs32;
+        esd::launch_fin_gen(f, c->stream);
+    }
     esd::launch_scatter(n, c->p2u, c->x, xout, c->stream);
     if (sampling) {
         HIPCHK(hipMemcpyAsync(c->xN, c->x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
@@ -554,11 +661,11 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         info->mode_used = kind;
         info->relres = bn2 > 0 ? std::sqrt(rn2 / bn2) : std::sqrt(rn2);
         info->true_relres = bn2 > 0 ? std::sqrt(c->Sh->out / bn2) : std::sqrt(c->Sh->out);
+        info->lambda_max = power ? c->Sh->lam : 0.0;
         fill_lanczos(c, info);
     }
     return converged ? ESD_OK : ESD_NOT_CONVERGED;
 }
-
 
 // C = W^T (A W) on the matrix cores, symmetrised; C^{-1} from its Cholesky
 // factor (host, FP64); FP32 copies of W and AW for the mixed inner loop.
@@ -617,7 +724,7 @@ void esd_destroy(esd_ctx *c) {
     void *ptrs[] = {c->u_from_l, c->adiag, c->ldiag, c->dinv, c->dinv32, c->p2u, c->urp, c->ucol, c->bad,
                     c->b, c->x, c->r, c->z, c->zsc, c->y, c->q, c->p[0], c->p[1], c->t, c->v[0], c->v[1],
                     c->r32, c->z32, c->zsc32, c->y32, c->q32, c->p32[0], c->p32[1], c->d32, c->v32[0], c->v32[1],
-                    c->red.part, c->red.gpart, c->red.tick, c->S, c->slots, c->slot_table, c->xN,
+                    c->part_spmv, c->part_upd, c->part_gen, c->part_sweep, c->S, c->slots, c->slot_table, c->xN,
                     c->E, c->AE, c->W, c->AW, c->W32, c->AW32, c->Cinv, c->gram_part, c->G, c->Tm, c->ha, c->hb};
     for (void *p : ptrs) if (p) hipFree(p);
     if (c->Sh) hipHostFree(c->Sh);
@@ -688,11 +795,16 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
         SETUP_HIP(dalloc(p, nv));
         esd::launch_fill((int)nv, *p, 0.0f, c->stream);
     }
-    const int ng = esd::kMaxGrid / esd::kGroup + 1;
-    SETUP_HIP(dalloc(&c->red.part, (int64_t)esd::kMaxGrid * esd::kMaxNV));
-    SETUP_HIP(dalloc(&c->red.gpart, (int64_t)ng * esd::kMaxNV));
-    SETUP_HIP(dalloc(&c->red.tick, ng + 1));
-    SETUP_HIP(hipMemsetAsync(c->red.tick, 0, sizeof(unsigned) * (ng + 1), c->stream));
+    SETUP_HIP(dalloc(&c->part_spmv, (int64_t)esd::kMaxGrid * esd::kMaxNV));
+    SETUP_HIP(dalloc(&c->part_upd, (int64_t)esd::kMaxGrid * esd::kMaxNV));
+    SETUP_HIP(dalloc(&c->part_gen, (int64_t)esd::kMaxGrid * esd::kMaxNV));
+    {
+        int64_t cap = esd::grid_red(n, 1);
+        int64_t tot = 0;
+        for (size_t l = 0; l + 1 < c->lvl.size(); ++l) tot += esd::grid_red(c->lvl[l + 1] - c->lvl[l], 1);
+        c->sweep_cap = std::max(cap, tot);
+        SETUP_HIP(dalloc(&c->part_sweep, c->sweep_cap));
+    }
     SETUP_HIP(dalloc(&c->S, 1));
     SETUP_HIP(hipMemsetAsync(c->S, 0, sizeof(Scal), c->stream));
     SETUP_HIP(hipHostMalloc((void **)&c->Sh, sizeof(Scal), hipHostMallocDefault));
@@ -751,6 +863,24 @@ esd_status esd_sample_errors(esd_ctx *c, int32_t m) {
     if (m < 1 || m > c->m_max) return fail(c, ESD_EINVAL, "m must be in [1, m_max]");
     c->m_req = m;
     c->armed = true;
+    return ESD_OK;
+}
+
+esd_status esd_load_samples(esd_ctx *c, const double *X, int32_t k, const double *xN) {
+    if (!c || !X || !xN) return ESD_EINVAL;
+    if (k < 1 || k > c->m_max) return fail(c, ESD_EINVAL, "k must be in [1, m_max]");
+    const int n = (int)c->n;
+    for (int s = 0; s < k; ++s)
+        esd::launch_gather(n, c->p2u, X + (size_t)s * n, c->slots + (size_t)s * n, c->stream);
+    esd::launch_gather(n, c->p2u, xN, c->xN, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->m_req = k;
+    c->slot_iter.resize(k);
+    for (int s = 0; s < k; ++s) c->slot_iter[s] = s + 1;
+    c->nsamples = k;
+    c->have_samples = true;
+    c->armed = false;
     return ESD_OK;
 }
 
@@ -839,7 +969,7 @@ esd_status esd_prec_apply(esd_ctx *c, const double *r, double *z) {
     esd_status st = put_scal(c);
     if (st) return st;
     auto V = vecs<double>(c);
-    launch_prec<double>(c, V, false, false, 0);
+    launch_prec<double>(c, V, false, false);
     esd::launch_scatter(n, c->p2u, c->z, z, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -913,15 +1043,15 @@ esd_status esd_build_aux(esd_ctx *c, double theta, double *ritz, int32_t *m_bar,
         double *v = c->E + (size_t)kept * n;
         // eq. (ek): e = x_1 - x~, normalised, then classical Gram-Schmidt twice
         esd::launch_sub(n, c->xN, c->slots + (size_t)s * n, v, c->stream);
-        esd::launch_dot(n, v, v, &c->S->out, c->S, -1.0, c->red, g, c->stream);
+        dev_norm2(c, v, &c->S->out);
         if ((st = sync_read(c))) return st;
         double nv2 = c->Sh->out;
         if (!(nv2 > 0.0)) continue;
         esd::launch_scale_copy(n, v, v, 1.0 / std::sqrt(nv2), c->stream);
         if (kept > 0) {
             for (int pass = 0; pass < 2; ++pass) {
-                esd::launch_tsdot(n, c->E, kept, v, c->S, c->red, g, c->stream);
-                esd::launch_axpy_cols(n, v, c->E, kept, c->S->svec, -1.0, &c->S->out, c->S, 0, c->red, g, c->stream);
+                dev_tsdot(c, c->E, kept, v, nullptr, 1.0);
+                dev_axpy(c, v, c->E, kept, c->S->svec, -1.0, &c->S->out, 0);
             }
             if ((st = sync_read(c))) return st;
             nv2 = c->Sh->out;

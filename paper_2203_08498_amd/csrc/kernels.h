@@ -7,15 +7,16 @@
 namespace esd {
 
 constexpr int kBlock = 256;     // threads per block of every row kernel
-constexpr int kGroup = 32;      // blocks per first-level reduction group
 constexpr int kMaxGrid = 2048;  // largest grid of a reducing kernel
 constexpr int kMaxNV = 72;      // largest number of values reduced together
+constexpr int kFinThreads = 1024; // threads of a finalize kernel
+constexpr int kPartBudget = 48 * 1024; // doubles a finalize kernel reads at most
 
 // Solver scalars kept in device memory; every per-iteration quantity (rho,
-// alpha, beta, the coarse vectors) is produced and consumed on the device.
+// alpha, beta, the coarse vectors, the stop decision) is produced and
+// consumed on the device.
 struct Scal {
     double rho;      // (r, z) of the current preconditioned residual
-    double rho_acc;  // partial (r, z) summed over the sweep launches of one application
     double alpha, beta;
     double rr;       // ||r||^2 of the recurrence residual
     double tol2;     // tol^2 ||b||^2
@@ -35,25 +36,23 @@ struct Scal {
     double svec[64]; // last tall-skinny product W^T v
 };
 
-struct Red {
-    double *part;   // [grid][kMaxNV]
-    double *gpart;  // [grid / kGroup][kMaxNV]
-    unsigned *tick; // [1 + grid / kGroup]
-};
-
 template <typename T> struct Ell {
     const int64_t *sptr;
     const int32_t *col;
     const T *val;
 };
 
+// Reducing kernels write one row of `stride` doubles per block to `part`
+// (plain stores; the kernel boundary publishes them to every XCD), and a
+// one-block finalize kernel sums the rows in a fixed order.
+
 // one iteration's SpMV: p_new = z + beta p_old (p_new = z on the first
-// iteration), q = A p_new, (p_new, q), W^T q -> mu -> alpha; optional power
-// iterate v_new = A v_old / ||v_old||; optional sampling store of the iterate.
+// iteration), q = A p_new; partials (p_new, q), W^T q, ||v_new||^2; optional
+// power iterate v_new = A v_old / ||v_old||; optional sampling store.
 template <typename T> struct SpmvIt {
     int n;
     Scal *S;
-    Red red;
+    double *part;
     Ell<T> A;
     const T *z, *pold;
     T *pnew, *q;
@@ -61,9 +60,6 @@ template <typename T> struct SpmvIt {
     T *vnew;
     const T *W;
     int m;
-    const double *Cinv;
-    double *hist_alpha;
-    int hist_base;
     const int32_t *slot_table;
     int sample_base;
     double *slots;
@@ -73,34 +69,67 @@ template <typename T> struct SpmvIt {
 };
 
 // x += alpha p; r -= alpha w with w = q (plain, SC) or q - AW mu (deflated);
-// ||r||^2; W^T r -> u for subspace correction; stop test.
+// partials ||r||^2 and, for subspace correction, W^T r.
 template <typename T> struct UpdIt {
     int n;
     Scal *S;
-    Red red;
+    double *part;
     const T *p, *q;
     T *x, *r;
     const T *AW; // deflated
     const T *W;  // subspace correction
     int m;
-    const double *Cinv;
 };
 
-// one level of the forward (L y = r) or backward (L^T z = y) IC(0) sweep
+// one level of the forward (L y = r) or backward (L^T z = y) IC(0) sweep;
+// launches that finish rows of z write one (r, z) partial per block
 template <typename T> struct Sweep {
     int r0, r1; // physical row range of the level
     int n;
     Scal *S;
-    Red red;
-    Ell<T> M;   // L (forward) or U = L^T (backward)
+    double *part; // this launch's partial slots (one per block)
+    Ell<T> M;     // L (forward) or U = L^T (backward)
     const T *dinv;
     const T *r;
     T *y, *z, *zsc;
     const T *W;
-    int m;      // > 0: subspace correction adds W u to zsc
+    int m;        // > 0: subspace correction adds W u to zsc
+};
+
+// finalize after the SpMV: alpha = rho / ((p,q) - s^T C^{-1} s), mu = C^{-1} s
+struct FinAlpha {
+    Scal *S;
+    const double *part;
+    int nblk, stride, m, power;
+    const double *Cinv;
+    double *hist_alpha;
+    int hist_base;
+};
+// finalize after the preconditioner: stop test on ||r||^2, rho, beta
+struct FinRho {
+    Scal *S;
+    const double *part_upd; // column 0 = ||r||^2 partials
+    int nblk_upd, stride_upd;
+    const double *part_sweep;
+    int nsweep;
     double *hist_beta;
     int hist_base;
-    int final_;   // last launch of this preconditioner application
+    int init; // first preconditioner application of a solve: only rho
+};
+// generic finalize of a per-solve reduction: tot[k] = column sums
+struct FinGen {
+    Scal *S;
+    const double *part;
+    int nblk, stride, ncol;
+    double *out0;     // *out0 = scale0 * tot[0] (optional)
+    double scale0;
+    int check;        // S->rr = tot[0]; S->done = 1 when tot[0] <= S->tol2
+    double settol;    // >= 0: S->bnorm2 = tot[0], S->tol2 = settol^2 tot[0]
+    int vcol0, m;     // columns vcol0 .. vcol0+m-1 form a vector s (m > 0)
+    const double *Cinv;
+    double *coef;     // coef = cscale * C^{-1} s (optional)
+    double cscale;
+    int store_svec;   // S->svec = s
 };
 
 void launch_spmv_it(const SpmvIt<double> &a, int mt, bool power, int grid, hipStream_t s);
@@ -113,34 +142,39 @@ void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
 void launch_copyz(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_copyz(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
+void launch_fin_alpha(const FinAlpha &f, hipStream_t s);
+void launch_fin_u(Scal *S, const double *part, int nblk, int stride, int m, const double *Cinv, hipStream_t s);
+void launch_fin_rho(const FinRho &f, hipStream_t s);
+void launch_fin_gen(const FinGen &f, hipStream_t s);
+// stride of the partial rows of the iteration kernels
+int spmv_stride(int m, bool power);
+int update_stride(int m, int kind);
+// grid of a reducing row kernel over `rows` rows with `stride` partials per block
+int grid_red(int64_t rows, int stride);
 
 // ---- per-solve and setup kernels (FP64 unless stated) ----
+// Each reducing launcher writes partials to `part` with the grid it returns
+// through *nblk; FinGen then reduces them.
 void launch_gather(int n, const int32_t *idx, const double *src, double *dst, hipStream_t s);
 void launch_scatter(int n, const int32_t *idx, const double *src, double *dst, hipStream_t s);
 void launch_fill(int n, double *dst, double v, hipStream_t s);
 void launch_fill(int n, float *dst, float v, hipStream_t s);
-// out = a.b; if tol >= 0 also S->bnorm2 = out, S->tol2 = tol^2 out
-void launch_dot(int n, const double *a, const double *b, double *out, Scal *S, double tol, Red red,
-                int grid, hipStream_t s);
-// t = b - A x (A in FP64); *out = ||t||^2; W^T t -> coef = C^{-1} W^T t when W;
-// check: S->rr = ||t||^2 and S->done = (||t||^2 <= S->tol2)
+// partial x.y (stride 1)
+void launch_dot(int n, const double *a, const double *b, double *part, int *nblk, hipStream_t s);
+// t = b - A x (A in FP64); partials [||t||^2, W^T t] (stride 1 + bucket(m))
 void launch_resid(int n, Ell<double> A, const double *b, const double *x, double *t, const double *W,
-                  int m, const double *Cinv, double *coef, double *out, Scal *S, int check, Red red,
-                  int grid, hipStream_t s);
-// y += sign * M coef (M: n x m column-major); *out = ||y||^2 when out;
-// check as in launch_resid
+                  int m, double *part, int *nblk, int *stride, hipStream_t s);
+// y += sign * M coef (M: n x m column-major); partials ||y||^2 when part != null
 void launch_axpy_cols(int n, double *y, const double *M, int m, const double *coef, double sign,
-                      double *out, Scal *S, int check, Red red, int grid, hipStream_t s);
-// tall-skinny W^T v -> S->svec (and nothing else)
-void launch_tsdot(int n, const double *W, int m, const double *v, Scal *S, Red red, int grid,
+                      double *part, int *nblk, hipStream_t s);
+// partials W^T v (stride bucket(m))
+void launch_tsdot(int n, const double *W, int m, const double *v, double *part, int *nblk, int *stride,
                   hipStream_t s);
-// y = A x (FP64 or FP32 values; FP64 vectors)
+// y = A x (FP64)
 void launch_spmv(int n, Ell<double> A, const double *x, double *y, hipStream_t s);
-// S->lam = (v, A v) * scale^2 with v of type T
-void launch_rayleigh(int n, Ell<double> A, const double *v, double scale2, Scal *S, Red red, int grid,
-                     hipStream_t s);
-void launch_rayleigh(int n, Ell<float> A, const float *v, double scale2, Scal *S, Red red, int grid,
-                     hipStream_t s);
+// partials (v, A v)
+void launch_rayleigh(int n, Ell<double> A, const double *v, double *part, int *nblk, hipStream_t s);
+void launch_rayleigh(int n, Ell<float> A, const float *v, double *part, int *nblk, hipStream_t s);
 // out[k] = scale * sum_j Cinv[k m + j] s[j] (one block)
 void launch_coarse(int m, const double *Cinv, const double *s, double scale, double *out, hipStream_t st);
 // sample store of the iterate (used when a solve stops at maxit)

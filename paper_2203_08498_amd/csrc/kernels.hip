@@ -8,11 +8,12 @@
 // Padding slots point at column n, and every vector that is gathered has a
 // zero at index n.
 //
-// Reductions are deterministic: each block reduces its values with wavefront
-// butterflies and LDS, writes them to a fixed slot, and the last block of
-// each group of 32 (ticket counter) sums its group in slot order; the last
-// group reducer sums the groups in order and runs the kernel's scalar epilogue
-// (alpha, beta, the coarse solve, the stop test) on the device.
+// Reductions are deterministic and need no cross-XCD fences: a reducing kernel
+// reduces its values per block (wavefront butterflies, then LDS in wavefront
+// order) and stores one row of partials per block; the kernel boundary makes
+// them visible to every XCD, and a one-block finalize kernel sums the rows in
+// a fixed order and runs the scalar step (alpha, beta, the coarse solve, the
+// stop test) on the device.
 #include <cfloat>
 
 #include "kernels.h"
@@ -38,16 +39,11 @@ __device__ __forceinline__ Tiles my_tiles(int rows) {
     return {t0, min(nt, t0 + per)};
 }
 
-__device__ __forceinline__ double ld_agent(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Deterministic grid reduction of NV doubles.  Returns true in the one block
-// that holds the totals (in tot[], shared), after a __syncthreads.
+// Block reduction of NV doubles; thread k < NV stores the block total at
+// part[blockIdx.x * stride + k].
 template <int NV>
-__device__ bool reduce_last(double (&v)[NV], const Red &red, double *tot) {
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *part, int stride) {
     __shared__ double lds[kBlock / 64][NV];
-    __shared__ int flag;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -57,52 +53,43 @@ __device__ bool reduce_last(double (&v)[NV], const Red &red, double *tot) {
         if (lane == 0) lds[wid][k] = x;
     }
     __syncthreads();
-    const int G = gridDim.x, b = blockIdx.x;
-    const int g = b / kGroup, ng = (G + kGroup - 1) / kGroup;
-    const int gs = min(kGroup, G - g * kGroup);
     for (int k = threadIdx.x; k < NV; k += kBlock) {
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) s += lds[w][k];
-        red.part[(size_t)b * kMaxNV + k] = s;
+        part[(size_t)blockIdx.x * stride + k] = s;
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) flag = (atomicAdd(&red.tick[1 + g], 1u) == (unsigned)(gs - 1));
-    __syncthreads();
-    if (!flag) return false;
-    __threadfence();
-    for (int k = threadIdx.x; k < NV; k += kBlock) {
-        double s = 0.0;
-        for (int j = 0; j < gs; ++j) s += ld_agent(&red.part[(size_t)(g * kGroup + j) * kMaxNV + k]);
-        red.gpart[(size_t)g * kMaxNV + k] = s;
-    }
-    if (threadIdx.x == 0) red.tick[1 + g] = 0;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) flag = (atomicAdd(&red.tick[0], 1u) == (unsigned)(ng - 1));
-    __syncthreads();
-    if (!flag) return false;
-    __threadfence();
-    for (int k = threadIdx.x; k < NV; k += kBlock) {
-        double s = 0.0;
-        for (int j = 0; j < ng; ++j) s += ld_agent(&red.gpart[(size_t)j * kMaxNV + k]);
-        tot[k] = s;
-    }
-    if (threadIdx.x == 0) red.tick[0] = 0;
-    __syncthreads();
-    return true;
 }
 
-// coef[k] = sum_j Cinv[k m + j] s[j] for k < m (threads k), into dst and sh
-__device__ __forceinline__ void coarse_apply(const double *Cinv, int m, const double *s, double *dst,
-                                             double *sh) {
-    if ((int)threadIdx.x < m) {
-        double acc = 0.0;
-        for (int j = 0; j < m; ++j) acc += Cinv[threadIdx.x * m + j] * s[j];
-        dst[threadIdx.x] = acc;
-        if (sh) sh[threadIdx.x] = acc;
+// Column sums of an nblk x stride partial table, columns [c0, c0 + nc), into
+// tot[0 .. nc) (shared).  Thread t handles column c0 + t % P2 and the rows
+// congruent to t / P2 modulo kFinThreads / P2; the row groups are then added
+// pairwise in a fixed tree.  Must be called by all kFinThreads threads.
+__device__ void fin_colsum(const double *part, int nblk, int stride, int c0, int nc, double *tot) {
+    __shared__ double buf[kFinThreads];
+    int p2 = 1;
+    while (p2 < nc) p2 <<= 1;
+    const int groups = kFinThreads / p2;
+    const int t = threadIdx.x, k = t % p2, g = t / p2;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (k < nc) {
+        int j = g;
+        for (; j + 3 * groups < nblk; j += 4 * groups) {
+            a0 += part[(size_t)j * stride + c0 + k];
+            a1 += part[(size_t)(j + groups) * stride + c0 + k];
+            a2 += part[(size_t)(j + 2 * groups) * stride + c0 + k];
+            a3 += part[(size_t)(j + 3 * groups) * stride + c0 + k];
+        }
+        for (; j < nblk; j += groups) a0 += part[(size_t)j * stride + c0 + k];
     }
+    buf[t] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    for (int h = groups / 2; h >= 1; h >>= 1) {
+        if (g < h) buf[t] += buf[t + h * p2];
+        __syncthreads();
+    }
+    if (t < nc) tot[t] = buf[t];
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------------
@@ -158,23 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
             a.slots[(size_t)slot * n + i] =
                 a.xbase ? a.xbase[i] + a.xscale * (double)a.xit[i] : (double)a.xit[i];
     }
-    __shared__ double tot[NV];
-    if (!reduce_last<NV>(acc, a.red, tot)) return;
-    __shared__ double mus[MT > 0 ? MT : 1];
-    if constexpr (MT > 0) {
-        coarse_apply(a.Cinv, m, tot + 1, S->mu, mus);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        double denom = tot[0];
-        if constexpr (MT > 0)
-            for (int k = 0; k < m; ++k) denom -= tot[1 + k] * mus[k];
-        const double alpha = S->rho / denom;
-        S->alpha = alpha;
-        if (a.hist_alpha) a.hist_alpha[a.hist_base + iter] = alpha;
-        if (!isfinite(alpha)) S->done = 3;
-        if constexpr (POW) S->vscale = 1.0 / sqrt(tot[NV - 1]);
-    }
+    block_partials<NV>(acc, a.part, NV);
 }
 
 // KIND: 0 plain, 1 deflated (w = q - AW mu), 2 subspace correction (W^T r)
@@ -215,50 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
                 if (k < m) acc[1 + k] += (double)a.W[(size_t)k * n + i] * (double)ri;
         }
     }
-    __shared__ double tot[NV];
-    if (!reduce_last<NV>(acc, a.red, tot)) return;
-    if constexpr (KIND == 2) coarse_apply(a.Cinv, m, tot + 1, S->u, nullptr);
-    if (threadIdx.x == 0) {
-        const double rr = tot[0];
-        const int it = S->iter + 1;
-        S->iter = it;
-        S->rr = rr;
-        int d = 0;
-        if (!(rr <= DBL_MAX)) d = 3;
-        else if (rr <= S->tol2) d = 1;
-        else if (it >= S->maxit) d = 2;
-        else if (S->stag_window > 0) {
-            if (rr < 0.81 * S->rr_ref) {
-                S->rr_ref = rr;
-                S->it_ref = it;
-            } else if (it - S->it_ref >= S->stag_window) {
-                d = 4;
-            }
-        }
-        S->done = d;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void finish_rho(const Sweep<T> &a, double (&acc)[1]) {
-    __shared__ double tot[1];
-    if (!reduce_last<1>(acc, a.red, tot)) return;
-    if (threadIdx.x == 0) {
-        Scal *S = a.S;
-        if (!a.final_) {
-            S->rho_acc += tot[0];
-        } else {
-            const double rn = S->rho_acc + tot[0];
-            S->rho_acc = 0.0;
-            if (S->iter > 0) {
-                const double b = rn / S->rho;
-                S->beta = b;
-                if (a.hist_beta) a.hist_beta[a.hist_base + S->iter - 1] = b;
-            }
-            S->rho = rn;
-            if (!isfinite(rn)) S->done = 3;
-        }
-    }
+    block_partials<NV>(acc, a.part, NV);
 }
 
 template <typename T, bool SC>
@@ -301,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(Sweep<T> a) {
             acc[0] += (double)ri * (double)zs;
         }
     }
-    if constexpr (LAST) finish_rho(a, acc);
+    if constexpr (LAST) block_partials<1>(acc, a.part, 1);
 }
 
 template <typename T, bool SC>
@@ -326,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
         if constexpr (SC) a.zsc[i] = zs;
         acc[0] += (double)a.r[i] * (double)zs;
     }
-    finish_rho(a, acc);
+    block_partials<1>(acc, a.part, 1);
 }
 
 // M = I: z = r (+ W u for subspace correction)
@@ -344,7 +272,116 @@ __global__ __launch_bounds__(kBlock) void k_copyz(Sweep<T> a) {
         if constexpr (SC) a.zsc[i] = zs;
         acc[0] += (double)ri * (double)zs;
     }
-    finish_rho(a, acc);
+    block_partials<1>(acc, a.part, 1);
+}
+
+// ------------------------------------------------------------------------
+// finalize kernels (one block of kFinThreads)
+// ------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_alpha(FinAlpha f) {
+    Scal *S = f.S;
+    if (S->done) return;
+    __shared__ double tot[kMaxNV];
+    __shared__ double mus[64];
+    const int ncol = 1 + f.m;
+    fin_colsum(f.part, f.nblk, f.stride, 0, ncol, tot);
+    if (f.power) fin_colsum(f.part, f.nblk, f.stride, f.stride - 1, 1, tot + ncol);
+    const int t = threadIdx.x;
+    if (t < f.m) {
+        double acc = 0.0;
+        for (int j = 0; j < f.m; ++j) acc += f.Cinv[t * f.m + j] * tot[1 + j];
+        mus[t] = acc;
+        S->mu[t] = acc;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double denom = tot[0];
+        for (int k = 0; k < f.m; ++k) denom -= tot[1 + k] * mus[k];
+        const double alpha = S->rho / denom;
+        S->alpha = alpha;
+        if (f.hist_alpha) f.hist_alpha[f.hist_base + S->iter] = alpha;
+        if (!isfinite(alpha)) S->done = 3;
+        if (f.power) S->vscale = 1.0 / sqrt(tot[ncol]);
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_u(Scal *S, const double *part, int nblk, int stride, int m,
+                                                       const double *Cinv) {
+    if (S->done) return;
+    __shared__ double tot[kMaxNV];
+    fin_colsum(part, nblk, stride, 1, m, tot);
+    const int t = threadIdx.x;
+    if (t < m) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += Cinv[t * m + j] * tot[j];
+        S->u[t] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
+    Scal *S = f.S;
+    if (S->done) return;
+    __shared__ double tot[2];
+    fin_colsum(f.part_sweep, f.nsweep, 1, 0, 1, tot + 1);
+    if (!f.init) fin_colsum(f.part_upd, f.nblk_upd, f.stride_upd, 0, 1, tot);
+    if (threadIdx.x == 0) {
+        const double rn = tot[1];
+        if (f.init) {
+            S->rho = rn;
+            if (!isfinite(rn)) S->done = 3;
+            return;
+        }
+        const double rr = tot[0];
+        const int it = S->iter + 1;
+        S->iter = it;
+        S->rr = rr;
+        int d = 0;
+        if (!(rr <= DBL_MAX) || !isfinite(rn)) d = 3;
+        else if (rr <= S->tol2) d = 1;
+        else if (it >= S->maxit) d = 2;
+        else if (S->stag_window > 0) {
+            if (rr < 0.81 * S->rr_ref) {
+                S->rr_ref = rr;
+                S->it_ref = it;
+            } else if (it - S->it_ref >= S->stag_window) {
+                d = 4;
+            }
+        }
+        S->done = d;
+        const double b = rn / S->rho;
+        S->beta = b;
+        if (f.hist_beta) f.hist_beta[f.hist_base + it - 1] = b;
+        S->rho = rn;
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_gen(FinGen f) {
+    Scal *S = f.S;
+    __shared__ double tot[kMaxNV];
+    fin_colsum(f.part, f.nblk, f.stride, 0, f.ncol, tot);
+    const int t = threadIdx.x;
+    if (f.m > 0) {
+        if (t < f.m) {
+            if (f.store_svec) S->svec[t] = tot[f.vcol0 + t];
+            if (f.coef) {
+                double acc = 0.0;
+                for (int j = 0; j < f.m; ++j) acc += f.Cinv[t * f.m + j] * tot[f.vcol0 + j];
+                f.coef[t] = f.cscale * acc;
+            }
+        }
+    }
+    if (t == 0) {
+        if (f.out0) *f.out0 = f.scale0 * tot[0];
+        if (f.check) {
+            S->rr = tot[0];
+            if (tot[0] <= S->tol2) S->done = 1;
+        }
+        if (f.settol >= 0.0) {
+            S->bnorm2 = tot[0];
+            S->tol2 = f.settol * f.settol * tot[0];
+        }
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -384,30 +421,19 @@ __global__ void k_scale_copy(int n, const double *src, double *dst, double scale
     if (i < n) dst[i] = src[i] * scale;
 }
 
-__global__ __launch_bounds__(kBlock) void k_dot(int n, const double *x, const double *y, double *out,
-                                                Scal *S, double tol, Red red) {
+__global__ __launch_bounds__(kBlock) void k_dot(int n, const double *x, const double *y, double *part) {
     double acc[1] = {0.0};
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = t * kBlock + threadIdx.x;
         if (i < n) acc[0] += x[i] * y[i];
     }
-    __shared__ double tot[1];
-    if (!reduce_last<1>(acc, red, tot)) return;
-    if (threadIdx.x == 0) {
-        *out = tot[0];
-        if (tol >= 0.0) {
-            S->bnorm2 = tot[0];
-            S->tol2 = tol * tol * tot[0];
-        }
-    }
+    block_partials<1>(acc, part, 1);
 }
 
 template <int MT>
-__global__ __launch_bounds__(kBlock) void k_resid(int n, Ell<double> A, const double *b,
-                                                  const double *x, double *t, const double *W, int m,
-                                                  const double *Cinv, double *coef, double *out,
-                                                  Scal *S, int check, Red red) {
+__global__ __launch_bounds__(kBlock) void k_resid(int n, Ell<double> A, const double *b, const double *x,
+                                                  double *t, const double *W, int m, double *part) {
     constexpr int NV = 1 + MT;
     double acc[NV];
 #pragma unroll
@@ -433,25 +459,12 @@ __global__ __launch_bounds__(kBlock) void k_resid(int n, Ell<double> A, const do
                 if (k < m) acc[1 + k] += W[(size_t)k * n + i] * ri;
         }
     }
-    __shared__ double tot[NV];
-    if (!reduce_last<NV>(acc, red, tot)) return;
-    if constexpr (MT > 0) {
-        if ((int)threadIdx.x < m) S->svec[threadIdx.x] = tot[1 + threadIdx.x];
-        if (coef) coarse_apply(Cinv, m, tot + 1, coef, nullptr);
-    }
-    if (threadIdx.x == 0) {
-        if (out) *out = tot[0];
-        if (check) {
-            S->rr = tot[0];
-            if (tot[0] <= S->tol2) S->done = 1;
-        }
-    }
+    block_partials<NV>(acc, part, NV);
 }
 
-template <int MT>
+template <int MT, bool RED>
 __global__ __launch_bounds__(kBlock) void k_axpy_cols(int n, double *y, const double *M, int m,
-                                                      const double *coef, double sign, double *out,
-                                                      Scal *S, int check, Red red) {
+                                                      const double *coef, double sign, double *part) {
     double acc[1] = {0.0};
     double c[MT];
 #pragma unroll
@@ -467,21 +480,11 @@ __global__ __launch_bounds__(kBlock) void k_axpy_cols(int n, double *y, const do
         y[i] = s;
         acc[0] += s * s;
     }
-    if (!out && !check) return;
-    __shared__ double tot[1];
-    if (!reduce_last<1>(acc, red, tot)) return;
-    if (threadIdx.x == 0) {
-        if (out) *out = tot[0];
-        if (check) {
-            S->rr = tot[0];
-            if (tot[0] <= S->tol2) S->done = 1;
-        }
-    }
+    if constexpr (RED) block_partials<1>(acc, part, 1);
 }
 
 template <int MT>
-__global__ __launch_bounds__(kBlock) void k_tsdot(int n, const double *W, int m, const double *v,
-                                                  Scal *S, Red red) {
+__global__ __launch_bounds__(kBlock) void k_tsdot(int n, const double *W, int m, const double *v, double *part) {
     double acc[MT];
 #pragma unroll
     for (int k = 0; k < MT; ++k) acc[k] = 0.0;
@@ -494,9 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_tsdot(int n, const double *W, int m,
         for (int k = 0; k < MT; ++k)
             if (k < m) acc[k] += W[(size_t)k * n + i] * vi;
     }
-    __shared__ double tot[MT];
-    if (!reduce_last<MT>(acc, red, tot)) return;
-    if ((int)threadIdx.x < m) S->svec[threadIdx.x] = tot[threadIdx.x];
+    block_partials<MT>(acc, part, MT);
 }
 
 __global__ __launch_bounds__(kBlock) void k_spmv(int n, Ell<double> A, const double *x, double *y) {
@@ -514,8 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, Ell<double> A, const dou
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_rayleigh(int n, Ell<T> A, const T *v, double scale2, Scal *S,
-                                                     Red red) {
+__global__ __launch_bounds__(kBlock) void k_rayleigh(int n, Ell<T> A, const T *v, double *part) {
     double acc[1] = {0.0};
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
@@ -531,9 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_rayleigh(int n, Ell<T> A, const T *v
         }
         acc[0] += (double)v[i] * s;
     }
-    __shared__ double tot[1];
-    if (!reduce_last<1>(acc, red, tot)) return;
-    if (threadIdx.x == 0) S->lam = tot[0] * scale2;
+    block_partials<1>(acc, part, 1);
 }
 
 __global__ void k_coarse(int m, const double *Cinv, const double *s, double scale, double *out) {
@@ -640,7 +638,8 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // Block partial of G = E^T F (E: n x ma, F: n x mb, column-major, ma, mb <= 64)
 // with the FP64 matrix cores.  v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16]
-// and B[l/16][l%16]; the 4 accumulator values of lane l are D[4(l/16)+r][l%16].
+// and B[l/16][l%16]; accumulator value r of lane l is D[l/16 + 4r][l%16]
+// (checked on gfx950 with an in-bounds layout probe).
 // Each of the 4 wavefronts owns up to 4 of the 16 output tiles.
 __global__ __launch_bounds__(256) void k_gram_part(int n, const double *E, int ma, const double *F, int mb,
                                                    double *part) {
@@ -675,7 +674,7 @@ __global__ __launch_bounds__(256) void k_gram_part(int n, const double *E, int m
         const int a0 = (tile / tb) * 16, b0 = (tile % tb) * 16;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-            const int ii = a0 + 4 * lk + rr, jj = b0 + li;
+            const int ii = a0 + lk + 4 * rr, jj = b0 + li;
             out[ii * 64 + jj] = acc[q][rr];
         }
     }
@@ -740,6 +739,15 @@ inline int mt_bucket(int m) {
     default: { constexpr int MTV = 64; CALL; } break;                                              \
     }
 
+int spmv_stride(int m, bool power) { return 1 + (m > 0 ? mt_bucket(m) : 0) + (power ? 1 : 0); }
+int update_stride(int m, int kind) { return 1 + (kind == 2 ? mt_bucket(m) : 0); }
+int grid_red(int64_t rows, int stride) {
+    int g = grid_for(rows);
+    const int cap = kPartBudget / stride;
+    if (g > cap) g = cap / 8 * 8;
+    return g < 1 ? 1 : g;
+}
+
 template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, int mt, bool power, int grid, hipStream_t s) {
     if (power) {
         ESD_MT_SWITCH(mt, (k_spmv_it<T, MTV, true><<<grid, kBlock, 0, s>>>(a)));
@@ -792,6 +800,13 @@ template <typename T> static void copyz_impl(const Sweep<T> &a, bool sc, int gri
 void launch_copyz(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { copyz_impl(a, sc, grid, s); }
 void launch_copyz(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { copyz_impl(a, sc, grid, s); }
 
+void launch_fin_alpha(const FinAlpha &f, hipStream_t s) { k_fin_alpha<<<1, kFinThreads, 0, s>>>(f); }
+void launch_fin_u(Scal *S, const double *part, int nblk, int stride, int m, const double *Cinv, hipStream_t s) {
+    k_fin_u<<<1, kFinThreads, 0, s>>>(S, part, nblk, stride, m, Cinv);
+}
+void launch_fin_rho(const FinRho &f, hipStream_t s) { k_fin_rho<<<1, kFinThreads, 0, s>>>(f); }
+void launch_fin_gen(const FinGen &f, hipStream_t s) { k_fin_gen<<<1, kFinThreads, 0, s>>>(f); }
+
 void launch_gather(int n, const int32_t *idx, const double *src, double *dst, hipStream_t s) {
     k_gather<<<blocks(n), kBlock, 0, s>>>(n, idx, src, dst);
 }
@@ -800,34 +815,50 @@ void launch_scatter(int n, const int32_t *idx, const double *src, double *dst, h
 }
 void launch_fill(int n, double *dst, double v, hipStream_t s) { k_fill<double><<<blocks(n), kBlock, 0, s>>>(n, dst, v); }
 void launch_fill(int n, float *dst, float v, hipStream_t s) { k_fill<float><<<blocks(n), kBlock, 0, s>>>(n, dst, v); }
-void launch_dot(int n, const double *a, const double *b, double *out, Scal *S, double tol, Red red, int grid,
-                hipStream_t s) {
-    k_dot<<<grid, kBlock, 0, s>>>(n, a, b, out, S, tol, red);
+void launch_dot(int n, const double *a, const double *b, double *part, int *nblk, hipStream_t s) {
+    const int g = grid_red(n, 1);
+    k_dot<<<g, kBlock, 0, s>>>(n, a, b, part);
+    *nblk = g;
 }
 void launch_resid(int n, Ell<double> A, const double *b, const double *x, double *t, const double *W, int m,
-                  const double *Cinv, double *coef, double *out, Scal *S, int check, Red red, int grid,
-                  hipStream_t s) {
+                  double *part, int *nblk, int *stride, hipStream_t s) {
     if (!W) m = 0;
-    ESD_MT_SWITCH(m, (k_resid<MTV><<<grid, kBlock, 0, s>>>(n, A, b, x, t, W, m, Cinv, coef, out, S, check, red)));
+    const int st = 1 + (m > 0 ? mt_bucket(m) : 0);
+    const int g = grid_red(n, st);
+    ESD_MT_SWITCH(m, (k_resid<MTV><<<g, kBlock, 0, s>>>(n, A, b, x, t, W, m, part)));
+    *nblk = g;
+    *stride = st;
 }
-void launch_axpy_cols(int n, double *y, const double *M, int m, const double *coef, double sign, double *out,
-                      Scal *S, int check, Red red, int grid, hipStream_t s) {
-    ESD_MT_SWITCH(m, (k_axpy_cols<(MTV > 0 ? MTV : 8)><<<grid, kBlock, 0, s>>>(n, y, M, m, coef, sign, out, S,
-                                                                              check, red)));
+void launch_axpy_cols(int n, double *y, const double *M, int m, const double *coef, double sign, double *part,
+                      int *nblk, hipStream_t s) {
+    const int g = grid_red(n, 1);
+    if (part) {
+        ESD_MT_SWITCH(m, (k_axpy_cols<(MTV > 0 ? MTV : 8), true><<<g, kBlock, 0, s>>>(n, y, M, m, coef, sign, part)));
+    } else {
+        ESD_MT_SWITCH(m, (k_axpy_cols<(MTV > 0 ? MTV : 8), false><<<g, kBlock, 0, s>>>(n, y, M, m, coef, sign, part)));
+    }
+    if (nblk) *nblk = g;
 }
-void launch_tsdot(int n, const double *W, int m, const double *v, Scal *S, Red red, int grid, hipStream_t s) {
-    ESD_MT_SWITCH(m, (k_tsdot<(MTV > 0 ? MTV : 8)><<<grid, kBlock, 0, s>>>(n, W, m, v, S, red)));
+void launch_tsdot(int n, const double *W, int m, const double *v, double *part, int *nblk, int *stride,
+                  hipStream_t s) {
+    const int st = mt_bucket(m) > 0 ? mt_bucket(m) : 8;
+    const int g = grid_red(n, st);
+    ESD_MT_SWITCH(m, (k_tsdot<(MTV > 0 ? MTV : 8)><<<g, kBlock, 0, s>>>(n, W, m, v, part)));
+    *nblk = g;
+    *stride = st;
 }
 void launch_spmv(int n, Ell<double> A, const double *x, double *y, hipStream_t s) {
     k_spmv<<<blocks(n), kBlock, 0, s>>>(n, A, x, y);
 }
-void launch_rayleigh(int n, Ell<double> A, const double *v, double scale2, Scal *S, Red red, int grid,
-                     hipStream_t s) {
-    k_rayleigh<double><<<grid, kBlock, 0, s>>>(n, A, v, scale2, S, red);
+void launch_rayleigh(int n, Ell<double> A, const double *v, double *part, int *nblk, hipStream_t s) {
+    const int g = grid_red(n, 1);
+    k_rayleigh<double><<<g, kBlock, 0, s>>>(n, A, v, part);
+    *nblk = g;
 }
-void launch_rayleigh(int n, Ell<float> A, const float *v, double scale2, Scal *S, Red red, int grid,
-                     hipStream_t s) {
-    k_rayleigh<float><<<grid, kBlock, 0, s>>>(n, A, v, scale2, S, red);
+void launch_rayleigh(int n, Ell<float> A, const float *v, double *part, int *nblk, hipStream_t s) {
+    const int g = grid_red(n, 1);
+    k_rayleigh<float><<<g, kBlock, 0, s>>>(n, A, v, part);
+    *nblk = g;
 }
 void launch_coarse(int m, const double *Cinv, const double *s, double scale, double *out, hipStream_t st) {
     if (m > 0) k_coarse<<<1, 64, 0, st>>>(m, Cinv, s, scale, out);

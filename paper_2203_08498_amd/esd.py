@@ -35,7 +35,7 @@ class EsdInfo(C.Structure):
 
 
 EXPORTS = [
-    "esd_setup", "esd_factor_ic0", "esd_sample_errors", "esd_build_aux", "esd_set_aux", "esd_get_aux",
+    "esd_setup", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
     "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_grad_values", "esd_spmv",
     "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag", "esd_get_history", "esd_get_samples",
     "esd_get_layout", "esd_get_timing", "esd_status_string", "esd_last_error", "esd_destroy",
@@ -57,6 +57,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_setup.argtypes = [C.POINTER(P), P, i64, P, P, P, P, i32]
     L.esd_factor_ic0.argtypes = [P]
     L.esd_sample_errors.argtypes = [P, i32]
+    L.esd_load_samples.argtypes = [P, P, i32, P]
     L.esd_build_aux.argtypes = [P, dbl, P, P, P]
     L.esd_set_aux.argtypes = [P, P, i32]
     L.esd_get_aux.argtypes = [P, P, P]
@@ -77,7 +78,8 @@ def load_library(path: str = LIB_PATH):
     L.esd_last_error.argtypes = [P]
     L.esd_last_error.restype = C.c_char_p
     L.esd_destroy.argtypes = [P]
-    for name in ("esd_setup", "esd_factor_ic0", "esd_sample_errors", "esd_build_aux", "esd_set_aux",
+    for name in ("esd_setup", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
+                 "esd_set_aux",
                  "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve",
                  "esd_grad_values", "esd_spmv", "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag",
                  "esd_get_history", "esd_get_samples", "esd_get_layout", "esd_get_timing"):
@@ -171,6 +173,13 @@ class Solver:
         st = self.L.esd_sample_errors(self.h, int(m))
         if st != 0:
             raise EsdError(st, self.L.esd_last_error(self.h).decode())
+
+    def load_samples(self, X, xN):
+        """X: n x k approximate solutions (as sampled at iterations 1..k), xN: final solution."""
+        X = self._vec(X)
+        Xc = X.t().contiguous()
+        xN = self._vec(xN)
+        self._check(self.L.esd_load_samples(self.h, _dptr(Xc), int(X.shape[1]), _dptr(xN)))
 
     def build_aux(self, theta: float):
         ritz = np.zeros(max(self.m_max, 1))
