@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark: time-to-solution per system of a sequence of SPD systems sharing
+one matrix, deflated (error-vector sampling) versus plain ICCG, on one MI355X.
+
+Workload (default): 3-D 7-point FV diffusion on 128^3 cells, lognormal
+coefficients (sigma = 2) with 16 low-conductivity spheres (radius 6, contrast
+1e-5), diagonal scaling, 8 parity colours, IC(0); a sequence of 10 systems
+b_k = f + 0.1 x_{k-1}; m = 16 sampled vectors, theta = 1e-3; FP64; relative
+residual 1e-8.  All inputs are seeded and synthetic.
+
+One step = factor_ic0 + the whole sequence: system 1 is plain ICCG with
+sampling method A and the power iteration, then build_aux (error vectors,
+Gram-Schmidt, Rayleigh-Ritz, W, C = W^T A W), then systems 2..10 deflated.
+`value` = mean seconds per system of that step (sampling and build included).
+The same sequence solved with plain ICCG throughout is timed beside it.
+
+Roofline: the dominant kernel is the per-iteration SpMV launch; its duration
+is measured with hipEvents on the solver's stream around every executed
+launch in the timed steps.  cpu_baseline: the FP64 C oracle, one thread.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=128, help="grid cells per axis")
+    ap.add_argument("--systems", type=int, default=10)
+    ap.add_argument("--m", type=int, default=16)
+    ap.add_argument("--theta", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-iters", type=int, default=30)
+    return ap.parse_args()
+
+
+def run_sequence(s, p, args, mode, esd, P, timing):
+    """One step: factor + the whole sequence; returns per-system records."""
+    import torch
+
+    flags_t = esd.FLAG_TIMING_SPMV if timing else 0
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.factor_ic0()
+    x = None
+    spmv_ms, spmv_n = 0.0, 0
+    f = torch.as_tensor(p.f, device=s.device)
+    for k in range(args.systems):
+        bt = s.sequence_rhs(f, x, 0.1)
+        if k == 0 and mode != esd.PLAIN:
+            s.sample_errors(args.m)
+            x, info = s.solve(bt, tol=args.tol, maxit=20000, flags=esd.FLAG_POWER | flags_t)
+            tb = time.perf_counter()
+            st, ritz, mb, mt = s.build_aux(args.theta)
+            info["build_aux_s"] = time.perf_counter() - tb
+            info["m_bar"], info["m_tilde_built"] = mb, mt
+            info["ritz_min"] = float(ritz[0]) if len(ritz) else 0.0
+        else:
+            x, info = s.solve(bt, tol=args.tol, maxit=20000, mode=mode, flags=esd.FLAG_POWER | flags_t)
+        if timing:
+            tm = s.timing()
+            spmv_ms += tm["spmv_ms"] * tm["iters"]
+            spmv_n += tm["iters"]
+        recs.append(info)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return recs, wall, spmv_ms, spmv_n
+
+
+def cpu_baseline(p, args, mt, iters_per_system):
+    """Oracle (plain C, 1 thread): a bounded number of deflated PCG iterations
+    on the same matrix with a seeded random W of the same width."""
+    import numpy as np
+
+    import oracle as O
+
+    o = O.Oracle.from_problem(p)
+    t0 = time.perf_counter()
+    o.factor_ic0()
+    t_fac = time.perf_counter() - t0
+    k = max(mt, 1)
+    W = np.random.default_rng([2, 9]).standard_normal((p.n, k))
+    W, _ = np.linalg.qr(W)
+    o.set_aux(W)
+    t0 = time.perf_counter()
+    o.solve(p.f, tol=0.0, maxit=args.cpu_iters, mode=O.DEFLATED if mt > 0 else O.PLAIN)
+    t_it = (time.perf_counter() - t0) / args.cpu_iters
+    return {
+        "value": t_it * iters_per_system,
+        "unit": "s/system",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "FP64 C oracle, 1 thread: %d deflated PCG iterations (m_tilde=%d, seeded random W) on the "
+                  "same %d-row matrix, %.3f s/iteration x %.1f iterations per system (mean of this run); "
+                  "IC(0) factor %.2f s not included" % (args.cpu_iters, k, p.n, t_it, iters_per_system, t_fac),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this solver is a single-GPU build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2203_08498_amd import esd, problems as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    p = P.config2(N=args.N, m=args.m, systems=args.systems)
+    print("# workload %s n=%d nnz=%d" % (p.name, p.n, p.nnz), file=sys.stderr, flush=True)
+    s = esd.Solver.from_problem(p, m_max=args.m)
+    s.set_power_start(P.power_start(2, p.n))
+    for _ in range(args.warmup):
+        run_sequence(s, p, args, esd.DEFLATED, esd, P, False)
+        run_sequence(s, p, args, esd.PLAIN, esd, P, False)
+        print("# warmup step done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    walls, walls_plain, spmv_ms, spmv_n = [], [], 0.0, 0
+    recs = recs_plain = None
+    for k in range(args.steps):
+        recs, wall, sm, sn = run_sequence(s, p, args, esd.DEFLATED, esd, P, True)
+        walls.append(wall)
+        spmv_ms += sm
+        spmv_n += sn
+        recs_plain, wall_p, _, _ = run_sequence(s, p, args, esd.PLAIN, esd, P, False)
+        walls_plain.append(wall_p)
+        print("# step %d: deflated %.4f s, plain %.4f s" % (k, wall, wall_p), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = float(np.mean(walls))
+    Tp = float(np.mean(walls_plain))
+    per_sys = T / args.systems
+    per_sys_plain = Tp / args.systems
+    mt = recs[0].get("m_tilde_built", 0)
+    its_defl = [r["iters"] for r in recs[1:]]
+    its_plain = [r["iters"] for r in recs_plain]
+    # roofline of the per-iteration SpMV launch (deflated: W^T q fused in)
+    avg_spmv_s = (spmv_ms / max(spmv_n, 1)) * 1e-3
+    n, nnz = p.n, p.nnz
+    m_used = float(np.mean([r["m_tilde"] for r in recs]))
+    # matrix (8 B value + 4 B index per stored entry), z and p_old read, p and q
+    # written, the power iterate read and written, W read (m_tilde columns)
+    bytes_spmv = 12.0 * nnz + 32.0 * n + 16.0 * n + 8.0 * n * m_used
+    achieved = bytes_spmv / avg_spmv_s / 1e9 if avg_spmv_s > 0 else 0.0
+    out = {
+        "metric": "time-to-solution/system at relres 1e-8, deflated vs plain ICCG; SpMV GB/s",
+        "value": per_sys,
+        "unit": "s/system",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded lognormal-coefficient FV diffusion, config-2 recipe)",
+        "config": {
+            "workload": "fv3d-7pt %d^3, lognormal sigma=2 + 16 spheres r=6 contrast 1e-5, diag-scaled, "
+                        "8 colours, IC(0); %d systems b_k=f+0.1x_(k-1); m=%d theta=%g; deflated ICCG"
+                        % (args.N, args.systems, args.m, args.theta),
+            "n": n, "nnz": nnz, "systems": args.systems, "m": args.m, "theta": args.theta,
+        },
+        "plain_s_per_system": per_sys_plain,
+        "speedup_vs_plain": per_sys_plain / per_sys if per_sys > 0 else None,
+        "iters_deflated_mean": float(np.mean(its_defl)) if its_defl else None,
+        "iters_plain_mean": float(np.mean(its_plain)),
+        "iters_sampling_solve": recs[0]["iters"],
+        "m_tilde": mt,
+        "build_aux_s": recs[0].get("build_aux_s"),
+        "kappa_cg_last": recs[-1]["kappa"],
+        "kappa_es_last": recs[-1]["kappa_es"],
+        "true_relres_max": max(r["true_relres"] for r in recs),
+        "roofline": {
+            "kernel": "k_spmv_it (q = A p with p = z + beta p_old, (p,q), W^T q, power iterate A v)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_spmv,
+            "avg_launch_us": avg_spmv_s * 1e6,
+            "launches": spmv_n,
+        },
+    }
+    if not args.no_cpu:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, args, mt, float(np.mean(its_defl)) if its_defl else its_plain[0])
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -65,6 +65,7 @@ typedef enum {
 #define ESD_FLAG_MIXED 4  /* FP32 inner solves inside an FP64 iterative-refinement loop */
 #define ESD_FLAG_SYNC_EVERY 8 /* check convergence after every iteration (no speculative chunk) */
 #define ESD_FLAG_TIMING 16    /* hipEvents around the SpMV, update and sweep launches of every executed iteration */
+#define ESD_FLAG_TIMING_SPMV 32 /* hipEvents around the SpMV launch of every executed iteration only */
 
 typedef struct {
     int32_t iters;        /* CG iterations (mixed: total inner iterations) */
@@ -158,6 +159,12 @@ esd_status esd_set_mixed_params(esd_ctx *ctx, double inner_tol, int32_t max_oute
  * accelerated mode had no W, ESD_ENOAUX if no aux space was ever built. */
 esd_status esd_solve(esd_ctx *ctx, const double *b, const double *x0, double tol, int32_t maxit,
                      int32_t mode, int32_t flags, double *x, esd_info *info);
+
+/* esd_sequence_rhs - right-hand side of the next system of the sequence
+ * (Sec. 2: b_k depends on the earlier solutions): b = f + c * xprev, with
+ * f(d), xprev(d), b(d) float64[n]; xprev may be NULL (b = f).  Enqueued on
+ * the context's stream. */
+esd_status esd_sequence_rhs(esd_ctx *ctx, const double *f, const double *xprev, double c, double *b);
 
 /* esd_grad_values - gradient of a loss through x = A^{-1} b with respect to
  * every stored value: gval[k] = -lam[row k] * x[col k] in the caller's CSR

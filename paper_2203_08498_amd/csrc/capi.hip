@@ -36,7 +36,7 @@ template <typename T> struct VecSet {
     Ell<T> A, L, U;
 };
 
-constexpr int kFlagTiming = ESD_FLAG_TIMING;
+constexpr int kFlagTiming = ESD_FLAG_TIMING | ESD_FLAG_TIMING_SPMV;
 
 } // namespace
 
@@ -50,6 +50,7 @@ struct esd_ctx {
     std::vector<int32_t> p2u_h, lperm_h;
     DevEll A, L, U;
     int64_t *u_from_l = nullptr;
+    double *l_orig = nullptr; // a_ij of the strictly lower entries (factor input)
     double *adiag = nullptr, *ldiag = nullptr, *dinv = nullptr;
     float *dinv32 = nullptr;
     int32_t *p2u = nullptr;
@@ -295,6 +296,7 @@ struct KrylovOpts {
     bool sampling = false;
     bool sync_every = false;
     bool timing = false;
+    bool timing_all = false;
     int hist_base = 0;
     int sample_base = 0;
     const double *xbase = nullptr;
@@ -359,9 +361,9 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             esd::launch_fin_alpha(fa, c->stream);
             esd::launch_update_it(ua, m, o.kind, gu, c->stream);
             if (sc) esd::launch_fin_u(c->S, c->part_upd, gu, ustride, m, c->Cinv, c->stream);
-            if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 2], c->stream));
+            if (o.timing_all) HIPCHK(hipEventRecord(c->ev[4 * j + 2], c->stream));
             fr.nsweep = launch_prec<T>(c, V, o.noprec, sc);
-            if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 3], c->stream));
+            if (o.timing_all) HIPCHK(hipEventRecord(c->ev[4 * j + 3], c->stream));
             esd::launch_fin_rho(fr, c->stream);
         }
         HIPCHK(hipGetLastError());
@@ -372,8 +374,10 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             for (int j = 0; j < executed; ++j) {
                 float a = 0, b = 0, d = 0;
                 (void)hipEventElapsedTime(&a, c->ev[4 * j + 0], c->ev[4 * j + 1]);
-                (void)hipEventElapsedTime(&b, c->ev[4 * j + 1], c->ev[4 * j + 2]);
-                (void)hipEventElapsedTime(&d, c->ev[4 * j + 2], c->ev[4 * j + 3]);
+                if (o.timing_all) {
+                    (void)hipEventElapsedTime(&b, c->ev[4 * j + 1], c->ev[4 * j + 2]);
+                    (void)hipEventElapsedTime(&d, c->ev[4 * j + 2], c->ev[4 * j + 3]);
+                }
                 c->t_spmv += a; c->t_upd += b; c->t_sweep += d; c->t_count++;
             }
         }
@@ -497,6 +501,7 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
     o.sampling = sampling;
     o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
     o.timing = (flags & kFlagTiming) != 0;
+    o.timing_all = (flags & ESD_FLAG_TIMING) != 0;
     int iters = 0;
     st = krylov<double>(c, V, o, &iters, &c->vb64);
     if (st) return st;
@@ -608,6 +613,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         o.sampling = sampling;
         o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
         o.timing = (flags & kFlagTiming) != 0;
+    o.timing_all = (flags & ESD_FLAG_TIMING) != 0;
         o.hist_base = total;
         o.sample_base = total;
         o.xbase = c->x;
@@ -721,7 +727,7 @@ void esd_destroy(esd_ctx *c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     free_ell(c->A); free_ell(c->L); free_ell(c->U);
-    void *ptrs[] = {c->u_from_l, c->adiag, c->ldiag, c->dinv, c->dinv32, c->p2u, c->urp, c->ucol, c->bad,
+    void *ptrs[] = {c->u_from_l, c->l_orig, c->adiag, c->ldiag, c->dinv, c->dinv32, c->p2u, c->urp, c->ucol, c->bad,
                     c->b, c->x, c->r, c->z, c->zsc, c->y, c->q, c->p[0], c->p[1], c->t, c->v[0], c->v[1],
                     c->r32, c->z32, c->zsc32, c->y32, c->q32, c->p32[0], c->p32[1], c->d32, c->v32[0], c->v32[1],
                     c->part_spmv, c->part_upd, c->part_gen, c->part_sweep, c->S, c->slots, c->slot_table, c->xN,
@@ -766,6 +772,9 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     SETUP_CHK(upload_ell(c, c->A, H.A));
     SETUP_CHK(upload_ell(c, c->L, H.L));
     SETUP_CHK(upload_ell(c, c->U, H.U));
+    SETUP_HIP(dalloc(&c->l_orig, c->L.size));
+    if (c->L.size)
+        SETUP_HIP(hipMemcpyAsync(c->l_orig, c->L.v64, sizeof(double) * c->L.size, hipMemcpyDeviceToDevice, c->stream));
     SETUP_HIP(dalloc(&c->u_from_l, (int64_t)H.u_from_l.size()));
     if (!H.u_from_l.empty())
         SETUP_HIP(hipMemcpyAsync(c->u_from_l, H.u_from_l.data(), sizeof(int64_t) * H.u_from_l.size(),
@@ -836,7 +845,9 @@ esd_status esd_factor_ic0(esd_ctx *c) {
     if (!c) return ESD_EINVAL;
     const int n = (int)c->n;
     HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
-    // L values start as a_ij (uploaded); factor level by level
+    // L values start as a_ij; factor level by level, in place
+    if (c->L.size)
+        HIPCHK(hipMemcpyAsync(c->L.v64, c->l_orig, sizeof(double) * c->L.size, hipMemcpyDeviceToDevice, c->stream));
     const int nl = (int)c->lvl.size() - 1;
     Ell<double> L = c->L.e64();
     for (int l = 0; l < nl; ++l)
@@ -939,6 +950,13 @@ esd_status esd_solve(esd_ctx *c, const double *b, const double *x0, double tol, 
     if (st < 0) return st;
     if (st == ESD_OK && warn != ESD_OK) return warn;
     return st;
+}
+
+esd_status esd_sequence_rhs(esd_ctx *c, const double *f, const double *xprev, double cc, double *b) {
+    if (!c || !f || !b) return ESD_EINVAL;
+    esd::launch_axpby((int)c->n, f, xprev, cc, b, c->stream);
+    HIPCHK(hipGetLastError());
+    return ESD_OK;
 }
 
 esd_status esd_grad_values(esd_ctx *c, const double *lam, const double *x, double *gval) {

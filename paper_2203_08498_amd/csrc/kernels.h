@@ -184,6 +184,8 @@ void launch_cast_scale(int n, const double *src, float *dst, double scale, hipSt
 void launch_cast(int64_t n, const double *src, float *dst, hipStream_t s);
 void launch_add_scaled(int n, double *x, const float *d, double scale, hipStream_t s);
 void launch_sub(int n, const double *a, const double *b, double *dst, hipStream_t s);
+// b = f + c x (x may be null)
+void launch_axpby(int n, const double *f, const double *x, double c, double *b, hipStream_t s);
 void launch_scale_copy(int n, const double *src, double *dst, double scale, hipStream_t s);
 
 // IC(0) factor of one level (FP64, in place on the L values; writes ldiag)

@@ -412,6 +412,10 @@ __global__ void k_add_scaled(int n, double *x, const float *d, double scale) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] += scale * (double)d[i];
 }
+__global__ void k_axpby(int n, const double *f, const double *x, double c, double *b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = x ? f[i] + c * x[i] : f[i];
+}
 __global__ void k_sub(int n, const double *a, const double *b, double *dst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = a[i] - b[i];
@@ -874,6 +878,9 @@ void launch_cast(int64_t n, const double *src, float *dst, hipStream_t s) {
 }
 void launch_add_scaled(int n, double *x, const float *d, double scale, hipStream_t s) {
     k_add_scaled<<<blocks(n), kBlock, 0, s>>>(n, x, d, scale);
+}
+void launch_axpby(int n, const double *f, const double *x, double c, double *b, hipStream_t s) {
+    k_axpby<<<blocks(n), kBlock, 0, s>>>(n, f, x, c, b);
 }
 void launch_sub(int n, const double *a, const double *b, double *dst, hipStream_t s) {
     k_sub<<<blocks(n), kBlock, 0, s>>>(n, a, b, dst);

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesd.so")
 
 PLAIN, DEFLATED, SUBSPACE = 0, 1, 2
-FLAG_NOPREC, FLAG_POWER, FLAG_MIXED, FLAG_SYNC_EVERY, FLAG_TIMING = 1, 2, 4, 8, 16
+FLAG_NOPREC, FLAG_POWER, FLAG_MIXED, FLAG_SYNC_EVERY, FLAG_TIMING, FLAG_TIMING_SPMV = 1, 2, 4, 8, 16, 32
 OK, NOT_CONVERGED, AUX_EMPTY = 0, 1, 2
 EINVAL, ENOTSPD, EHIP, ENUMERIC, ENOAUX, ENOSAMPLES = -1, -2, -3, -4, -5, -6
 
@@ -36,7 +36,7 @@ class EsdInfo(C.Structure):
 
 EXPORTS = [
     "esd_setup", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
-    "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_grad_values", "esd_spmv",
+    "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
     "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag", "esd_get_history", "esd_get_samples",
     "esd_get_layout", "esd_get_timing", "esd_status_string", "esd_last_error", "esd_destroy",
 ]
@@ -64,6 +64,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_set_power_start.argtypes = [P, P]
     L.esd_set_mixed_params.argtypes = [P, dbl, i32]
     L.esd_solve.argtypes = [P, P, P, dbl, i32, i32, i32, P, C.POINTER(EsdInfo)]
+    L.esd_sequence_rhs.argtypes = [P, P, P, dbl, P]
     L.esd_grad_values.argtypes = [P, P, P, P]
     L.esd_spmv.argtypes = [P, P, P]
     L.esd_prec_apply.argtypes = [P, P, P]
@@ -80,7 +81,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_destroy.argtypes = [P]
     for name in ("esd_setup", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
                  "esd_set_aux",
-                 "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve",
+                 "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs",
                  "esd_grad_values", "esd_spmv", "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag",
                  "esd_get_history", "esd_get_samples", "esd_get_layout", "esd_get_timing"):
         getattr(L, name).restype = C.c_int
@@ -231,6 +232,15 @@ class Solver:
         d = info.as_dict()
         d["status"] = st
         return x, d
+
+    def sequence_rhs(self, f, xprev=None, c=0.1, out=None):
+        """b = f + c * xprev on the device (b = f without xprev)."""
+        f = self._vec(f)
+        xprev = None if xprev is None else self._vec(xprev)
+        b = out if out is not None else self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.esd_sequence_rhs(self.h, _dptr(f), None if xprev is None else _dptr(xprev), float(c),
+                                            _dptr(b)))
+        return b
 
     def grad_values(self, lam, x):
         lam, x = self._vec(lam), self._vec(x)

@@ -75,6 +75,13 @@ def test_ic0_factor_diagonal(case):
     assert np.abs(s.factor_diag() - d_user).max() <= 1e-13 * np.abs(d_user).max()
 
 
+def test_refactor_is_idempotent(case):
+    name, p, s, o = case
+    d1 = s.factor_diag()
+    s.factor_ic0()
+    assert np.array_equal(s.factor_diag(), d1)
+
+
 def test_preconditioner(case):
     name, p, s, o = case
     r = np.random.default_rng(2).standard_normal(p.n)
