@@ -62,10 +62,17 @@ typedef enum {
 /* solve flags */
 #define ESD_FLAG_NOPREC 1 /* M = I (unpreconditioned CG), used for closed-form checks */
 #define ESD_FLAG_POWER 2  /* power iteration fused into the SpMV, (q v) = A (p v) (Alg. PCG-con) */
-#define ESD_FLAG_MIXED 4  /* FP32 inner solves inside an FP64 iterative-refinement loop */
+#define ESD_FLAG_MIXED 4  /* FP32 inner solves inside an FP64 iterative-refinement loop; if a
+                             refinement step fails to halve the FP64 residual the solve is
+                             finished by FP64 CG (reported in esd_info.fp64_iters) */
 #define ESD_FLAG_SYNC_EVERY 8 /* check convergence after every iteration (no speculative chunk) */
 #define ESD_FLAG_TIMING 16    /* hipEvents around the SpMV, update and sweep launches of every executed iteration */
 #define ESD_FLAG_TIMING_SPMV 32 /* hipEvents around the SpMV launch of every executed iteration only */
+#define ESD_FLAG_TRUE_RES 64  /* FP64: after the recurrence test, restart from x while the recomputed
+                                 residual misses tol (at most 4 restarts) */
+#define ESD_FLAG_STREAM 128   /* launch every kernel on the stream; by default the iterations run as
+                                 replays of a captured 16-iteration HIP graph, cached in the context
+                                 (timing and ESD_FLAG_SYNC_EVERY solves always use stream launches) */
 
 typedef struct {
     int32_t iters;        /* CG iterations (mixed: total inner iterations) */
@@ -74,6 +81,8 @@ typedef struct {
     int32_t m_tilde;      /* columns of W used by this solve (0 for PLAIN) */
     int32_t nsamples;     /* sampling stores made during this solve */
     int32_t mode_used;    /* ESD_PLAIN if an accelerated mode fell back */
+    int32_t fp64_iters;   /* mixed: iterations finished in FP64 after the FP32 refinement stalled */
+    int32_t reserved;
     double relres;        /* recurrence residual norm / ||b|| at exit */
     double true_relres;   /* ||b - A x||_2 / ||b||_2 recomputed in FP64 */
     double kappa;         /* K1: extreme Lanczos values from the CG alpha/beta */
@@ -100,6 +109,13 @@ typedef struct {
  */
 esd_status esd_setup(esd_ctx **ctx, void *hip_stream, int64_t n, const int64_t *rowptr,
                      const int32_t *col, const double *val, const int32_t *colors, int32_t m_max);
+
+/* esd_update_values - new values val(d) float64[nnz] for the same pattern, in
+ * the caller's CSR order (a slowly varying matrix A_k, Sec. 2; finite-
+ * difference checks).  The IC(0) factor must be recomputed with
+ * esd_factor_ic0 before the next solve; an existing W is kept and AW, C =
+ * W^T A W are recomputed for the new values. */
+esd_status esd_update_values(esd_ctx *ctx, const double *val);
 
 /* esd_factor_ic0 - IC(0) on the stored lower pattern in the chosen order (the
  * paper's IC preconditioner, Sec. 4.4).  FP64 factor plus an FP32 copy.

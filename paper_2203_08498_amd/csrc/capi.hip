@@ -32,7 +32,7 @@ struct DevEll {
 
 template <typename T> struct VecSet {
     T *x, *r, *z, *zsc, *y, *q, *p[2], *v[2];
-    const T *W, *AW, *dinv;
+    const T *W, *AW, *Wrm, *AWrm, *dinv;
     Ell<T> A, L, U;
 };
 
@@ -51,6 +51,7 @@ struct esd_ctx {
     DevEll A, L, U;
     int64_t *u_from_l = nullptr;
     double *l_orig = nullptr; // a_ij of the strictly lower entries (factor input)
+    int32_t *a_src = nullptr, *l_src = nullptr, *d_src = nullptr; // caller-CSR positions
     double *adiag = nullptr, *ldiag = nullptr, *dinv = nullptr;
     float *dinv32 = nullptr;
     int32_t *p2u = nullptr;
@@ -63,7 +64,7 @@ struct esd_ctx {
     // FP32 vectors
     float *r32 = nullptr, *z32 = nullptr, *zsc32 = nullptr, *y32 = nullptr, *q32 = nullptr,
           *p32[2] = {nullptr, nullptr}, *d32 = nullptr, *v32[2] = {nullptr, nullptr};
-    double *part_spmv = nullptr, *part_upd = nullptr, *part_gen = nullptr, *part_sweep = nullptr;
+    double *part_spmv = nullptr, *part_upd = nullptr, *part_gen = nullptr, *part_sweep = nullptr, *part_ts = nullptr;
     int64_t sweep_cap = 0;
     Scal *S = nullptr;
     Scal *Sh = nullptr; // pinned host mirror
@@ -83,6 +84,10 @@ struct esd_ctx {
     int m_bar = 0, m_tilde = 0;
     double *E = nullptr, *AE = nullptr, *W = nullptr, *AW = nullptr;
     float *W32 = nullptr, *AW32 = nullptr;
+    double *W_rm = nullptr;  // row-major copies for the tall-skinny W^T v and (AW)^T v
+    float *W32_rm = nullptr;
+    double *AW_rm = nullptr;
+    float *AW32_rm = nullptr;
     double *Cinv = nullptr, *gram_part = nullptr, *G = nullptr, *Tm = nullptr;
     std::vector<double> Ch, ritz;
     // power iteration state
@@ -99,6 +104,17 @@ struct esd_ctx {
     int max_outer = 30;
     int stag_window = 50;
     bool factored = false;
+    // captured iteration chunks (replayed with hipGraphLaunch), invalidated
+    // whenever a buffer they reference is reallocated or the aux space changes
+    struct GraphEntry {
+        uint32_t key;
+        uint32_t epoch;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    uint32_t epoch = 1;
+    bool use_graphs = true;
+    hipStream_t cap = nullptr; // private stream the chunks are captured on
     // kernel timing
     std::vector<hipEvent_t> ev;
     double t_spmv = 0, t_sweep = 0, t_upd = 0;
@@ -164,7 +180,7 @@ template <> VecSet<double> vecs<double>(esd_ctx *c) {
     VecSet<double> V;
     V.x = c->x; V.r = c->r; V.z = c->z; V.zsc = c->zsc; V.y = c->y; V.q = c->q;
     V.p[0] = c->p[0]; V.p[1] = c->p[1]; V.v[0] = c->v[0]; V.v[1] = c->v[1];
-    V.W = c->W; V.AW = c->AW; V.dinv = c->dinv;
+    V.W = c->W; V.AW = c->AW; V.Wrm = c->W_rm; V.AWrm = c->AW_rm; V.dinv = c->dinv;
     V.A = c->A.e64(); V.L = c->L.e64(); V.U = c->U.e64();
     return V;
 }
@@ -172,7 +188,7 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
     VecSet<float> V;
     V.x = c->d32; V.r = c->r32; V.z = c->z32; V.zsc = c->zsc32; V.y = c->y32; V.q = c->q32;
     V.p[0] = c->p32[0]; V.p[1] = c->p32[1]; V.v[0] = c->v32[0]; V.v[1] = c->v32[1];
-    V.W = c->W32; V.AW = c->AW32; V.dinv = c->dinv32;
+    V.W = c->W32; V.AW = c->AW32; V.Wrm = c->W32_rm; V.AWrm = c->AW32_rm; V.dinv = c->dinv32;
     V.A = c->A.e32(); V.L = c->L.e32(); V.U = c->U.e32();
     return V;
 }
@@ -181,7 +197,7 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
 // coarse term W u is added into zsc.  Every launch that finishes rows of z
 // writes one (r, z) partial per block; returns the number of partial slots.
 template <typename T>
-int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc) {
+int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_l0 = false) {
     esd::Sweep<T> s{};
     s.n = (int)c->n;
     s.S = c->S;
@@ -202,7 +218,7 @@ int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc) {
     int off = 0;
     const int nl = (int)c->lvl.size() - 1;
     s.M = V.L;
-    for (int l = 0; l < nl; ++l) {
+    for (int l = (skip_l0 && nl >= 2) ? 1 : 0; l < nl; ++l) {
         s.r0 = (int)c->lvl[l]; s.r1 = (int)c->lvl[l + 1];
         const bool last = (l == nl - 1);
         const int g = esd::grid_red(s.r1 - s.r0, 1);
@@ -295,95 +311,172 @@ struct KrylovOpts {
     bool power = false;
     bool sampling = false;
     bool sync_every = false;
+    bool stream_only = false;
     bool timing = false;
     bool timing_all = false;
-    int hist_base = 0;
-    int sample_base = 0;
-    const double *xbase = nullptr;
-    double xscale = 1.0;
+    const double *xbase = nullptr; // mixed inner solves sample xbase + S.xscale * iterate
 };
 
 // Runs the CG loop from the state prepared by the caller (x, r, S with
 // tol2/maxit/done set; u = C^{-1} W^T r for subspace correction).  Returns the
 // number of completed iterations through *iters and the exit code in Sh->done.
+//
+// Deflation iterates with projected directions: after the preconditioner,
+// zhat = P z = z - W C^{-1} (AW)^T z, p = zhat + beta p, q = A p; then
+// (p, q) = (p, P^T A p) without cancellation and r -= alpha q is the deflated
+// residual update of the deflated PCG (P^T A = A P for symmetric A).  The
+// range(W) part of x is fixed by the final correction.
 template <typename T>
 esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iters, int *vbase) {
     const int n = (int)c->n;
     const int m = (o.kind != 0) ? c->m_tilde : 0;
-    const bool sc = (o.kind == 2);
-    // z_0 = M^{-1} r_0 (+ W u), rho_0
+    const bool sc = (o.kind == 2), defl = (o.kind == 1);
+    const int gt = m > 0 ? esd::tsdot_grid(n, m) : 1;
+    const int st_t = m > 0 ? esd::tsdot_stride(m) : 1;
+    const int gn = esd::grid_red(n, 1);
+    // tall-skinny (AW)^T z (deflation) or W^T r (subspace correction)
+    esd::TsDot<T> ta{};
+    ta.n = n; ta.m = m; ta.Wrm = defl ? V.AWrm : V.Wrm; ta.v = defl ? V.z : V.r; ta.part = c->part_ts; ta.S = c->S;
+    esd::Proj<T> pa{};
+    pa.n = n; pa.m = m; pa.S = c->S; pa.z = V.z; pa.W = V.W; pa.zhat = V.zsc;
+    // z_0 = M^{-1} r_0 (+ W u), rho_0 (and zhat_0 for deflation)
     {
         const int ns = launch_prec<T>(c, V, o.noprec, sc);
+        if (defl) esd::launch_tsdot_rm(ta, gt, c->stream);
         esd::FinRho fr{};
         fr.S = c->S; fr.part_sweep = c->part_sweep; fr.nsweep = ns; fr.init = 1;
+        fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
         esd::launch_fin_rho(fr, c->stream);
+        if (defl) esd::launch_proj(pa, gn, c->stream);
     }
-    const int ms = (o.kind == 1) ? m : 0;
-    const int sstride = esd::spmv_stride(ms, o.power);
+    const int sstride = esd::spmv_stride(o.power);
     const int gs = esd::grid_red(n, sstride);
-    const int ustride = esd::update_stride(m, o.kind);
-    const int gu = esd::grid_red(n, ustride);
+    const int gu = esd::grid_red(n, 1);
+    const int nl = (int)c->lvl.size() - 1;
+    const bool fuse_l0 = !o.noprec && nl >= 2;
     esd::SpmvIt<T> sa{};
     sa.n = n; sa.S = c->S; sa.part = c->part_spmv; sa.A = V.A;
-    sa.z = sc ? V.zsc : V.z;
-    sa.W = (o.kind == 1) ? V.W : nullptr;
-    sa.m = ms;
+    sa.z = (sc || defl) ? V.zsc : V.z;
     sa.slot_table = o.sampling ? c->slot_table : nullptr;
-    sa.sample_base = o.sample_base;
     sa.slots = c->slots;
     sa.xit = V.x;
     sa.xbase = o.xbase;
-    sa.xscale = o.xscale;
     sa.q = V.q;
     esd::FinAlpha fa{};
-    fa.S = c->S; fa.part = c->part_spmv; fa.nblk = gs; fa.stride = sstride; fa.m = ms; fa.power = o.power;
-    fa.Cinv = c->Cinv; fa.hist_alpha = c->ha; fa.hist_base = o.hist_base;
+    fa.S = c->S; fa.part = c->part_spmv; fa.nblk = gs; fa.stride = sstride; fa.power = o.power;
+    fa.part_s = c->part_ts; fa.nblk_s = gt; fa.stride_s = st_t; fa.m = 0;
+    fa.Cinv = c->Cinv; fa.hist_alpha = c->ha;
     esd::UpdIt<T> ua{};
     ua.n = n; ua.S = c->S; ua.part = c->part_upd; ua.q = V.q; ua.x = V.x; ua.r = V.r;
-    ua.AW = V.AW; ua.W = V.W; ua.m = m;
+    ua.AW = V.AW; ua.m = 0;
+    ua.l0 = fuse_l0 ? (int)c->lvl[1] : 0; ua.dinv = V.dinv; ua.y = V.y;
     esd::FinRho fr{};
-    fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = ustride;
-    fr.part_sweep = c->part_sweep; fr.hist_beta = c->hb; fr.hist_base = o.hist_base; fr.init = 0;
-    int launched = 0;
-    int chunk = o.sync_every ? 1 : 8;
+    fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = 1;
+    fr.part_sweep = c->part_sweep; fr.hist_beta = c->hb; fr.init = 0;
+    fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
     const bool timing = o.timing;
-    for (;;) {
-        for (int j = 0; j < chunk; ++j) {
-            const int it = launched + j;
+    // one chunk of iterations; `it0` must be even so that a replay of the
+    // chunk reuses the same ping-pong buffers
+    auto body = [&](int it0, int count) -> hipError_t {
+        for (int j = 0; j < count; ++j) {
+            const int it = it0 + j;
             sa.pold = V.p[it & 1];
             sa.pnew = V.p[(it + 1) & 1];
             sa.vold = V.v[(*vbase + it) & 1];
             sa.vnew = V.v[(*vbase + it + 1) & 1];
             ua.p = V.p[(it + 1) & 1];
-            if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 0], c->stream));
-            esd::launch_spmv_it(sa, ms, o.power, gs, c->stream);
-            if (timing) HIPCHK(hipEventRecord(c->ev[4 * j + 1], c->stream));
+            hipError_t e;
+            if (timing && (e = hipEventRecord(c->ev[4 * j + 0], c->stream)) != hipSuccess) return e;
+            esd::launch_spmv_it(sa, o.power, gs, c->stream);
+            if (timing && (e = hipEventRecord(c->ev[4 * j + 1], c->stream)) != hipSuccess) return e;
             esd::launch_fin_alpha(fa, c->stream);
-            esd::launch_update_it(ua, m, o.kind, gu, c->stream);
-            if (sc) esd::launch_fin_u(c->S, c->part_upd, gu, ustride, m, c->Cinv, c->stream);
-            if (o.timing_all) HIPCHK(hipEventRecord(c->ev[4 * j + 2], c->stream));
-            fr.nsweep = launch_prec<T>(c, V, o.noprec, sc);
-            if (o.timing_all) HIPCHK(hipEventRecord(c->ev[4 * j + 3], c->stream));
+            esd::launch_update_it(ua, 0, gu, c->stream);
+            if (sc) {
+                esd::launch_tsdot_rm(ta, gt, c->stream);
+                esd::launch_fin_u(c->S, c->part_ts, gt, st_t, m, c->Cinv, c->stream);
+            }
+            if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 2], c->stream)) != hipSuccess) return e;
+            fr.nsweep = launch_prec<T>(c, V, o.noprec, sc, fuse_l0);
+            if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 3], c->stream)) != hipSuccess) return e;
+            if (defl) esd::launch_tsdot_rm(ta, gt, c->stream);
             esd::launch_fin_rho(fr, c->stream);
+            if (defl) esd::launch_proj(pa, gn, c->stream);
         }
-        HIPCHK(hipGetLastError());
-        esd_status st = sync_read(c);
-        if (st != ESD_OK) return st;
-        if (timing) {
-            const int executed = std::min(chunk, std::max(0, c->Sh->iter - launched));
-            for (int j = 0; j < executed; ++j) {
-                float a = 0, b = 0, d = 0;
-                (void)hipEventElapsedTime(&a, c->ev[4 * j + 0], c->ev[4 * j + 1]);
-                if (o.timing_all) {
-                    (void)hipEventElapsedTime(&b, c->ev[4 * j + 1], c->ev[4 * j + 2]);
-                    (void)hipEventElapsedTime(&d, c->ev[4 * j + 2], c->ev[4 * j + 3]);
-                }
-                c->t_spmv += a; c->t_upd += b; c->t_sweep += d; c->t_count++;
+        return hipGetLastError();
+    };
+    auto harvest = [&](int launched, int chunk) {
+        if (!timing) return;
+        const int executed = std::min(chunk, std::max(0, c->Sh->iter - launched));
+        for (int j = 0; j < executed; ++j) {
+            float a = 0, b = 0, d = 0;
+            (void)hipEventElapsedTime(&a, c->ev[4 * j + 0], c->ev[4 * j + 1]);
+            if (o.timing_all) {
+                (void)hipEventElapsedTime(&b, c->ev[4 * j + 1], c->ev[4 * j + 2]);
+                (void)hipEventElapsedTime(&d, c->ev[4 * j + 2], c->ev[4 * j + 3]);
+            }
+            c->t_spmv += a; c->t_upd += b; c->t_sweep += d; c->t_count++;
+        }
+    };
+    constexpr int kChunk = 16;
+    hipGraphExec_t ex = nullptr;
+    // kernel timing uses events between launches: stream launches then
+    if (c->use_graphs && !o.sync_every && !o.stream_only && !timing) {
+        const uint32_t key = (sizeof(T) == 4 ? 1u : 0u) | ((uint32_t)o.kind << 1) | ((uint32_t)o.noprec << 3) |
+                             ((uint32_t)o.power << 4) | ((uint32_t)o.sampling << 5) | ((uint32_t)(*vbase & 1) << 6) |
+                             ((uint32_t)fuse_l0 << 7);
+        for (auto &g : c->graphs)
+            if (g.key == key && g.epoch == c->epoch) ex = g.exec;
+        if (!ex && !c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+            c->cap = nullptr;
+            c->use_graphs = false;
+        }
+        if (!ex && c->cap) {
+            // capture on the private stream (the caller's may be the null
+            // stream, which cannot be captured); replays go to the caller's
+            hipGraph_t graph = nullptr;
+            hipStream_t user = c->stream;
+            c->stream = c->cap;
+            bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+            if (ok) {
+                const hipError_t eb = body(0, kChunk);
+                const hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+                ok = eb == hipSuccess && ee == hipSuccess && graph;
+            }
+            c->stream = user;
+            if (ok) ok = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            if (ok) {
+                for (auto it = c->graphs.begin(); it != c->graphs.end();)
+                    if (it->key == key) { (void)hipGraphExecDestroy(it->exec); it = c->graphs.erase(it); } else ++it;
+                c->graphs.push_back({key, c->epoch, ex});
+            } else {
+                ex = nullptr;
+                c->use_graphs = false; // capture unsupported here: stream launches from now on
             }
         }
-        launched += chunk;
-        if (c->Sh->done) break;
-        if (!o.sync_every && chunk < 32) chunk *= 2;
+    }
+    int launched = 0;
+    if (ex) {
+        for (;;) {
+            HIPCHK(hipGraphLaunch(ex, c->stream));
+            esd_status st = sync_read(c);
+            if (st != ESD_OK) return st;
+            harvest(launched, kChunk);
+            launched += kChunk;
+            if (c->Sh->done) break;
+        }
+    } else {
+        int chunk = o.sync_every ? 1 : 8;
+        for (;;) {
+            HIPCHK(body(launched, chunk));
+            esd_status st = sync_read(c);
+            if (st != ESD_OK) return st;
+            harvest(launched, chunk);
+            launched += chunk;
+            if (c->Sh->done) break;
+            if (!o.sync_every && chunk < 32) chunk *= 2;
+        }
     }
     *iters = c->Sh->iter;
     *vbase = (*vbase + c->Sh->iter) & 1;
@@ -399,6 +492,7 @@ void init_scal(esd_ctx *c, int maxit, double vscale, int stag) {
     S.stag_window = stag;
     S.rr_ref = 1e300;
     S.rho = 1.0;
+    S.xscale = 1.0;
 }
 
 void fill_lanczos(esd_ctx *c, esd_info *info) {
@@ -436,6 +530,7 @@ esd_status ensure_tables(esd_ctx *c, int maxit) {
         HIPCHK(dalloc(&c->ha, need));
         HIPCHK(dalloc(&c->hb, need));
         c->hcap = need;
+        c->epoch++;
     }
     if (c->armed) {
         esd::sampling_table(c->m_req, (int64_t)maxit + 2, c->table_h);
@@ -444,6 +539,7 @@ esd_status ensure_tables(esd_ctx *c, int maxit) {
             c->slot_table = nullptr;
             HIPCHK(dalloc(&c->slot_table, (int64_t)c->table_h.size()));
             c->slot_table_cap = (int64_t)c->table_h.size();
+            c->epoch++;
         }
         HIPCHK(hipMemcpyAsync(c->slot_table, c->table_h.data(), sizeof(int32_t) * c->table_h.size(),
                               hipMemcpyHostToDevice, c->stream));
@@ -475,6 +571,7 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
     const int m = kind ? c->m_tilde : 0;
     const bool sampling = c->armed;
     const bool power = (flags & ESD_FLAG_POWER) != 0;
+    const bool restart = (flags & ESD_FLAG_TRUE_RES) != 0;
     auto V = vecs<double>(c);
     esd::launch_gather(n, c->p2u, b, c->b, c->stream);
     if (x0) esd::launch_gather(n, c->p2u, x0, c->x, c->stream);
@@ -489,35 +586,59 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
         f.settol = tol;
         esd::launch_fin_gen(f, c->stream);
     }
-    // r_0 = b - A x_0; deflation: r_0 = P^T r_0 = r_0 - AW C^{-1} W^T r_0;
-    // subspace correction: u = C^{-1} W^T r_0 for z_0
-    double *coef = (kind == 1) ? c->S->mu : (kind == 2 ? c->S->u : nullptr);
-    dev_resid(c, c->b, c->x, c->r, m ? c->W : nullptr, m, coef, nullptr, kind != 1);
-    if (kind == 1) dev_axpy(c, c->r, c->AW, m, c->S->mu, -1.0, nullptr, 1);
-    KrylovOpts o;
-    o.kind = kind;
-    o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
-    o.power = power;
-    o.sampling = sampling;
-    o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
-    o.timing = (flags & kFlagTiming) != 0;
-    o.timing_all = (flags & ESD_FLAG_TIMING) != 0;
-    int iters = 0;
-    st = krylov<double>(c, V, o, &iters, &c->vb64);
+    st = sync_read(c);
     if (st) return st;
-    const int done = c->Sh->done;
-    const double rr = c->Sh->rr;
-    c->segments.assign(1, {0, iters});
-    if (sampling && done == 2 && iters < (int)c->table_h.size() && c->table_h[iters] >= 0)
-        esd::launch_sample_store(n, c->slots + (size_t)c->table_h[iters] * n, c->x, c->stream);
-    if (kind == 1) {
-        // x = P x_i + W C^{-1} W^T b  ==  x_i + W C^{-1} W^T (b - A x_i)
-        dev_resid(c, c->b, c->x, c->t, c->W, m, c->S->mu, nullptr, 0);
-        dev_axpy(c, c->x, c->W, m, c->S->mu, 1.0, nullptr, 0);
+    const double bn2 = c->Sh->bnorm2, tol2 = c->Sh->tol2;
+    c->segments.clear();
+    int total = 0, done = 0, cycles = 0;
+    double rr = 0.0, tr2 = 0.0;
+    for (;;) {
+        // r_0 = b - A x_0; deflation: r_0 = P^T r_0 = r_0 - AW C^{-1} W^T r_0;
+        // subspace correction: u = C^{-1} W^T r_0 for z_0
+        init_scal(c, maxit - total, c->vs64, 0);
+        c->Sh->bnorm2 = bn2;
+        c->Sh->tol2 = tol2;
+        c->Sh->hist_base = total;
+        c->Sh->sample_base = total;
+        if ((st = put_scal(c))) return st;
+        double *coef = (kind == 1) ? c->S->mu : (kind == 2 ? c->S->u : nullptr);
+        dev_resid(c, c->b, c->x, c->r, m ? c->W : nullptr, m, coef, nullptr, kind != 1);
+        if (kind == 1) dev_axpy(c, c->r, c->AW, m, c->S->mu, -1.0, nullptr, 1);
+        KrylovOpts o;
+        o.kind = kind;
+        o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
+        o.power = power;
+        o.sampling = sampling && cycles == 0;
+        o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
+        o.stream_only = (flags & ESD_FLAG_STREAM) != 0;
+        o.timing = (flags & kFlagTiming) != 0;
+        o.timing_all = (flags & ESD_FLAG_TIMING) != 0;
+        int iters = 0;
+        st = krylov<double>(c, V, o, &iters, &c->vb64);
+        if (st) return st;
+        done = c->Sh->done;
+        rr = c->Sh->rr;
+        if (power) c->vs64 = c->Sh->vscale;
+        c->segments.push_back({total, iters});
+        if (o.sampling) {
+            if (done == 2 && iters < (int)c->table_h.size() && c->table_h[iters] >= 0)
+                esd::launch_sample_store(n, c->slots + (size_t)c->table_h[iters] * n, c->x, c->stream);
+            record_samples(c, iters, done == 2);
+        }
+        total += iters;
+        if (kind == 1) {
+            // x = P x_i + W C^{-1} W^T b  ==  x_i + W C^{-1} W^T (b - A x_i)
+            dev_resid(c, c->b, c->x, c->t, c->W, m, c->S->mu, nullptr, 0);
+            dev_axpy(c, c->x, c->W, m, c->S->mu, 1.0, nullptr, 0);
+        }
+        dev_resid(c, c->b, c->x, c->t, nullptr, 0, nullptr, &c->S->out, 0);
+        if ((st = sync_read(c))) return st;
+        tr2 = c->Sh->out;
+        ++cycles;
+        // optional: restart from x while the recomputed residual misses the tolerance
+        if (!restart || done != 1 || tr2 <= tol2 || cycles > 4 || total >= maxit) break;
     }
-    dev_resid(c, c->b, c->x, c->t, nullptr, 0, nullptr, &c->S->out, 0);
     if (power) {
-        c->vs64 = c->Sh->vscale;
         int nb = 0;
         esd::launch_rayleigh(n, c->A.e64(), c->v[c->vb64], c->part_gen, &nb, c->stream);
         esd::FinGen f = fin_gen(c, nb, 1, 1);
@@ -528,28 +649,27 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
     esd::launch_scatter(n, c->p2u, c->x, xout, c->stream);
     if (sampling) {
         HIPCHK(hipMemcpyAsync(c->xN, c->x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-        record_samples(c, iters, done == 2);
         c->armed = false;
     }
     st = sync_read(c);
     if (st) return st;
-    st = read_history(c, iters);
+    st = read_history(c, total);
     if (st) return st;
-    const double bn2 = c->Sh->bnorm2;
     if (info) {
-        info->iters = iters;
-        info->outer_iters = 1;
-        info->converged = (done == 1);
+        info->iters = total;
+        info->outer_iters = cycles;
+        info->converged = (done == 1) && (!restart || tr2 <= tol2);
         info->m_tilde = m;
         info->nsamples = sampling ? c->nsamples : 0;
         info->mode_used = kind;
         info->relres = bn2 > 0 ? std::sqrt(rr / bn2) : std::sqrt(rr);
-        info->true_relres = bn2 > 0 ? std::sqrt(c->Sh->out / bn2) : std::sqrt(c->Sh->out);
+        info->true_relres = bn2 > 0 ? std::sqrt(tr2 / bn2) : std::sqrt(tr2);
         info->lambda_max = power ? c->Sh->lam : 0.0;
         fill_lanczos(c, info);
     }
     if (done == 3) return fail(c, ESD_ENUMERIC, "non-finite value in the iteration");
-    return done == 1 ? ESD_OK : ESD_NOT_CONVERGED;
+    const bool ok = (done == 1) && (!restart || tr2 <= tol2);
+    return ok ? ESD_OK : ESD_NOT_CONVERGED;
 }
 
 esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol, int maxit, int kind,
@@ -575,9 +695,9 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     st = sync_read(c);
     if (st) return st;
     const double bn2 = c->Sh->bnorm2, tol2 = c->Sh->tol2;
-    int total = 0, outer = 0, done_in = 0;
-    bool converged = false;
-    double rn2 = 0.0;
+    int total = 0, outer = 0, done_in = 0, fp64_iters = 0;
+    bool converged = false, fp64 = false;
+    double rn2 = 0.0, rn2_prev = -1.0;
     c->segments.clear();
     for (outer = 0; outer <= c->max_outer; ++outer) {
         // FP64 true residual; deflation: coarse correction x += W C^{-1} W^T r
@@ -594,6 +714,45 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         if (!(rn2 <= 1e300)) return fail(c, ESD_ENUMERIC, "non-finite residual");
         if (rn2 <= tol2) { converged = true; break; }
         if (total >= maxit || outer == c->max_outer) break;
+        // a refinement step that does not halve the residual: the FP32 inner
+        // operator is too far from A (kappa * u_32 >~ 1); finish in FP64
+        if (rn2_prev >= 0.0 && rn2 > 0.25 * rn2_prev) {
+            // an FP64 step that does not halve it either: the residual is at
+            // the FP64 rounding floor of b - A x; stop (not converged)
+            if (fp64) break;
+            fp64 = true;
+        }
+        rn2_prev = rn2;
+        if (fp64) {
+            auto V64 = vecs<double>(c);
+            init_scal(c, maxit - total, c->vs64, 0);
+            c->Sh->tol2 = tol2;
+            c->Sh->bnorm2 = bn2;
+            c->Sh->rr = rn2;
+            c->Sh->hist_base = total;
+            c->Sh->sample_base = total;
+            if ((st = put_scal(c))) return st;
+            if (kind == 2) dev_tsdot(c, c->W, m, c->r, c->S->u, 1.0);
+            KrylovOpts o;
+            o.kind = kind;
+            o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
+            o.power = false;
+            o.sampling = false;
+            o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
+            o.stream_only = (flags & ESD_FLAG_STREAM) != 0;
+            int it64 = 0;
+            st = krylov<double>(c, V64, o, &it64, &c->vb64);
+            if (st) return st;
+            c->segments.push_back({total, it64});
+            total += it64;
+            fp64_iters += it64;
+            if (c->Sh->done == 3) return fail(c, ESD_ENUMERIC, "non-finite value in the FP64 finish");
+            if (kind == 1) {
+                dev_resid(c, c->b, c->x, c->t, c->W, m, c->S->mu, nullptr, 0);
+                dev_axpy(c, c->x, c->W, m, c->S->mu, 1.0, nullptr, 0);
+            }
+            continue; // the next pass recomputes the FP64 residual and tests it
+        }
         const double rn = std::sqrt(rn2);
         esd::launch_cast_scale(n, c->r, c->r32, 1.0 / rn, c->stream);
         esd::launch_fill(n, c->d32, 0.0f, c->stream);
@@ -602,6 +761,9 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         init_scal(c, maxit - total, c->vs32, c->stag_window);
         c->Sh->tol2 = want * want;
         c->Sh->bnorm2 = bn2;
+        c->Sh->hist_base = total;
+        c->Sh->sample_base = total;
+        c->Sh->xscale = rn;
         st = put_scal(c);
         if (st) return st;
         // u = C^{-1} W^T r / ||r|| for the first preconditioned inner residual
@@ -612,12 +774,10 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         o.power = power;
         o.sampling = sampling;
         o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
+        o.stream_only = (flags & ESD_FLAG_STREAM) != 0;
         o.timing = (flags & kFlagTiming) != 0;
-    o.timing_all = (flags & ESD_FLAG_TIMING) != 0;
-        o.hist_base = total;
-        o.sample_base = total;
+        o.timing_all = (flags & ESD_FLAG_TIMING) != 0;
         o.xbase = c->x;
-        o.xscale = rn;
         int it_in = 0;
         st = krylov<float>(c, V, o, &it_in, &c->vb32);
         if (st) return st;
@@ -665,6 +825,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         info->m_tilde = m;
         info->nsamples = sampling ? c->nsamples : 0;
         info->mode_used = kind;
+        info->fp64_iters = fp64_iters;
         info->relres = bn2 > 0 ? std::sqrt(rn2 / bn2) : std::sqrt(rn2);
         info->true_relres = bn2 > 0 ? std::sqrt(c->Sh->out / bn2) : std::sqrt(c->Sh->out);
         info->lambda_max = power ? c->Sh->lam : 0.0;
@@ -691,10 +852,13 @@ esd_status finish_aux(esd_ctx *c, int k) {
     HIPCHK(hipMemcpyAsync(c->Cinv, Cinv.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, c->stream));
     esd::launch_cast((int64_t)k * n, c->W, c->W32, c->stream);
     esd::launch_cast((int64_t)k * n, c->AW, c->AW32, c->stream);
+    esd::launch_to_rowmajor(n, k, c->W, c->W_rm, c->W32_rm, c->stream);
+    esd::launch_to_rowmajor(n, k, c->AW, c->AW_rm, c->AW32_rm, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     c->m_tilde = k;
     c->aux_built = true;
+    c->epoch++;
     return ESD_OK;
 }
 
@@ -727,14 +891,16 @@ void esd_destroy(esd_ctx *c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     free_ell(c->A); free_ell(c->L); free_ell(c->U);
-    void *ptrs[] = {c->u_from_l, c->l_orig, c->adiag, c->ldiag, c->dinv, c->dinv32, c->p2u, c->urp, c->ucol, c->bad,
+    void *ptrs[] = {c->u_from_l, c->l_orig, c->a_src, c->l_src, c->d_src, c->adiag, c->ldiag, c->dinv, c->dinv32, c->p2u, c->urp, c->ucol, c->bad,
                     c->b, c->x, c->r, c->z, c->zsc, c->y, c->q, c->p[0], c->p[1], c->t, c->v[0], c->v[1],
                     c->r32, c->z32, c->zsc32, c->y32, c->q32, c->p32[0], c->p32[1], c->d32, c->v32[0], c->v32[1],
-                    c->part_spmv, c->part_upd, c->part_gen, c->part_sweep, c->S, c->slots, c->slot_table, c->xN,
+                    c->part_spmv, c->part_upd, c->part_gen, c->part_sweep, c->part_ts, c->W_rm, c->W32_rm, c->AW_rm, c->AW32_rm, c->S, c->slots, c->slot_table, c->xN,
                     c->E, c->AE, c->W, c->AW, c->W32, c->AW32, c->Cinv, c->gram_part, c->G, c->Tm, c->ha, c->hb};
     for (void *p : ptrs) if (p) hipFree(p);
     if (c->Sh) hipHostFree(c->Sh);
-    for (auto &e : c->ev) hipEventDestroy(e);
+    for (auto &e : c->ev) (void)hipEventDestroy(e);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
 }
 
@@ -772,6 +938,14 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     SETUP_CHK(upload_ell(c, c->A, H.A));
     SETUP_CHK(upload_ell(c, c->L, H.L));
     SETUP_CHK(upload_ell(c, c->U, H.U));
+    SETUP_HIP(dalloc(&c->a_src, c->A.size));
+    SETUP_HIP(dalloc(&c->l_src, c->L.size));
+    SETUP_HIP(dalloc(&c->d_src, n));
+    if (c->A.size)
+        SETUP_HIP(hipMemcpyAsync(c->a_src, H.a_src.data(), sizeof(int32_t) * c->A.size, hipMemcpyHostToDevice, c->stream));
+    if (c->L.size)
+        SETUP_HIP(hipMemcpyAsync(c->l_src, H.l_src.data(), sizeof(int32_t) * c->L.size, hipMemcpyHostToDevice, c->stream));
+    SETUP_HIP(hipMemcpyAsync(c->d_src, H.d_src.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
     SETUP_HIP(dalloc(&c->l_orig, c->L.size));
     if (c->L.size)
         SETUP_HIP(hipMemcpyAsync(c->l_orig, c->L.v64, sizeof(double) * c->L.size, hipMemcpyDeviceToDevice, c->stream));
@@ -807,6 +981,7 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     SETUP_HIP(dalloc(&c->part_spmv, (int64_t)esd::kMaxGrid * esd::kMaxNV));
     SETUP_HIP(dalloc(&c->part_upd, (int64_t)esd::kMaxGrid * esd::kMaxNV));
     SETUP_HIP(dalloc(&c->part_gen, (int64_t)esd::kMaxGrid * esd::kMaxNV));
+    SETUP_HIP(dalloc(&c->part_ts, (int64_t)esd::kMaxGrid * esd::kMaxNV));
     {
         int64_t cap = esd::grid_red(n, 1);
         int64_t tot = 0;
@@ -827,6 +1002,10 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     SETUP_HIP(dalloc(&c->AW, (int64_t)esd::kMaxCols * n));
     SETUP_HIP(dalloc(&c->W32, (int64_t)esd::kMaxCols * n));
     SETUP_HIP(dalloc(&c->AW32, (int64_t)esd::kMaxCols * n));
+    SETUP_HIP(dalloc(&c->W_rm, (int64_t)esd::kMaxCols * n));
+    SETUP_HIP(dalloc(&c->W32_rm, (int64_t)esd::kMaxCols * n));
+    SETUP_HIP(dalloc(&c->AW_rm, (int64_t)esd::kMaxCols * n));
+    SETUP_HIP(dalloc(&c->AW32_rm, (int64_t)esd::kMaxCols * n));
     SETUP_HIP(dalloc(&c->Cinv, 64 * 64));
     SETUP_HIP(dalloc(&c->gram_part, (int64_t)esd::gram_grid((int)n) * 4096));
     SETUP_HIP(dalloc(&c->G, 64 * 64));
@@ -866,6 +1045,22 @@ esd_status esd_factor_ic0(esd_ctx *c) {
         return fail(c, ESD_ENOTSPD, "IC(0) pivot <= 0");
     }
     c->factored = true;
+    return ESD_OK;
+}
+
+esd_status esd_update_values(esd_ctx *c, const double *val) {
+    if (!c || !val) return ESD_EINVAL;
+    esd::launch_map_values(c->A.size, c->a_src, val, c->A.v64, c->A.v32, c->stream);
+    esd::launch_map_values(c->L.size, c->l_src, val, c->l_orig, nullptr, c->stream);
+    esd::launch_map_values(c->n, c->d_src, val, c->adiag, nullptr, c->stream);
+    HIPCHK(hipGetLastError());
+    c->factored = false;
+    if (c->aux_built && c->m_tilde > 0) {
+        // keep W, refresh AW = A W and C = W^T A W for the new values
+        esd::launch_spmm((int)c->n, c->A.e64(), c->W, c->m_tilde, c->AW, c->stream);
+        return finish_aux(c, c->m_tilde);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
     return ESD_OK;
 }
 

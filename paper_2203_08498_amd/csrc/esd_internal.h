@@ -32,6 +32,9 @@ struct HostLayout {
     HostEll U;                     // strictly upper (logical) entries
     std::vector<int64_t> u_from_l; // position in L of the transposed entry of each U slot (-1 pad)
     std::vector<double> adiag;     // a_ii per physical row
+    // position in the caller's CSR of every ELL slot (-1 padding) and of every
+    // diagonal, so that new values of the same pattern can be scattered in
+    std::vector<int32_t> a_src, l_src, d_src;
 };
 
 // Builds the layout; returns an empty string on success, else the reason.

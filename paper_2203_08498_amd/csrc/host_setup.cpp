@@ -17,6 +17,7 @@ struct Ent {
     int32_t key; // sort key (physical or logical column)
     int32_t pc;  // physical column
     double v;
+    int32_t src; // position in the caller's CSR
 };
 
 void ell_alloc(HostEll &E, const std::vector<int32_t> &len, int64_t n) {
@@ -42,6 +43,7 @@ inline int64_t ell_pos(const HostEll &E, int64_t row, int64_t k) {
 std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                          const int32_t *colors, HostLayout &H) {
     if (n <= 0 || n >= (int64_t(1) << 31) - 64) return "n out of range";
+    if (rowptr[n] >= (int64_t(1) << 31)) return "nnz out of range";
     if (rowptr[0] != 0) return "rowptr[0] != 0";
     for (int64_t i = 0; i < n; ++i)
         if (rowptr[i + 1] < rowptr[i]) return "rowptr not monotone";
@@ -127,6 +129,9 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
     ell_alloc(H.L, lenL, n);
     ell_alloc(H.U, lenU, n);
     H.adiag.assign(n, 0.0);
+    H.a_src.assign(H.A.col.size(), -1);
+    H.l_src.assign(H.L.col.size(), -1);
+    H.d_src.assign(n, -1);
 #pragma omp parallel
     {
         std::vector<Ent> ea, el, eu;
@@ -136,10 +141,10 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
             ea.clear(); el.clear(); eu.clear();
             for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
                 int32_t cu = col[k], q = lpos[cu], pc = ppos[q];
-                ea.push_back({pc, pc, val[k]});
-                if (q < l) el.push_back({q, pc, val[k]});
-                else if (q > l) eu.push_back({q, pc, val[k]});
-                else H.adiag[p] = val[k];
+                ea.push_back({pc, pc, val[k], (int32_t)k});
+                if (q < l) el.push_back({q, pc, val[k], (int32_t)k});
+                else if (q > l) eu.push_back({q, pc, val[k], (int32_t)k});
+                else { H.adiag[p] = val[k]; H.d_src[p] = (int32_t)k; }
             }
             auto by = [](const Ent &a, const Ent &b) { return a.key < b.key; };
             std::sort(ea.begin(), ea.end(), by);
@@ -147,11 +152,11 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
             std::sort(eu.begin(), eu.end(), by);
             for (size_t k = 0; k < ea.size(); ++k) {
                 int64_t pos = ell_pos(H.A, p, k);
-                H.A.col[pos] = ea[k].pc; H.A.val[pos] = ea[k].v;
+                H.A.col[pos] = ea[k].pc; H.A.val[pos] = ea[k].v; H.a_src[pos] = ea[k].src;
             }
             for (size_t k = 0; k < el.size(); ++k) {
                 int64_t pos = ell_pos(H.L, p, k);
-                H.L.col[pos] = el[k].pc; H.L.val[pos] = el[k].v;
+                H.L.col[pos] = el[k].pc; H.L.val[pos] = el[k].v; H.l_src[pos] = el[k].src;
             }
             for (size_t k = 0; k < eu.size(); ++k) {
                 int64_t pos = ell_pos(H.U, p, k);

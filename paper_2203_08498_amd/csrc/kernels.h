@@ -7,7 +7,7 @@
 namespace esd {
 
 constexpr int kBlock = 256;     // threads per block of every row kernel
-constexpr int kMaxGrid = 2048;  // largest grid of a reducing kernel
+constexpr int kMaxGrid = 8192;  // largest grid of a reducing kernel
 constexpr int kMaxNV = 72;      // largest number of values reduced together
 constexpr int kFinThreads = 1024; // threads of a finalize kernel
 constexpr int kPartBudget = 48 * 1024; // doubles a finalize kernel reads at most
@@ -30,7 +30,10 @@ struct Scal {
     int32_t done;    // 0 running, 1 converged, 2 maxit, 3 non-finite, 4 stagnated
     int32_t maxit;
     int32_t stag_window; // 0 = off
+    int32_t hist_base;   // offset of this Krylov run in the alpha/beta history
+    int32_t sample_base; // offset of this Krylov run in the sampling schedule
     int32_t pad;
+    double xscale;       // sampled value = xbase + xscale * iterate (mixed inner solves)
     double mu[64];   // C^{-1} W^T q (deflation) or generic coarse coefficients
     double u[64];    // C^{-1} W^T r (subspace correction)
     double svec[64]; // last tall-skinny product W^T v
@@ -47,8 +50,8 @@ template <typename T> struct Ell {
 // one-block finalize kernel sums the rows in a fixed order.
 
 // one iteration's SpMV: p_new = z + beta p_old (p_new = z on the first
-// iteration), q = A p_new; partials (p_new, q), W^T q, ||v_new||^2; optional
-// power iterate v_new = A v_old / ||v_old||; optional sampling store.
+// iteration), q = A p_new; partials (p_new, q) and ||v_new||^2; optional power
+// iterate v_new = A v_old / ||v_old||; optional sampling store of the iterate.
 template <typename T> struct SpmvIt {
     int n;
     Scal *S;
@@ -58,27 +61,37 @@ template <typename T> struct SpmvIt {
     T *pnew, *q;
     const T *vold;
     T *vnew;
-    const T *W;
-    int m;
     const int32_t *slot_table;
-    int sample_base;
     double *slots;
     const T *xit;
     const double *xbase;
-    double xscale;
 };
 
 // x += alpha p; r -= alpha w with w = q (plain, SC) or q - AW mu (deflated);
-// partials ||r||^2 and, for subspace correction, W^T r.
+// partials ||r||^2; rows [0, l0) also do their forward-sweep step y = r / l_ii
+// (they have no logically-earlier neighbour).
 template <typename T> struct UpdIt {
     int n;
     Scal *S;
     double *part;
     const T *p, *q;
     T *x, *r;
-    const T *AW; // deflated
-    const T *W;  // subspace correction
+    const T *AW; // deflated, column-major
     int m;
+    int l0;      // rows of the first sweep level fused here (0 = none)
+    const T *dinv;
+    T *y;
+};
+
+// Tall-skinny s = W^T v with W row-major (n x m, W[i m + k]): lane t of a
+// wavefront owns column t % P and row offset t / P (P = next power of two
+// >= m), so a row's m values are read by consecutive lanes; partial rows of P.
+template <typename T> struct TsDot {
+    int n, m;
+    const T *Wrm;
+    const T *v;
+    double *part;
+    const Scal *S; // skip when S->done (may be null)
 };
 
 // one level of the forward (L y = r) or backward (L^T z = y) IC(0) sweep;
@@ -97,15 +110,18 @@ template <typename T> struct Sweep {
 };
 
 // finalize after the SpMV: alpha = rho / ((p,q) - s^T C^{-1} s), mu = C^{-1} s
+// with s = W^T q from a TsDot partial table
 struct FinAlpha {
     Scal *S;
     const double *part;
-    int nblk, stride, m, power;
+    int nblk, stride, power;
+    const double *part_s; // W^T q partials (deflated), nblk_s x stride_s
+    int nblk_s, stride_s, m;
     const double *Cinv;
     double *hist_alpha;
-    int hist_base;
 };
-// finalize after the preconditioner: stop test on ||r||^2, rho, beta
+// finalize after the preconditioner: stop test on ||r||^2, rho, beta; with
+// deflation also mu = C^{-1} (AW)^T z for the projected direction
 struct FinRho {
     Scal *S;
     const double *part_upd; // column 0 = ||r||^2 partials
@@ -113,8 +129,19 @@ struct FinRho {
     const double *part_sweep;
     int nsweep;
     double *hist_beta;
-    int hist_base;
     int init; // first preconditioner application of a solve: only rho
+    const double *part_s; // (AW)^T z partials (deflated), nblk_s x stride_s
+    int nblk_s, stride_s, m;
+    const double *Cinv;
+};
+
+// zhat = z - W mu (W column-major n x m, mu = S->mu): the projected
+// preconditioned residual of the deflated iteration
+template <typename T> struct Proj {
+    int n, m;
+    const Scal *S;
+    const T *z, *W;
+    T *zhat;
 };
 // generic finalize of a per-solve reduction: tot[k] = column sums
 struct FinGen {
@@ -132,10 +159,19 @@ struct FinGen {
     int store_svec;   // S->svec = s
 };
 
-void launch_spmv_it(const SpmvIt<double> &a, int mt, bool power, int grid, hipStream_t s);
-void launch_spmv_it(const SpmvIt<float> &a, int mt, bool power, int grid, hipStream_t s);
-void launch_update_it(const UpdIt<double> &a, int mt, int kind, int grid, hipStream_t s);
-void launch_update_it(const UpdIt<float> &a, int mt, int kind, int grid, hipStream_t s);
+void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s);
+void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s);
+// kind 0 plain / subspace correction, 1 deflated
+void launch_update_it(const UpdIt<double> &a, int kind, int grid, hipStream_t s);
+void launch_update_it(const UpdIt<float> &a, int kind, int grid, hipStream_t s);
+void launch_proj(const Proj<double> &a, int grid, hipStream_t s);
+void launch_proj(const Proj<float> &a, int grid, hipStream_t s);
+void launch_tsdot_rm(const TsDot<double> &a, int grid, hipStream_t s);
+void launch_tsdot_rm(const TsDot<float> &a, int grid, hipStream_t s);
+int tsdot_stride(int m);
+int tsdot_grid(int64_t n, int m);
+// row-major copy Wrm[i m + k] = W[k n + i] (FP64 and FP32)
+void launch_to_rowmajor(int n, int m, const double *W, double *Wrm, float *Wrm32, hipStream_t s);
 void launch_fwd(const Sweep<double> &a, bool last, bool sc, int grid, hipStream_t s);
 void launch_fwd(const Sweep<float> &a, bool last, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
@@ -147,8 +183,7 @@ void launch_fin_u(Scal *S, const double *part, int nblk, int stride, int m, cons
 void launch_fin_rho(const FinRho &f, hipStream_t s);
 void launch_fin_gen(const FinGen &f, hipStream_t s);
 // stride of the partial rows of the iteration kernels
-int spmv_stride(int m, bool power);
-int update_stride(int m, int kind);
+int spmv_stride(bool power);
 // grid of a reducing row kernel over `rows` rows with `stride` partials per block
 int grid_red(int64_t rows, int stride);
 
@@ -194,6 +229,9 @@ void launch_factor_level(int r0, int r1, int n, Ell<double> L, double *lval, con
 void launch_finish_factor(int n, const double *ldiag, double *dinv, float *dinv32, hipStream_t s);
 void launch_gather_u(int64_t cnt, const int64_t *map, const double *lval, double *uval,
                      hipStream_t s);
+// dst[i] = val[src[i]] (0 where src < 0), optional FP32 copy
+void launch_map_values(int64_t cnt, const int32_t *src, const double *val, double *dst, float *dst32,
+                       hipStream_t s);
 
 // A E for m columns (column-major, FP64)
 void launch_spmm(int n, Ell<double> A, const double *E, int m, double *AE, hipStream_t s);

@@ -71,18 +71,25 @@ __device__ void fin_colsum(const double *part, int nblk, int stride, int c0, int
     while (p2 < nc) p2 <<= 1;
     const int groups = kFinThreads / p2;
     const int t = threadIdx.x, k = t % p2, g = t / p2;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double acc = 0.0;
     if (k < nc) {
-        int j = g;
-        for (; j + 3 * groups < nblk; j += 4 * groups) {
-            a0 += part[(size_t)j * stride + c0 + k];
-            a1 += part[(size_t)(j + groups) * stride + c0 + k];
-            a2 += part[(size_t)(j + 2 * groups) * stride + c0 + k];
-            a3 += part[(size_t)(j + 3 * groups) * stride + c0 + k];
+        // all loads of a round are issued before any add: one memory latency
+        // per 16 rows instead of one per row
+        for (int j0 = g; j0 < nblk; j0 += 16 * groups) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int j = j0 + u * groups;
+                v[u] = (j < nblk) ? part[(size_t)j * stride + c0 + k] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u += 2) v[u] += v[u + 1];
+#pragma unroll
+            for (int u = 0; u < 16; u += 4) v[u] += v[u + 2];
+            acc += (v[0] + v[4]) + (v[8] + v[12]);
         }
-        for (; j < nblk; j += groups) a0 += part[(size_t)j * stride + c0 + k];
     }
-    buf[t] = (a0 + a1) + (a2 + a3);
+    buf[t] = acc;
     __syncthreads();
     for (int h = groups / 2; h >= 1; h >>= 1) {
         if (g < h) buf[t] += buf[t + h * p2];
@@ -96,7 +103,75 @@ __device__ void fin_colsum(const double *part, int nblk, int stride, int c0, int
 // per-iteration kernels
 // ------------------------------------------------------------------------
 
-template <typename T, int MT, bool POW>
+// sum_k val_k * g(col_k) over one sliced-ELL row; the row's entries are
+// loaded eight at a time before any gather is issued, so a wavefront keeps
+// up to 8 value/index loads and then 8 (or 16) gathers in flight.
+template <typename T, typename G>
+__device__ __forceinline__ T ell_dot(const Ell<T> &M, int i, int n, G g) {
+    const int lane = i & 63;
+    const int64_t base = M.sptr[i >> 6];
+    const int w = (int)((M.sptr[(i >> 6) + 1] - base) >> 6);
+    T sum = T(0);
+    for (int k0 = 0; k0 < w; k0 += 8) {
+        int c[8];
+        T a[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k0 + k < w) {
+                const int64_t pos = base + (int64_t)(k0 + k) * 64 + lane;
+                c[k] = M.col[pos];
+                a[k] = M.val[pos];
+            } else {
+                c[k] = n;
+                a[k] = T(0);
+            }
+        }
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = g(c[k]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += a[k] * v[k];
+    }
+    return sum;
+}
+
+// two right-hand sides sharing the matrix loads: (A x, A y)
+template <typename T, typename G1, typename G2>
+__device__ __forceinline__ void ell_dot2(const Ell<T> &M, int i, int n, G1 g1, G2 g2, T &s1, T &s2) {
+    const int lane = i & 63;
+    const int64_t base = M.sptr[i >> 6];
+    const int w = (int)((M.sptr[(i >> 6) + 1] - base) >> 6);
+    s1 = T(0);
+    s2 = T(0);
+    for (int k0 = 0; k0 < w; k0 += 8) {
+        int c[8];
+        T a[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k0 + k < w) {
+                const int64_t pos = base + (int64_t)(k0 + k) * 64 + lane;
+                c[k] = M.col[pos];
+                a[k] = M.val[pos];
+            } else {
+                c[k] = n;
+                a[k] = T(0);
+            }
+        }
+        T v1[8], v2[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v1[k] = g1(c[k]);
+            v2[k] = g2(c[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            s1 += a[k] * v1[k];
+            s2 += a[k] * v2[k];
+        }
+    }
+}
+
+template <typename T, bool POW>
 __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
@@ -105,59 +180,49 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
     const T beta = first ? T(0) : (T)S->beta;
     const T vs = POW ? (T)S->vscale : T(0);
     int slot = -1;
-    if (a.slot_table && iter >= 1) slot = a.slot_table[a.sample_base + iter];
-    constexpr int NV = 1 + MT + (POW ? 1 : 0);
+    if (a.slot_table && iter >= 1) slot = a.slot_table[S->sample_base + iter];
+    constexpr int NV = 1 + (POW ? 1 : 0);
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    const int n = a.n, m = a.m;
+    const int n = a.n;
+    const T *z = a.z, *po = a.pold, *vo = a.vold;
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = t * kBlock + threadIdx.x;
         if (i >= n) continue;
-        const int lane = i & 63;
-        const int64_t base = a.A.sptr[i >> 6];
-        const int w = (int)((a.A.sptr[(i >> 6) + 1] - base) >> 6);
-        T sum = T(0), vsum = T(0);
-        for (int k = 0; k < w; ++k) {
-            const int64_t pos = base + (int64_t)k * 64 + lane;
-            const int c = a.A.col[pos];
-            const T av = a.A.val[pos];
-            const T pj = first ? a.z[c] : a.z[c] + beta * a.pold[c];
-            sum += av * pj;
-            if constexpr (POW) vsum += av * a.vold[c];
+        T sum, vsum = T(0);
+        if (first) {
+            if constexpr (POW) ell_dot2(a.A, i, n, [&](int c) { return z[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
+            else sum = ell_dot(a.A, i, n, [&](int c) { return z[c]; });
+        } else {
+            if constexpr (POW)
+                ell_dot2(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
+            else sum = ell_dot(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; });
         }
-        const T pi = first ? a.z[i] : a.z[i] + beta * a.pold[i];
+        const T pi = first ? z[i] : z[i] + beta * po[i];
         a.pnew[i] = pi;
         a.q[i] = sum;
         acc[0] += (double)pi * (double)sum;
-        if constexpr (MT > 0) {
-#pragma unroll
-            for (int k = 0; k < MT; ++k)
-                if (k < m) acc[1 + k] += (double)a.W[(size_t)k * n + i] * (double)sum;
-        }
         if constexpr (POW) {
             const T vn = vsum * vs;
             a.vnew[i] = vn;
-            acc[NV - 1] += (double)vn * (double)vn;
+            acc[1] += (double)vn * (double)vn;
         }
         if (slot >= 0)
             a.slots[(size_t)slot * n + i] =
-                a.xbase ? a.xbase[i] + a.xscale * (double)a.xit[i] : (double)a.xit[i];
+                a.xbase ? a.xbase[i] + S->xscale * (double)a.xit[i] : (double)a.xit[i];
     }
     block_partials<NV>(acc, a.part, NV);
 }
 
-// KIND: 0 plain, 1 deflated (w = q - AW mu), 2 subspace correction (W^T r)
+// KIND: 0 plain / subspace correction, 1 deflated (w = q - AW mu)
 template <typename T, int MT, int KIND>
 __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
     const T ta = (T)S->alpha;
-    constexpr int NV = 1 + (KIND == 2 ? MT : 0);
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    double acc[1] = {0.0};
     const int n = a.n, m = a.m;
     double mu[KIND == 1 ? MT : 1];
     if constexpr (KIND == 1) {
@@ -180,13 +245,51 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
         const T ri = a.r[i] - ta * wi;
         a.r[i] = ri;
         acc[0] += (double)ri * (double)ri;
-        if constexpr (KIND == 2) {
-#pragma unroll
-            for (int k = 0; k < MT; ++k)
-                if (k < m) acc[1 + k] += (double)a.W[(size_t)k * n + i] * (double)ri;
-        }
+        if (i < a.l0) a.y[i] = ri * a.dinv[i];
     }
-    block_partials<NV>(acc, a.part, NV);
+    block_partials<1>(acc, a.part, 1);
+}
+
+// s = W^T v, W row-major n x m; P = next power of two >= m
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_tsdot_rm(TsDot<T> a) {
+    if (a.S && a.S->done) return;
+    constexpr int RPW = 64 / P;      // rows per wavefront step
+    constexpr int WAVES = kBlock / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int k = lane % P, ro = lane / P;
+    const int m = a.m, n = a.n;
+    const int G = gridDim.x;
+    constexpr int STEP = WAVES * RPW;
+    const int per = ((n + G - 1) / G + STEP - 1) / STEP * STEP;
+    const int r0 = xcd_block() * per, r1 = min(n, r0 + per);
+    double acc = 0.0;
+    if (k < m) {
+#pragma unroll 4
+        for (int r = r0 + wid * RPW + ro; r < r1; r += STEP)
+            acc += (double)a.Wrm[(size_t)r * m + k] * (double)a.v[r];
+    }
+#pragma unroll
+    for (int off = 32; off >= P; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __shared__ double lds[WAVES][P];
+    if (ro == 0) lds[wid][k] = acc;
+    __syncthreads();
+    if ((int)threadIdx.x < P) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) s += lds[w][threadIdx.x];
+        a.part[(size_t)blockIdx.x * P + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_to_rowmajor(int n, int m, const double *W, double *Wrm, float *Wrm32) {  // also used for AW
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < m; ++k) {
+        const double v = W[(size_t)k * n + i];
+        Wrm[(size_t)i * m + k] = v;
+        Wrm32[(size_t)i * m + k] = (float)v;
+    }
 }
 
 template <typename T, bool SC>
@@ -204,19 +307,13 @@ template <typename T, bool LAST, bool SC>
 __global__ __launch_bounds__(kBlock) void k_fwd(Sweep<T> a) {
     if (a.S->done) return;
     double acc[1] = {0.0};
+    const T *y = a.y;
     const Tiles tl = my_tiles(a.r1 - a.r0);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = a.r0 + t * kBlock + threadIdx.x;
         if (i >= a.r1) continue;
-        const int lane = i & 63;
-        const int64_t base = a.M.sptr[i >> 6];
-        const int w = (int)((a.M.sptr[(i >> 6) + 1] - base) >> 6);
         const T ri = a.r[i];
-        T s = ri;
-        for (int k = 0; k < w; ++k) {
-            const int64_t pos = base + (int64_t)k * 64 + lane;
-            s -= a.M.val[pos] * a.y[a.M.col[pos]];
-        }
+        const T s = ri - ell_dot(a.M, i, a.n, [&](int c) { return y[c]; });
         const T yi = s * a.dinv[i];
         if constexpr (!LAST) {
             a.y[i] = yi;
@@ -236,18 +333,12 @@ template <typename T, bool SC>
 __global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
     if (a.S->done) return;
     double acc[1] = {0.0};
+    const T *z = a.z;
     const Tiles tl = my_tiles(a.r1 - a.r0);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = a.r0 + t * kBlock + threadIdx.x;
         if (i >= a.r1) continue;
-        const int lane = i & 63;
-        const int64_t base = a.M.sptr[i >> 6];
-        const int w = (int)((a.M.sptr[(i >> 6) + 1] - base) >> 6);
-        T s = a.y[i];
-        for (int k = 0; k < w; ++k) {
-            const int64_t pos = base + (int64_t)k * 64 + lane;
-            s -= a.M.val[pos] * a.z[a.M.col[pos]];
-        }
+        const T s = a.y[i] - ell_dot(a.M, i, a.n, [&](int c) { return z[c]; });
         const T zi = s * a.dinv[i];
         a.z[i] = zi;
         const T zs = add_coarse<T, SC>(a, i, zi);
@@ -282,35 +373,35 @@ __global__ __launch_bounds__(kBlock) void k_copyz(Sweep<T> a) {
 __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(FinAlpha f) {
     Scal *S = f.S;
     if (S->done) return;
-    __shared__ double tot[kMaxNV];
+    __shared__ double tot[2];
+    __shared__ double sv[64];
     __shared__ double mus[64];
-    const int ncol = 1 + f.m;
-    fin_colsum(f.part, f.nblk, f.stride, 0, ncol, tot);
-    if (f.power) fin_colsum(f.part, f.nblk, f.stride, f.stride - 1, 1, tot + ncol);
+    fin_colsum(f.part, f.nblk, f.stride, 0, f.stride, tot);
+    if (f.m > 0) fin_colsum(f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv);
     const int t = threadIdx.x;
     if (t < f.m) {
         double acc = 0.0;
-        for (int j = 0; j < f.m; ++j) acc += f.Cinv[t * f.m + j] * tot[1 + j];
+        for (int j = 0; j < f.m; ++j) acc += f.Cinv[t * f.m + j] * sv[j];
         mus[t] = acc;
         S->mu[t] = acc;
     }
     __syncthreads();
     if (t == 0) {
         double denom = tot[0];
-        for (int k = 0; k < f.m; ++k) denom -= tot[1 + k] * mus[k];
+        for (int k = 0; k < f.m; ++k) denom -= sv[k] * mus[k];
         const double alpha = S->rho / denom;
         S->alpha = alpha;
-        if (f.hist_alpha) f.hist_alpha[f.hist_base + S->iter] = alpha;
+        if (f.hist_alpha) f.hist_alpha[S->hist_base + S->iter] = alpha;
         if (!isfinite(alpha)) S->done = 3;
-        if (f.power) S->vscale = 1.0 / sqrt(tot[ncol]);
+        if (f.power) S->vscale = 1.0 / sqrt(tot[1]);
     }
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_u(Scal *S, const double *part, int nblk, int stride, int m,
                                                        const double *Cinv) {
     if (S->done) return;
-    __shared__ double tot[kMaxNV];
-    fin_colsum(part, nblk, stride, 1, m, tot);
+    __shared__ double tot[64];
+    fin_colsum(part, nblk, stride, 0, m, tot);
     const int t = threadIdx.x;
     if (t < m) {
         double acc = 0.0;
@@ -323,8 +414,18 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
     Scal *S = f.S;
     if (S->done) return;
     __shared__ double tot[2];
+    __shared__ double sv[64];
     fin_colsum(f.part_sweep, f.nsweep, 1, 0, 1, tot + 1);
     if (!f.init) fin_colsum(f.part_upd, f.nblk_upd, f.stride_upd, 0, 1, tot);
+    if (f.m > 0) {
+        fin_colsum(f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv);
+        const int t = threadIdx.x;
+        if (t < f.m) {
+            double acc = 0.0;
+            for (int j = 0; j < f.m; ++j) acc += f.Cinv[t * f.m + j] * sv[j];
+            S->mu[t] = acc;
+        }
+    }
     if (threadIdx.x == 0) {
         const double rn = tot[1];
         if (f.init) {
@@ -351,8 +452,27 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
         S->done = d;
         const double b = rn / S->rho;
         S->beta = b;
-        if (f.hist_beta) f.hist_beta[f.hist_base + it - 1] = b;
+        if (f.hist_beta) f.hist_beta[S->hist_base + it - 1] = b;
         S->rho = rn;
+    }
+}
+
+template <typename T, int MT>
+__global__ __launch_bounds__(kBlock) void k_proj(Proj<T> a) {
+    if (a.S->done) return;
+    double mu[MT];
+#pragma unroll
+    for (int k = 0; k < MT; ++k) mu[k] = (k < a.m) ? a.S->mu[k] : 0.0;
+    const int n = a.n;
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        double s = (double)a.z[i];
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+            if (k < a.m) s -= (double)a.W[(size_t)k * n + i] * mu[k];
+        a.zhat[i] = (T)s;
     }
 }
 
@@ -600,6 +720,16 @@ __global__ void k_finish_factor(int n, const double *ldiag, double *dinv, float 
     }
 }
 
+__global__ void k_map_values(int64_t cnt, const int32_t *src, const double *val, double *dst, float *dst32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) {
+        const int32_t k = src[i];
+        const double v = k >= 0 ? val[k] : 0.0;
+        dst[i] = v;
+        if (dst32) dst32[i] = (float)v;
+    }
+}
+
 __global__ void k_gather_u(int64_t cnt, const int64_t *map, const double *lval, double *uval) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) {
@@ -743,43 +873,66 @@ inline int mt_bucket(int m) {
     default: { constexpr int MTV = 64; CALL; } break;                                              \
     }
 
-int spmv_stride(int m, bool power) { return 1 + (m > 0 ? mt_bucket(m) : 0) + (power ? 1 : 0); }
-int update_stride(int m, int kind) { return 1 + (kind == 2 ? mt_bucket(m) : 0); }
+int spmv_stride(bool power) { return power ? 2 : 1; }
 int grid_red(int64_t rows, int stride) {
     int g = grid_for(rows);
     const int cap = kPartBudget / stride;
     if (g > cap) g = cap / 8 * 8;
     return g < 1 ? 1 : g;
 }
+static int pow2_at_least(int m) {
+    int p = 1;
+    while (p < m) p <<= 1;
+    return p;
+}
+int tsdot_stride(int m) { return pow2_at_least(m); }
+int tsdot_grid(int64_t n, int m) {
+    int64_t g = (n + 1023) / 1024;
+    if (g > 2048) g = 2048;
+    const int cap = kPartBudget / pow2_at_least(m);
+    if (g > cap) g = cap;
+    if (g > 8) g = g / 8 * 8;
+    return g < 1 ? 1 : (int)g;
+}
 
-template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, int mt, bool power, int grid, hipStream_t s) {
-    if (power) {
-        ESD_MT_SWITCH(mt, (k_spmv_it<T, MTV, true><<<grid, kBlock, 0, s>>>(a)));
-    } else {
-        ESD_MT_SWITCH(mt, (k_spmv_it<T, MTV, false><<<grid, kBlock, 0, s>>>(a)));
-    }
+template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, bool power, int grid, hipStream_t s) {
+    if (power) k_spmv_it<T, true><<<grid, kBlock, 0, s>>>(a);
+    else k_spmv_it<T, false><<<grid, kBlock, 0, s>>>(a);
 }
-void launch_spmv_it(const SpmvIt<double> &a, int mt, bool power, int grid, hipStream_t s) {
-    spmv_it_impl(a, mt, power, grid, s);
-}
-void launch_spmv_it(const SpmvIt<float> &a, int mt, bool power, int grid, hipStream_t s) {
-    spmv_it_impl(a, mt, power, grid, s);
-}
+void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
+void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 
-template <typename T> static void update_it_impl(const UpdIt<T> &a, int mt, int kind, int grid, hipStream_t s) {
+template <typename T> static void update_it_impl(const UpdIt<T> &a, int kind, int grid, hipStream_t s) {
     if (kind == 1) {
-        ESD_MT_SWITCH(mt, (k_update_it<T, (MTV > 0 ? MTV : 8), 1><<<grid, kBlock, 0, s>>>(a)));
-    } else if (kind == 2) {
-        ESD_MT_SWITCH(mt, (k_update_it<T, (MTV > 0 ? MTV : 8), 2><<<grid, kBlock, 0, s>>>(a)));
+        ESD_MT_SWITCH(a.m, (k_update_it<T, (MTV > 0 ? MTV : 8), 1><<<grid, kBlock, 0, s>>>(a)));
     } else {
         k_update_it<T, 0, 0><<<grid, kBlock, 0, s>>>(a);
     }
 }
-void launch_update_it(const UpdIt<double> &a, int mt, int kind, int grid, hipStream_t s) {
-    update_it_impl(a, mt, kind, grid, s);
+void launch_update_it(const UpdIt<double> &a, int kind, int grid, hipStream_t s) { update_it_impl(a, kind, grid, s); }
+void launch_update_it(const UpdIt<float> &a, int kind, int grid, hipStream_t s) { update_it_impl(a, kind, grid, s); }
+
+template <typename T> static void proj_impl(const Proj<T> &a, int grid, hipStream_t s) {
+    ESD_MT_SWITCH(a.m, (k_proj<T, (MTV > 0 ? MTV : 8)><<<grid, kBlock, 0, s>>>(a)));
 }
-void launch_update_it(const UpdIt<float> &a, int mt, int kind, int grid, hipStream_t s) {
-    update_it_impl(a, mt, kind, grid, s);
+void launch_proj(const Proj<double> &a, int grid, hipStream_t s) { proj_impl(a, grid, s); }
+void launch_proj(const Proj<float> &a, int grid, hipStream_t s) { proj_impl(a, grid, s); }
+
+template <typename T> static void tsdot_impl(const TsDot<T> &a, int grid, hipStream_t s) {
+    switch (pow2_at_least(a.m)) {
+    case 1: k_tsdot_rm<T, 1><<<grid, kBlock, 0, s>>>(a); break;
+    case 2: k_tsdot_rm<T, 2><<<grid, kBlock, 0, s>>>(a); break;
+    case 4: k_tsdot_rm<T, 4><<<grid, kBlock, 0, s>>>(a); break;
+    case 8: k_tsdot_rm<T, 8><<<grid, kBlock, 0, s>>>(a); break;
+    case 16: k_tsdot_rm<T, 16><<<grid, kBlock, 0, s>>>(a); break;
+    case 32: k_tsdot_rm<T, 32><<<grid, kBlock, 0, s>>>(a); break;
+    default: k_tsdot_rm<T, 64><<<grid, kBlock, 0, s>>>(a); break;
+    }
+}
+void launch_tsdot_rm(const TsDot<double> &a, int grid, hipStream_t s) { tsdot_impl(a, grid, s); }
+void launch_tsdot_rm(const TsDot<float> &a, int grid, hipStream_t s) { tsdot_impl(a, grid, s); }
+void launch_to_rowmajor(int n, int m, const double *W, double *Wrm, float *Wrm32, hipStream_t s) {
+    k_to_rowmajor<<<blocks(n), kBlock, 0, s>>>(n, m, W, Wrm, Wrm32);
 }
 
 template <typename T> static void fwd_impl(const Sweep<T> &a, bool last, bool sc, int grid, hipStream_t s) {
@@ -896,6 +1049,9 @@ void launch_factor_level(int r0, int r1, int n, Ell<double> L, double *lval, con
 }
 void launch_finish_factor(int n, const double *ldiag, double *dinv, float *dinv32, hipStream_t s) {
     k_finish_factor<<<blocks(n), kBlock, 0, s>>>(n, ldiag, dinv, dinv32);
+}
+void launch_map_values(int64_t cnt, const int32_t *src, const double *val, double *dst, float *dst32, hipStream_t s) {
+    if (cnt > 0) k_map_values<<<(unsigned)((cnt + kBlock - 1) / kBlock), kBlock, 0, s>>>(cnt, src, val, dst, dst32);
 }
 void launch_gather_u(int64_t cnt, const int64_t *map, const double *lval, double *uval, hipStream_t s) {
     if (cnt > 0) k_gather_u<<<(unsigned)((cnt + kBlock - 1) / kBlock), kBlock, 0, s>>>(cnt, map, lval, uval);

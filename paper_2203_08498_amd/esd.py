@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesd.so")
 
 PLAIN, DEFLATED, SUBSPACE = 0, 1, 2
-FLAG_NOPREC, FLAG_POWER, FLAG_MIXED, FLAG_SYNC_EVERY, FLAG_TIMING, FLAG_TIMING_SPMV = 1, 2, 4, 8, 16, 32
+FLAG_NOPREC, FLAG_POWER, FLAG_MIXED, FLAG_SYNC_EVERY, FLAG_TIMING, FLAG_TIMING_SPMV, FLAG_TRUE_RES = 1, 2, 4, 8, 16, 32, 64
+FLAG_STREAM = 128
 OK, NOT_CONVERGED, AUX_EMPTY = 0, 1, 2
 EINVAL, ENOTSPD, EHIP, ENUMERIC, ENOAUX, ENOSAMPLES = -1, -2, -3, -4, -5, -6
 
@@ -25,6 +26,7 @@ class EsdInfo(C.Structure):
     _fields_ = [
         ("iters", C.c_int32), ("outer_iters", C.c_int32), ("converged", C.c_int32),
         ("m_tilde", C.c_int32), ("nsamples", C.c_int32), ("mode_used", C.c_int32),
+        ("fp64_iters", C.c_int32), ("reserved", C.c_int32),
         ("relres", C.c_double), ("true_relres", C.c_double), ("kappa", C.c_double),
         ("kappa_es", C.c_double), ("lambda_max", C.c_double), ("lambda_min_ritz", C.c_double),
         ("lanczos_min", C.c_double), ("lanczos_max", C.c_double), ("seconds", C.c_double),
@@ -35,7 +37,7 @@ class EsdInfo(C.Structure):
 
 
 EXPORTS = [
-    "esd_setup", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
+    "esd_setup", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
     "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
     "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag", "esd_get_history", "esd_get_samples",
     "esd_get_layout", "esd_get_timing", "esd_status_string", "esd_last_error", "esd_destroy",
@@ -56,6 +58,7 @@ def load_library(path: str = LIB_PATH):
     P, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.esd_setup.argtypes = [C.POINTER(P), P, i64, P, P, P, P, i32]
     L.esd_factor_ic0.argtypes = [P]
+    L.esd_update_values.argtypes = [P, P]
     L.esd_sample_errors.argtypes = [P, i32]
     L.esd_load_samples.argtypes = [P, P, i32, P]
     L.esd_build_aux.argtypes = [P, dbl, P, P, P]
@@ -79,7 +82,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_last_error.argtypes = [P]
     L.esd_last_error.restype = C.c_char_p
     L.esd_destroy.argtypes = [P]
-    for name in ("esd_setup", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
+    for name in ("esd_setup", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
                  "esd_set_aux",
                  "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs",
                  "esd_grad_values", "esd_spmv", "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag",
@@ -169,6 +172,13 @@ class Solver:
         st = self.L.esd_factor_ic0(self.h)
         if st != 0:
             raise EsdError(st, self.L.esd_last_error(self.h).decode())
+
+    def update_values(self, val):
+        """New stored values (same pattern, caller CSR order); call factor_ic0 afterwards."""
+        v = self._vec(val)
+        if v.numel() != self.nnz:
+            raise ValueError("expected %d values" % self.nnz)
+        self._check(self.L.esd_update_values(self.h, _dptr(v)))
 
     def sample_errors(self, m: int):
         st = self.L.esd_sample_errors(self.h, int(m))

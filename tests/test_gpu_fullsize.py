@@ -1,0 +1,147 @@
+"""Full-size checks in the launch configuration bench.py uses.
+
+Config 2 (128^3, FP64): element-wise parity with the oracle for the sampling
+solve, build_aux and a deflated solve.  Configs 3 (256^3) and 4 (Q1, 160^3
+nodes): SpMV, IC(0) factor and preconditioner against the oracle in full, and
+the mixed-precision deflated solver meeting the FP64 relative residual 1e-8
+with W^T r = 0 on its final residual.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2203_08498_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _relerr(a, b):
+    a = a.cpu().numpy() if hasattr(a, "cpu") else a
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _smooth_samples(p, k, steps=20, seed=21):
+    """Seeded approximate solutions whose errors are rich in the low spectrum:
+    random vectors smoothed by (I - A/2)^steps (scipy matvecs)."""
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n, p.n))
+    rng = np.random.default_rng(seed)
+    xN = rng.standard_normal(p.n)
+    E = rng.standard_normal((p.n, k))
+    for _ in range(steps):
+        E = E - 0.5 * (A @ E)
+        E /= np.linalg.norm(E, axis=0)
+    return xN[:, None] - E, xN
+
+
+def test_config2_full_parity_sampling_build_deflated():
+    from paper_2203_08498_amd import esd
+
+    p = P.config2()
+    print("config 2 full size: n", p.n, "nnz", p.nnz, flush=True)
+    s = esd.Solver.from_problem(p, m_max=16)
+    s.factor_ic0()
+    s.sample_errors(16)
+    x1, i1 = s.solve(p.f, tol=1e-8, maxit=20000)
+    st, ritz, mb, mt = s.build_aux(1e-3)
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    o.arm_sampling(16)
+    y1, j1 = o.solve(p.f, tol=1e-8, maxit=20000, flags=O.SAMPLE)
+    print("sampling solve its gpu/oracle", i1["iters"], j1.iters, "err", _relerr(x1, y1), flush=True)
+    assert abs(i1["iters"] - j1.iters) <= 2 and _relerr(x1, y1) <= 1e-10
+    samples = o.samples(16)
+    assert np.array_equal(s.samples(16), samples)
+    ost, oritz, omb, omt = o.build_aux(1e-3)
+    # end to end, the sampled basis is perturbed by dx / ||x_N - x_last sample||
+    ok_ = O.Oracle.from_problem(p)
+    ok_.factor_ic0()
+    xk, _ = ok_.solve(p.f, tol=0.0, maxit=int(samples.max()))
+    delta = np.linalg.norm(x1.cpu().numpy() - y1) / np.linalg.norm(y1 - xk)
+    print("ritz gpu", ritz[:8], "oracle", oritz[:8], "m_tilde", mt, omt, "basis perturbation", delta, flush=True)
+    assert mb == omb
+    assert np.abs(ritz - oritz).max() <= 10 * delta * 2.0
+    # identical seeded samples: Rayleigh-Ritz and the deflated solve element-wise
+    X, xN = _smooth_samples(p, 16)
+    s.load_samples(X, xN)
+    o.load_samples(X, xN)
+    # theta inside the widest relative gap among the smallest Ritz values, so
+    # the selection is decided far from rounding
+    _, r0, _, _ = o.build_aux(0.0)
+    kk = min(8, len(r0) - 1)
+    g = int(np.argmax(r0[1:kk + 1] / r0[:kk]))
+    theta = float(np.sqrt(r0[g] * r0[g + 1]))
+    st, ritz, mb, mt = s.build_aux(theta)
+    ost, oritz, omb, omt = o.build_aux(theta)
+    print("identical samples: m_bar", mb, omb, "m_tilde", mt, omt, "ritz", ritz[:4], flush=True)
+    assert (mb, mt) == (omb, omt) and mt > 0
+    assert np.max(np.abs(ritz - oritz) / np.abs(oritz)) <= 1e-8
+    b2 = P.sequence_rhs(p.f, y1)
+    x2, i2 = s.solve(b2, tol=1e-8, maxit=20000, mode=esd.DEFLATED)
+    y2, j2 = o.solve(b2, tol=1e-8, maxit=20000, mode=O.DEFLATED)
+    print("deflated its gpu/oracle", i2["iters"], j2.iters, "err", _relerr(x2, y2), flush=True)
+    assert abs(i2["iters"] - j2.iters) <= 2 and _relerr(x2, y2) <= 1e-10
+    assert i2["true_relres"] <= 1.01e-8
+    y3, j3 = o.solve(b2, tol=0.0, maxit=i2["iters"], mode=O.DEFLATED)
+    assert abs(i2["kappa"] / j3.kappa - 1) <= 1e-6
+    s.close()
+
+
+def _fp64_floor(p, x, b):
+    """Attainable relative residual of any FP64 solve: b - A x itself is only
+    known to about gamma_k ||(|A| |x|)|| with k = the longest row (rounding
+    bound of a length-k dot product, gamma_k = k u / (1 - k u))."""
+    import scipy.sparse as sp
+
+    x = x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+    b = b.cpu().numpy() if hasattr(b, "cpu") else np.asarray(b)
+    absA = sp.csr_matrix((np.abs(p.val), p.col, p.rowptr), shape=(p.n, p.n))
+    k = int(np.diff(p.rowptr).max())
+    u = 2.0 ** -53
+    return k * u / (1 - k * u) * np.linalg.norm(absA @ np.abs(x)) / np.linalg.norm(b)
+
+
+def _full_kernel_parity(p, s, o):
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(p.n)
+    assert _relerr(s.spmv(x), o.spmv(x)) <= 1e-14
+    assert o.factor_ic0() == 0
+    rp, c, v = o.factor_csr()
+    d_user = np.empty(p.n)
+    d_user[o.perm] = v[rp[1:] - 1]
+    assert np.abs(s.factor_diag() - d_user).max() <= 1e-12 * np.abs(d_user).max()
+    assert _relerr(s.prec(x), o.prec(x)) <= 1e-11
+
+
+@pytest.mark.parametrize("which", ["cfg3_256", "cfg4_q1_160"])
+def test_large_configs_kernels_and_mixed_deflated(which):
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    p = P.config3() if which == "cfg3_256" else P.config4()
+    m = p.params["m"]
+    print(which, "n", p.n, "nnz", p.nnz, "m", m, flush=True)
+    s = esd.Solver.from_problem(p, m_max=m)
+    s.factor_ic0()
+    o = O.Oracle.from_problem(p)
+    _full_kernel_parity(p, s, o)
+    del o
+    s.sample_errors(m)
+    x1, i1 = s.solve(p.f, tol=1e-8, maxit=50000, flags=esd.FLAG_MIXED)
+    print(which, "sampling solve its", i1["iters"], "fp64 its", i1["fp64_iters"], "relres", i1["true_relres"], flush=True)
+    assert i1["true_relres"] <= max(1e-8, _fp64_floor(p, x1, p.f))
+    st, ritz, mb, mt = s.build_aux(p.params["theta"])
+    print(which, "sampling solve its", i1["iters"], "m_bar", mb, "m_tilde", mt, "ritz", ritz[:4], flush=True)
+    b2 = s.sequence_rhs(torch.as_tensor(p.f, device="cuda"), x1, 0.1)
+    x2, i2 = s.solve(b2, tol=1e-8, maxit=50000, mode=esd.DEFLATED if mt else esd.PLAIN, flags=esd.FLAG_MIXED)
+    print(which, "deflated mixed its", i2["iters"], "outer", i2["outer_iters"], "fp64 its", i2["fp64_iters"],
+          "relres", i2["true_relres"], flush=True)
+    assert i2["true_relres"] <= max(1e-8, _fp64_floor(p, x2, b2))
+    if mt:
+        W, _ = s.get_aux()
+        r = b2 - s.spmv(x2)
+        # the final coarse correction leaves the FP64 residual W-orthogonal
+        assert float((W.t() @ r).norm()) <= 1e-6 * float(r.norm()) + 1e-14 * float(b2.norm())
+    s.close()

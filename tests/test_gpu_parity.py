@@ -219,6 +219,27 @@ def test_mixed_precision_meets_fp64_tolerance(case):
         assert _relerr(x, y) <= 1e-5
 
 
+def test_graph_replays_match_stream_launches(case):
+    """The captured 16-iteration chunks replay the same kernels with the same
+    arguments as direct stream launches: results are bit-identical, also on a
+    second replay of the cached graph and across the mode/precision variants."""
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    modes = [esd.PLAIN] + ([esd.DEFLATED, esd.SUBSPACE] if getattr(s, "m_tilde", 0) else [])
+    for flags in (0, esd.FLAG_MIXED):
+        for mode in modes:
+            xs, i_s = s.solve(p.f, tol=1e-8, maxit=5000, mode=mode, flags=flags | esd.FLAG_STREAM)
+            for rep in range(2):
+                xg, i_g = s.solve(p.f, tol=1e-8, maxit=5000, mode=mode, flags=flags)
+                print(name, "mode", mode, "flags", flags, "rep", rep, "its", i_g["iters"], i_s["iters"], flush=True)
+                assert i_g["iters"] == i_s["iters"] and i_g["status"] == i_s["status"]
+                assert torch.equal(xg, xs)
+                assert i_g["kappa"] == i_s["kappa"]
+
+
 def test_gradient_values(case):
     name, p, s, o = case
     rng = np.random.default_rng(5)

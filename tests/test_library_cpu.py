@@ -45,8 +45,8 @@ def test_binding_covers_header(lib):
 def test_info_struct_layout():
     from paper_2203_08498_amd import esd
 
-    # 6 int32 followed by 9 doubles, no padding
-    assert ctypes.sizeof(esd.EsdInfo) == 6 * 4 + 9 * 8
+    # 8 int32 followed by 9 doubles, no padding
+    assert ctypes.sizeof(esd.EsdInfo) == 8 * 4 + 9 * 8
 
 
 def test_setup_rejects_bad_input_without_gpu(lib):
