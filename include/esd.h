@@ -72,7 +72,8 @@ typedef enum {
                                  residual misses tol (at most 4 restarts) */
 #define ESD_FLAG_STREAM 128   /* launch every kernel on the stream; by default the iterations run as
                                  replays of a captured 16-iteration HIP graph, cached in the context
-                                 (timing and ESD_FLAG_SYNC_EVERY solves always use stream launches) */
+                                 (solves with ESD_FLAG_TIMING, ESD_FLAG_TIMING_SPMV or
+                                 ESD_FLAG_SYNC_EVERY always use stream launches) */
 
 typedef struct {
     int32_t iters;        /* CG iterations (mixed: total inner iterations) */

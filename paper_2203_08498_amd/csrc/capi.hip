@@ -419,18 +419,20 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     };
     constexpr int kChunk = 16;
     hipGraphExec_t ex = nullptr;
-    // kernel timing uses events between launches: stream launches then
+    bool known = false;
+    // kernel timing reads hipEvents recorded between stream launches (events
+    // recorded as graph nodes give no elapsed time): timing solves stay off graphs
     if (c->use_graphs && !o.sync_every && !o.stream_only && !timing) {
         const uint32_t key = (sizeof(T) == 4 ? 1u : 0u) | ((uint32_t)o.kind << 1) | ((uint32_t)o.noprec << 3) |
                              ((uint32_t)o.power << 4) | ((uint32_t)o.sampling << 5) | ((uint32_t)(*vbase & 1) << 6) |
                              ((uint32_t)fuse_l0 << 7);
         for (auto &g : c->graphs)
-            if (g.key == key && g.epoch == c->epoch) ex = g.exec;
-        if (!ex && !c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+            if (g.key == key && g.epoch == c->epoch) { ex = g.exec; known = true; }
+        if (!known && !c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
             c->cap = nullptr;
             c->use_graphs = false;
         }
-        if (!ex && c->cap) {
+        if (!known && c->cap) {
             // capture on the private stream (the caller's may be the null
             // stream, which cannot be captured); replays go to the caller's
             hipGraph_t graph = nullptr;
@@ -446,14 +448,15 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             if (ok) ok = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) == hipSuccess;
             if (graph) (void)hipGraphDestroy(graph);
             (void)hipGetLastError();
-            if (ok) {
-                for (auto it = c->graphs.begin(); it != c->graphs.end();)
-                    if (it->key == key) { (void)hipGraphExecDestroy(it->exec); it = c->graphs.erase(it); } else ++it;
-                c->graphs.push_back({key, c->epoch, ex});
-            } else {
-                ex = nullptr;
-                c->use_graphs = false; // capture unsupported here: stream launches from now on
-            }
+            if (!ok) ex = nullptr; // this variant does not capture: stream launches for it
+            for (auto it = c->graphs.begin(); it != c->graphs.end();)
+                if (it->key == key) {
+                    if (it->exec) (void)hipGraphExecDestroy(it->exec);
+                    it = c->graphs.erase(it);
+                } else {
+                    ++it;
+                }
+            c->graphs.push_back({key, c->epoch, ex});
         }
     }
     int launched = 0;
@@ -899,7 +902,8 @@ void esd_destroy(esd_ctx *c) {
     for (void *p : ptrs) if (p) hipFree(p);
     if (c->Sh) hipHostFree(c->Sh);
     for (auto &e : c->ev) (void)hipEventDestroy(e);
-    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto &g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
 }

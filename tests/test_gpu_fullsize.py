@@ -142,6 +142,9 @@ def test_large_configs_kernels_and_mixed_deflated(which):
     if mt:
         W, _ = s.get_aux()
         r = b2 - s.spmv(x2)
-        # the final coarse correction leaves the FP64 residual W-orthogonal
-        assert float((W.t() @ r).norm()) <= 1e-6 * float(r.norm()) + 1e-14 * float(b2.norm())
+        # the final coarse correction leaves the FP64 residual W-orthogonal, up
+        # to the rounding error of b - A x itself (W has orthonormal columns)
+        floor = _fp64_floor(p, x2, b2) * float(b2.norm())
+        print(which, "||W^T r||", float((W.t() @ r).norm()), "||r||", float(r.norm()), "floor", floor, flush=True)
+        assert float((W.t() @ r).norm()) <= 1e-6 * float(r.norm()) + floor
     s.close()
