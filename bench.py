@@ -12,7 +12,8 @@ One step = factor_ic0 + the whole sequence: system 1 is plain ICCG with
 sampling method A and the power iteration, then build_aux (error vectors,
 Gram-Schmidt, Rayleigh-Ritz, W, C = W^T A W), then systems 2..10 deflated.
 `value` = mean seconds per system of that step (sampling and build included).
-The same sequence solved with plain ICCG throughout is timed beside it.
+The same sequence solved with plain ICCG throughout, and with the FP32/FP64
+mixed deflated solver, is timed beside it (extra fields, not `value`).
 
 Roofline: the dominant kernel is the per-iteration SpMV launch; its duration
 is measured with hipEvents on the solver's stream around every executed
@@ -44,10 +45,12 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
 
 
-def run_sequence(s, p, args, mode, esd, P, timing):
+def run_sequence(s, p, args, mode, esd, P, timing, prec_flags=0):
     """One step: factor + the whole sequence; returns per-system records."""
     import torch
 
@@ -66,14 +69,17 @@ def run_sequence(s, p, args, mode, esd, P, timing):
         bt = s.sequence_rhs(f, x, 0.1)
         if k == 0 and mode != esd.PLAIN:
             s.sample_errors(args.m)
-            x, info = s.solve(bt, tol=args.tol, maxit=20000, flags=esd.FLAG_POWER | flags_t)
+            # K2: the power iteration rides on the SpMV of the first solve only;
+            # later systems report kappa_es with that lambda_max (same A)
+            x, info = s.solve(bt, tol=args.tol, maxit=20000, flags=esd.FLAG_POWER | flags_t | prec_flags)
             tb = time.perf_counter()
             st, ritz, mb, mt = s.build_aux(args.theta)
             info["build_aux_s"] = time.perf_counter() - tb
             info["m_bar"], info["m_tilde_built"] = mb, mt
             info["ritz_min"] = float(ritz[0]) if len(ritz) else 0.0
         else:
-            x, info = s.solve(bt, tol=args.tol, maxit=20000, mode=mode, flags=esd.FLAG_POWER | flags_t)
+            pw = esd.FLAG_POWER if k == 0 else 0
+            x, info = s.solve(bt, tol=args.tol, maxit=20000, mode=mode, flags=pw | flags_t | prec_flags)
         if flags_t:
             tm = s.timing()
             spmv_ms += tm["spmv_ms"] * tm["iters"]
@@ -127,6 +133,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calib:
+        # a plain copy of known size: what the HBM byte counters read for it
+        # calibrates the counters of the solver kernels (256 MiB read + written)
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("# copy calibration: 3 copies of 268435456 bytes", file=sys.stderr, flush=True)
     p = P.config2(N=args.N, m=args.m, systems=args.systems)
     print("# workload %s n=%d nnz=%d" % (p.name, p.n, p.nnz), file=sys.stderr, flush=True)
     s = esd.Solver.from_problem(p, m_max=args.m)
@@ -134,9 +150,10 @@ def main():
     for _ in range(args.warmup):
         run_sequence(s, p, args, esd.DEFLATED, esd, P, False)
         run_sequence(s, p, args, esd.PLAIN, esd, P, False)
+        run_sequence(s, p, args, esd.DEFLATED, esd, P, False, esd.FLAG_MIXED)
         print("# warmup step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    walls, walls_plain, spmv_ms, spmv_n = [], [], 0.0, 0
+    walls, walls_plain, walls_mixed, spmv_ms, spmv_n = [], [], [], 0.0, 0
     recs = recs_plain = None
     for k in range(args.steps):
         recs, wall, sm, sn = run_sequence(s, p, args, esd.DEFLATED, esd, P, True)
@@ -145,7 +162,11 @@ def main():
         spmv_n += sn
         recs_plain, wall_p, _, _ = run_sequence(s, p, args, esd.PLAIN, esd, P, False)
         walls_plain.append(wall_p)
-        print("# step %d: deflated %.4f s, plain %.4f s" % (k, wall, wall_p), file=sys.stderr, flush=True)
+        # the FP32/FP64 mixed deflated solver on the same sequence (context)
+        recs_mixed, wall_m, _, _ = run_sequence(s, p, args, esd.DEFLATED, esd, P, False, esd.FLAG_MIXED)
+        walls_mixed.append(wall_m)
+        print("# step %d: deflated %.4f s, plain %.4f s, mixed deflated %.4f s" % (k, wall, wall_p, wall_m),
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = float(np.mean(walls))
     Tp = float(np.mean(walls_plain))
@@ -157,9 +178,10 @@ def main():
     # roofline of the per-iteration SpMV launch (deflated: W^T q fused in)
     avg_spmv_s = (spmv_ms / max(spmv_n, 1)) * 1e-3
     n, nnz = p.n, p.nnz
-    # matrix (8 B value + 4 B index per stored entry), z and p_old read, p and q
-    # written, the power iterate read and written (W^T q is a separate kernel)
-    bytes_spmv = 12.0 * nnz + 32.0 * n + 16.0 * n
+    # deflated iterations: the projection has written p = zhat + beta p_old, so
+    # the SpMV reads the matrix (8 B value + 4 B index per stored entry) and p,
+    # and writes q (the timed system runs without the power iterate)
+    bytes_spmv = 12.0 * nnz + 16.0 * n
     achieved = bytes_spmv / avg_spmv_s / 1e9 if avg_spmv_s > 0 else 0.0
     out = {
         "metric": "time-to-solution/system at relres 1e-8, deflated vs plain ICCG; SpMV GB/s",
@@ -190,8 +212,12 @@ def main():
         "kappa_cg_last": recs[-1]["kappa"],
         "kappa_es_last": recs[-1]["kappa_es"],
         "true_relres_max": max(r["true_relres"] for r in recs),
+        "mixed_deflated_s_per_system": float(np.mean(walls_mixed)) / args.systems,
+        "mixed_iters_mean": float(np.mean([r["iters"] for r in recs_mixed[1:]])) if len(recs_mixed) > 1 else None,
+        "mixed_fp64_iters_mean": float(np.mean([r["fp64_iters"] for r in recs_mixed])),
+        "mixed_true_relres_max": max(r["true_relres"] for r in recs_mixed),
         "roofline": {
-            "kernel": "k_spmv_it (q = A p with p = z + beta p_old, (p,q), power iterate A v)",
+            "kernel": "k_spmv_it, deflated form (q = A p for the projected direction p, and (p, q))",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -88,7 +88,8 @@ typedef struct {
     double true_relres;   /* ||b - A x||_2 / ||b||_2 recomputed in FP64 */
     double kappa;         /* K1: extreme Lanczos values from the CG alpha/beta */
     double kappa_es;      /* K2: power-method lambda_max / smallest Ritz value (Sec. 5.4) */
-    double lambda_max;    /* (v, A v) of the power iteration (0 without ESD_FLAG_POWER) */
+    double lambda_max;    /* (v, A v) of the power iteration of this solve, or of the last solve on
+                             the current values that ran it (ESD_FLAG_POWER); 0 if none did */
     double lambda_min_ritz; /* smallest Ritz value of the last build_aux (0 if none) */
     double lanczos_min, lanczos_max; /* extreme eigenvalues of the Lanczos matrix */
     double seconds;       /* wall time of the solve on the stream (hipEvent) */

@@ -92,6 +92,7 @@ struct esd_ctx {
     std::vector<double> Ch, ritz;
     // power iteration state
     bool have_v = false;
+    double lam_last = 0.0; // lambda_max of the last solve that ran the power iteration
     int vb64 = 0, vb32 = 0;
     double vs64 = 1.0, vs32 = 1.0;
     // history of the last solve
@@ -322,7 +323,8 @@ struct KrylovOpts {
 // number of completed iterations through *iters and the exit code in Sh->done.
 //
 // Deflation iterates with projected directions: after the preconditioner,
-// zhat = P z = z - W C^{-1} (AW)^T z, p = zhat + beta p, q = A p; then
+// zhat = P z = z - W C^{-1} (AW)^T z and p = zhat + beta p in one pass, then
+// q = A p; so
 // (p, q) = (p, P^T A p) without cancellation and r -= alpha q is the deflated
 // residual update of the deflated PCG (P^T A = A P for symmetric A).  The
 // range(W) part of x is fixed by the final correction.
@@ -338,8 +340,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     esd::TsDot<T> ta{};
     ta.n = n; ta.m = m; ta.Wrm = defl ? V.AWrm : V.Wrm; ta.v = defl ? V.z : V.r; ta.part = c->part_ts; ta.S = c->S;
     esd::Proj<T> pa{};
-    pa.n = n; pa.m = m; pa.S = c->S; pa.z = V.z; pa.W = V.W; pa.zhat = V.zsc;
-    // z_0 = M^{-1} r_0 (+ W u), rho_0 (and zhat_0 for deflation)
+    pa.n = n; pa.m = m; pa.S = c->S; pa.z = V.z; pa.W = V.W;
+    // z_0 = M^{-1} r_0 (+ W u), rho_0 (and p_0 = zhat_0 for deflation)
     {
         const int ns = launch_prec<T>(c, V, o.noprec, sc);
         if (defl) esd::launch_tsdot_rm(ta, gt, c->stream);
@@ -347,7 +349,11 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
         fr.S = c->S; fr.part_sweep = c->part_sweep; fr.nsweep = ns; fr.init = 1;
         fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
         esd::launch_fin_rho(fr, c->stream);
-        if (defl) esd::launch_proj(pa, gn, c->stream);
+        if (defl) {
+            pa.pold = V.p[0];
+            pa.pnew = V.p[1];
+            esd::launch_proj(pa, gn, c->stream);
+        }
     }
     const int sstride = esd::spmv_stride(o.power);
     const int gs = esd::grid_red(n, sstride);
@@ -356,7 +362,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     const bool fuse_l0 = !o.noprec && nl >= 2;
     esd::SpmvIt<T> sa{};
     sa.n = n; sa.S = c->S; sa.part = c->part_spmv; sa.A = V.A;
-    sa.z = (sc || defl) ? V.zsc : V.z;
+    sa.z = defl ? nullptr : (sc ? V.zsc : V.z); // deflation: p_new given by the projection
     sa.slot_table = o.sampling ? c->slot_table : nullptr;
     sa.slots = c->slots;
     sa.xit = V.x;
@@ -400,7 +406,12 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 3], c->stream)) != hipSuccess) return e;
             if (defl) esd::launch_tsdot_rm(ta, gt, c->stream);
             esd::launch_fin_rho(fr, c->stream);
-            if (defl) esd::launch_proj(pa, gn, c->stream);
+            if (defl) {
+                // direction of iteration it + 1
+                pa.pold = V.p[(it + 1) & 1];
+                pa.pnew = V.p[it & 1];
+                esd::launch_proj(pa, gn, c->stream);
+            }
         }
         return hipGetLastError();
     };
@@ -1059,6 +1070,7 @@ esd_status esd_update_values(esd_ctx *c, const double *val) {
     esd::launch_map_values(c->n, c->d_src, val, c->adiag, nullptr, c->stream);
     HIPCHK(hipGetLastError());
     c->factored = false;
+    c->lam_last = 0.0;
     if (c->aux_built && c->m_tilde > 0) {
         // keep W, refresh AW = A W and C = W^T A W for the new values
         esd::launch_spmm((int)c->n, c->A.e64(), c->W, c->m_tilde, c->AW, c->stream);
@@ -1143,7 +1155,8 @@ esd_status esd_solve(esd_ctx *c, const double *b, const double *x0, double tol, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     inf->seconds = ms * 1e-3;
-    inf->lambda_max = (flags & ESD_FLAG_POWER) ? c->Sh->lam : 0.0;
+    if ((flags & ESD_FLAG_POWER) && st >= 0) c->lam_last = c->Sh->lam;
+    inf->lambda_max = c->lam_last;
     inf->lambda_min_ritz = c->ritz.empty() ? 0.0 : c->ritz[0];
     inf->kappa_es = (inf->lambda_min_ritz > 0 && inf->lambda_max > 0) ? inf->lambda_max / inf->lambda_min_ritz : 0.0;
     if (st < 0) return st;

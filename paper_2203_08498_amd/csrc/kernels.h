@@ -11,6 +11,7 @@ constexpr int kMaxGrid = 8192;  // largest grid of a reducing kernel
 constexpr int kMaxNV = 72;      // largest number of values reduced together
 constexpr int kFinThreads = 1024; // threads of a finalize kernel
 constexpr int kPartBudget = 48 * 1024; // doubles a finalize kernel reads at most
+constexpr int kTsBlock = 1024;        // threads per block of the tall-skinny W^T v kernel
 
 // Solver scalars kept in device memory; every per-iteration quantity (rho,
 // alpha, beta, the coarse vectors, the stop decision) is produced and
@@ -52,6 +53,8 @@ template <typename T> struct Ell {
 // one iteration's SpMV: p_new = z + beta p_old (p_new = z on the first
 // iteration), q = A p_new; partials (p_new, q) and ||v_new||^2; optional power
 // iterate v_new = A v_old / ||v_old||; optional sampling store of the iterate.
+// With z == nullptr the direction p_new is given (written by the deflation
+// projection) and only gathered.
 template <typename T> struct SpmvIt {
     int n;
     Scal *S;
@@ -135,13 +138,15 @@ struct FinRho {
     const double *Cinv;
 };
 
-// zhat = z - W mu (W column-major n x m, mu = S->mu): the projected
-// preconditioned residual of the deflated iteration
+// zhat = z - W mu (W column-major n x m, mu = S->mu), the projected
+// preconditioned residual of the deflated iteration, and the next direction
+// p_new = zhat + beta p_old (p_new = zhat before the first iteration)
 template <typename T> struct Proj {
     int n, m;
     const Scal *S;
     const T *z, *W;
-    T *zhat;
+    const T *pold;
+    T *pnew;
 };
 // generic finalize of a per-solve reduction: tot[k] = column sums
 struct FinGen {

@@ -61,26 +61,45 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *part, in
     }
 }
 
-// Column sums of an nblk x stride partial table, columns [c0, c0 + nc), into
-// tot[0 .. nc) (shared).  Thread t handles column c0 + t % P2 and the rows
-// congruent to t / P2 modulo kFinThreads / P2; the row groups are then added
-// pairwise in a fixed tree.  Must be called by all kFinThreads threads.
-__device__ void fin_colsum(const double *part, int nblk, int stride, int c0, int nc, double *tot) {
-    __shared__ double buf[kFinThreads];
+// One partial table for the finalize kernels: columns [c0, c0 + nc) of an
+// nblk x stride row-major table, summed into tot[0 .. nc) (shared or global).
+struct ColTab {
+    const double *part;
+    int nblk, stride, c0, nc;
+    double *tot;
+};
+
+// Column sums of NTAB <= 4 tables at once; must be called by all kFinThreads
+// threads.  The threads are split into equal slots, one per table.  In a slot
+// of NT threads, thread t handles column t % p2 (p2 = nc rounded up to a power
+// of two) and rows congruent to t / p2 modulo NT / p2, with 16 loads in flight;
+// lanes of one column are then added by shuffles in a fixed pattern and the
+// slot's waves through LDS, always in the same order (deterministic).
+template <int NTAB>
+__device__ void fin_colsums(const ColTab (&tab)[NTAB]) {
+    constexpr int SLOTS = NTAB <= 1 ? 1 : (NTAB <= 2 ? 2 : 4);
+    constexpr int NT = kFinThreads / SLOTS;
+    constexpr int WPS = NT / 64;
+    static_assert(NTAB >= 1 && NTAB <= 4, "at most four tables");
+    __shared__ double red[kFinThreads / 64][64];
+    const int slot = threadIdx.x / NT, t = threadIdx.x % NT;
+    const int lane = threadIdx.x & 63, wv = t >> 6;
+    ColTab T = tab[0];
+#pragma unroll
+    for (int q = 1; q < NTAB; ++q)
+        if (slot == q) T = tab[q];
+    const bool active = slot < NTAB;
     int p2 = 1;
-    while (p2 < nc) p2 <<= 1;
-    const int groups = kFinThreads / p2;
-    const int t = threadIdx.x, k = t % p2, g = t / p2;
+    while (p2 < T.nc) p2 <<= 1;
+    const int groups = NT / p2, k = t % p2, g = t / p2;
     double acc = 0.0;
-    if (k < nc) {
-        // all loads of a round are issued before any add: one memory latency
-        // per 16 rows instead of one per row
-        for (int j0 = g; j0 < nblk; j0 += 16 * groups) {
+    if (active && k < T.nc) {
+        for (int j0 = g; j0 < T.nblk; j0 += 16 * groups) {
             double v[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int j = j0 + u * groups;
-                v[u] = (j < nblk) ? part[(size_t)j * stride + c0 + k] : 0.0;
+                v[u] = (j < T.nblk) ? T.part[(size_t)j * T.stride + T.c0 + k] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 16; u += 2) v[u] += v[u + 1];
@@ -89,14 +108,28 @@ __device__ void fin_colsum(const double *part, int nblk, int stride, int c0, int
             acc += (v[0] + v[4]) + (v[8] + v[12]);
         }
     }
-    buf[t] = acc;
+    // lanes l and l ^ off hold the same column for off >= p2
+    for (int off = 32; off >= p2; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    red[threadIdx.x >> 6][lane] = acc;
     __syncthreads();
-    for (int h = groups / 2; h >= 1; h >>= 1) {
-        if (g < h) buf[t] += buf[t + h * p2];
-        __syncthreads();
+    if (active && t < T.nc) {
+        double sum = 0.0;
+        if (p2 <= 64) {
+            for (int w = 0; w < WPS; ++w) sum += red[slot * WPS + w][t];
+        } else {
+            for (int q = 0; q < groups; ++q) {
+                const int u = q * p2 + t;
+                sum += red[slot * WPS + (u >> 6)][u & 63];
+            }
+        }
+        T.tot[t] = sum;
     }
-    if (t < nc) tot[t] = buf[t];
     __syncthreads();
+}
+
+__device__ __forceinline__ void fin_colsum(const double *part, int nblk, int stride, int c0, int nc, double *tot) {
+    const ColTab tab[1] = {{part, nblk, stride, c0, nc, tot}};
+    fin_colsums<1>(tab);
 }
 
 // ------------------------------------------------------------------------
@@ -171,13 +204,13 @@ __device__ __forceinline__ void ell_dot2(const Ell<T> &M, int i, int n, G1 g1, G
     }
 }
 
-template <typename T, bool POW>
+template <typename T, bool POW, bool PG>
 __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
     const int iter = S->iter;
     const bool first = (iter == 0);
-    const T beta = first ? T(0) : (T)S->beta;
+    const T beta = (first || PG) ? T(0) : (T)S->beta;
     const T vs = POW ? (T)S->vscale : T(0);
     int slot = -1;
     if (a.slot_table && iter >= 1) slot = a.slot_table[S->sample_base + iter];
@@ -186,22 +219,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
     const int n = a.n;
-    const T *z = a.z, *po = a.pold, *vo = a.vold;
+    const T *z = a.z, *po = a.pold, *vo = a.vold, *pg = a.pnew;
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = t * kBlock + threadIdx.x;
         if (i >= n) continue;
-        T sum, vsum = T(0);
-        if (first) {
-            if constexpr (POW) ell_dot2(a.A, i, n, [&](int c) { return z[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
-            else sum = ell_dot(a.A, i, n, [&](int c) { return z[c]; });
+        T sum, vsum = T(0), pi;
+        if constexpr (PG) {
+            if constexpr (POW) ell_dot2(a.A, i, n, [&](int c) { return pg[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
+            else sum = ell_dot(a.A, i, n, [&](int c) { return pg[c]; });
+            pi = pg[i];
         } else {
-            if constexpr (POW)
-                ell_dot2(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
-            else sum = ell_dot(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; });
+            if (first) {
+                if constexpr (POW)
+                    ell_dot2(a.A, i, n, [&](int c) { return z[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
+                else sum = ell_dot(a.A, i, n, [&](int c) { return z[c]; });
+            } else {
+                if constexpr (POW)
+                    ell_dot2(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; }, [&](int c) { return vo[c]; },
+                             sum, vsum);
+                else sum = ell_dot(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; });
+            }
+            pi = first ? z[i] : z[i] + beta * po[i];
+            a.pnew[i] = pi;
         }
-        const T pi = first ? z[i] : z[i] + beta * po[i];
-        a.pnew[i] = pi;
         a.q[i] = sum;
         acc[0] += (double)pi * (double)sum;
         if constexpr (POW) {
@@ -250,12 +291,14 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
     block_partials<1>(acc, a.part, 1);
 }
 
-// s = W^T v, W row-major n x m; P = next power of two >= m
+// s = W^T v, W row-major n x m; P = next power of two >= m.  Lane l of a
+// wavefront takes column l % P of rows l / P, l / P + 64 / P, ...; blocks of
+// kTsBlock threads keep the partial table (one row of P per block) short.
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_tsdot_rm(TsDot<T> a) {
+__global__ __launch_bounds__(kTsBlock) void k_tsdot_rm(TsDot<T> a) {
     if (a.S && a.S->done) return;
     constexpr int RPW = 64 / P;      // rows per wavefront step
-    constexpr int WAVES = kBlock / 64;
+    constexpr int WAVES = kTsBlock / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int k = lane % P, ro = lane / P;
     const int m = a.m, n = a.n;
@@ -372,16 +415,27 @@ __global__ __launch_bounds__(kBlock) void k_copyz(Sweep<T> a) {
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(FinAlpha f) {
     Scal *S = f.S;
-    if (S->done) return;
     __shared__ double tot[2];
     __shared__ double sv[64];
     __shared__ double mus[64];
-    fin_colsum(f.part, f.nblk, f.stride, 0, f.stride, tot);
-    if (f.m > 0) fin_colsum(f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv);
+    __shared__ double cinv[64 * 64];
+    const int done0 = S->done;
     const int t = threadIdx.x;
+    double rho = 0.0;
+    int iter = 0, hbase = 0;
+    if (t == 0) { rho = S->rho; iter = S->iter; hbase = S->hist_base; }
+    const int mm = f.m * f.m;
+    for (int k = t; k < mm; k += kFinThreads) cinv[k] = f.Cinv[k];
+    if (f.m > 0) {
+        const ColTab tab[2] = {{f.part, f.nblk, f.stride, 0, f.stride, tot}, {f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv}};
+        fin_colsums<2>(tab);
+    } else {
+        fin_colsum(f.part, f.nblk, f.stride, 0, f.stride, tot);
+    }
+    if (done0) return;
     if (t < f.m) {
         double acc = 0.0;
-        for (int j = 0; j < f.m; ++j) acc += f.Cinv[t * f.m + j] * sv[j];
+        for (int j = 0; j < f.m; ++j) acc += cinv[t * f.m + j] * sv[j];
         mus[t] = acc;
         S->mu[t] = acc;
     }
@@ -389,9 +443,9 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(FinAlpha f) {
     if (t == 0) {
         double denom = tot[0];
         for (int k = 0; k < f.m; ++k) denom -= sv[k] * mus[k];
-        const double alpha = S->rho / denom;
+        const double alpha = rho / denom;
         S->alpha = alpha;
-        if (f.hist_alpha) f.hist_alpha[S->hist_base + S->iter] = alpha;
+        if (f.hist_alpha) f.hist_alpha[hbase + iter] = alpha;
         if (!isfinite(alpha)) S->done = 3;
         if (f.power) S->vscale = 1.0 / sqrt(tot[1]);
     }
@@ -412,21 +466,42 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_u(Scal *S, const double *pa
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
     Scal *S = f.S;
-    if (S->done) return;
     __shared__ double tot[2];
     __shared__ double sv[64];
-    fin_colsum(f.part_sweep, f.nsweep, 1, 0, 1, tot + 1);
-    if (!f.init) fin_colsum(f.part_upd, f.nblk_upd, f.stride_upd, 0, 1, tot);
-    if (f.m > 0) {
-        fin_colsum(f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv);
-        const int t = threadIdx.x;
-        if (t < f.m) {
-            double acc = 0.0;
-            for (int j = 0; j < f.m; ++j) acc += f.Cinv[t * f.m + j] * sv[j];
-            S->mu[t] = acc;
+    __shared__ double cinv[64 * 64];
+    // every load of the scalar block and of C^{-1} is issued before the
+    // partial sums, so their latencies overlap; nothing is written while
+    // `done` is set
+    const int done0 = S->done;
+    const int t = threadIdx.x;
+    double rho_old = 0.0, tol2 = 0.0, rr_ref = 0.0;
+    int iter = 0, maxit = 0, stag = 0, it_ref = 0, hbase = 0;
+    if (t == 0) {
+        rho_old = S->rho; tol2 = S->tol2; rr_ref = S->rr_ref;
+        iter = S->iter; maxit = S->maxit; stag = S->stag_window; it_ref = S->it_ref; hbase = S->hist_base;
+    }
+    const int mm = f.m * f.m;
+    for (int k = t; k < mm; k += kFinThreads) cinv[k] = f.Cinv[k];
+    {
+        // (r, z), (r, r) and, for deflation, (AW)^T z in one pass
+        const int nu = f.init ? 0 : f.nblk_upd;
+        if (f.m > 0) {
+            const ColTab tab[3] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 1},
+                                   {f.part_upd, nu, f.stride_upd, 0, 1, tot},
+                                   {f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv}};
+            fin_colsums<3>(tab);
+        } else {
+            const ColTab tab[2] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 1}, {f.part_upd, nu, f.stride_upd, 0, 1, tot}};
+            fin_colsums<2>(tab);
         }
     }
-    if (threadIdx.x == 0) {
+    if (done0) return;
+    if (t < f.m) {
+        double acc = 0.0;
+        for (int j = 0; j < f.m; ++j) acc += cinv[t * f.m + j] * sv[j];
+        S->mu[t] = acc;
+    }
+    if (t == 0) {
         const double rn = tot[1];
         if (f.init) {
             S->rho = rn;
@@ -434,35 +509,38 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
             return;
         }
         const double rr = tot[0];
-        const int it = S->iter + 1;
+        const int it = iter + 1;
         S->iter = it;
         S->rr = rr;
         int d = 0;
         if (!(rr <= DBL_MAX) || !isfinite(rn)) d = 3;
-        else if (rr <= S->tol2) d = 1;
-        else if (it >= S->maxit) d = 2;
-        else if (S->stag_window > 0) {
-            if (rr < 0.81 * S->rr_ref) {
+        else if (rr <= tol2) d = 1;
+        else if (it >= maxit) d = 2;
+        else if (stag > 0) {
+            if (rr < 0.81 * rr_ref) {
                 S->rr_ref = rr;
                 S->it_ref = it;
-            } else if (it - S->it_ref >= S->stag_window) {
+            } else if (it - it_ref >= stag) {
                 d = 4;
             }
         }
         S->done = d;
-        const double b = rn / S->rho;
+        const double b = rn / rho_old;
         S->beta = b;
-        if (f.hist_beta) f.hist_beta[S->hist_base + it - 1] = b;
+        if (f.hist_beta) f.hist_beta[hbase + it - 1] = b;
         S->rho = rn;
     }
 }
 
 template <typename T, int MT>
 __global__ __launch_bounds__(kBlock) void k_proj(Proj<T> a) {
-    if (a.S->done) return;
+    const Scal *S = a.S;
+    if (S->done) return;
+    const bool first = (S->iter == 0);
+    const T beta = first ? T(0) : (T)S->beta;
     double mu[MT];
 #pragma unroll
-    for (int k = 0; k < MT; ++k) mu[k] = (k < a.m) ? a.S->mu[k] : 0.0;
+    for (int k = 0; k < MT; ++k) mu[k] = (k < a.m) ? S->mu[k] : 0.0;
     const int n = a.n;
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
@@ -472,7 +550,8 @@ __global__ __launch_bounds__(kBlock) void k_proj(Proj<T> a) {
 #pragma unroll
         for (int k = 0; k < MT; ++k)
             if (k < a.m) s -= (double)a.W[(size_t)k * n + i] * mu[k];
-        a.zhat[i] = (T)s;
+        const T zh = (T)s;
+        a.pnew[i] = first ? zh : zh + beta * a.pold[i];
     }
 }
 
@@ -887,8 +966,8 @@ static int pow2_at_least(int m) {
 }
 int tsdot_stride(int m) { return pow2_at_least(m); }
 int tsdot_grid(int64_t n, int m) {
-    int64_t g = (n + 1023) / 1024;
-    if (g > 2048) g = 2048;
+    int64_t g = (n + 4095) / 4096;
+    if (g > 512) g = 512;
     const int cap = kPartBudget / pow2_at_least(m);
     if (g > cap) g = cap;
     if (g > 8) g = g / 8 * 8;
@@ -896,8 +975,13 @@ int tsdot_grid(int64_t n, int m) {
 }
 
 template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, bool power, int grid, hipStream_t s) {
-    if (power) k_spmv_it<T, true><<<grid, kBlock, 0, s>>>(a);
-    else k_spmv_it<T, false><<<grid, kBlock, 0, s>>>(a);
+    if (a.z) {
+        if (power) k_spmv_it<T, true, false><<<grid, kBlock, 0, s>>>(a);
+        else k_spmv_it<T, false, false><<<grid, kBlock, 0, s>>>(a);
+    } else {
+        if (power) k_spmv_it<T, true, true><<<grid, kBlock, 0, s>>>(a);
+        else k_spmv_it<T, false, true><<<grid, kBlock, 0, s>>>(a);
+    }
 }
 void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
@@ -920,13 +1004,13 @@ void launch_proj(const Proj<float> &a, int grid, hipStream_t s) { proj_impl(a, g
 
 template <typename T> static void tsdot_impl(const TsDot<T> &a, int grid, hipStream_t s) {
     switch (pow2_at_least(a.m)) {
-    case 1: k_tsdot_rm<T, 1><<<grid, kBlock, 0, s>>>(a); break;
-    case 2: k_tsdot_rm<T, 2><<<grid, kBlock, 0, s>>>(a); break;
-    case 4: k_tsdot_rm<T, 4><<<grid, kBlock, 0, s>>>(a); break;
-    case 8: k_tsdot_rm<T, 8><<<grid, kBlock, 0, s>>>(a); break;
-    case 16: k_tsdot_rm<T, 16><<<grid, kBlock, 0, s>>>(a); break;
-    case 32: k_tsdot_rm<T, 32><<<grid, kBlock, 0, s>>>(a); break;
-    default: k_tsdot_rm<T, 64><<<grid, kBlock, 0, s>>>(a); break;
+    case 1: k_tsdot_rm<T, 1><<<grid, kTsBlock, 0, s>>>(a); break;
+    case 2: k_tsdot_rm<T, 2><<<grid, kTsBlock, 0, s>>>(a); break;
+    case 4: k_tsdot_rm<T, 4><<<grid, kTsBlock, 0, s>>>(a); break;
+    case 8: k_tsdot_rm<T, 8><<<grid, kTsBlock, 0, s>>>(a); break;
+    case 16: k_tsdot_rm<T, 16><<<grid, kTsBlock, 0, s>>>(a); break;
+    case 32: k_tsdot_rm<T, 32><<<grid, kTsBlock, 0, s>>>(a); break;
+    default: k_tsdot_rm<T, 64><<<grid, kTsBlock, 0, s>>>(a); break;
     }
 }
 void launch_tsdot_rm(const TsDot<double> &a, int grid, hipStream_t s) { tsdot_impl(a, grid, s); }
