@@ -90,6 +90,28 @@ def run_sequence(s, p, args, mode, esd, P, timing, prec_flags=0):
     return recs, wall, spmv_ms, spmv_n
 
 
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None
+    when the summary is missing, covers another kernel, or was taken from other
+    kernel sources than the ones built now."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_spmv_it_fv3d128_hbm_counters.txt")
+    src = os.path.join(ROOT, "paper_2203_08498_amd", "csrc")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256(open(os.path.join(src, "kernels.hip"), "rb").read()
+                           + open(os.path.join(src, "kernels.h"), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.split(": ", 1)[0] in ("traffic_kernel", "traffic_bytes_per_launch", "kernels_sha256"))
+    if fields.get("kernels_sha256") != h or fields.get("traffic_kernel") != kernel:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(p, args, mt, iters_per_system):
     """Oracle (plain C, 1 thread): a bounded number of deflated PCG iterations
     on the same matrix with a seeded random W of the same width."""
@@ -223,7 +245,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": counter_traffic("k_spmv_it<double, false, true>") if args.N == 128 else None,
             "bytes_per_launch": bytes_spmv,
             "avg_launch_us": avg_spmv_s * 1e6,
             "launches": spmv_n,

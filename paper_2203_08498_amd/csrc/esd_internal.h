@@ -41,6 +41,17 @@ struct HostLayout {
 std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                          const int32_t *colors, HostLayout &out);
 
+// Order in which row tiles of `tile_rows` rows are handed to blocks, for the
+// whole row range and for every level.  Rows are grouped in segments of equal
+// (level, colour); a tile's key is the eighth of its segment that holds its
+// first row, and tiles are ordered by key (stably).  Blocks are remapped so
+// that each XCD takes one contiguous eighth of the order: it then works on
+// the same spatial eighth of every colour, whose neighbours lie in the same
+// eighth of the other colours, so gathered vectors are fetched into one XCD's
+// L2 instead of several.  `lvl_off[l]` is the start of level l's order.
+void tile_orders(const HostLayout &H, const int32_t *colors, int tile_rows, std::vector<int32_t> &full,
+                 std::vector<int32_t> &lvl, std::vector<int64_t> &lvl_off);
+
 // Sampling method A: slot of iteration i (>= 1) for m slots, and the table of
 // slots (or -1) for iterations 0..maxit.
 int sampling_slot(int64_t i, int m);

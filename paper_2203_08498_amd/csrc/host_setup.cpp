@@ -338,4 +338,49 @@ void tridiag_extremes(int k, const double *alpha, const double *beta, double *tm
     *tmax = bisect(k);
 }
 
+
+void tile_orders(const HostLayout &H, const int32_t *colors, int tile_rows, std::vector<int32_t> &full,
+                 std::vector<int32_t> &lvl, std::vector<int64_t> &lvl_off) {
+    const int64_t n = H.n;
+    const int nl = (int)H.lvl_ptr.size() - 1;
+    // segment of every physical row: runs of equal (level, colour)
+    std::vector<int64_t> seg_start(n), seg_len(n);
+    for (int l = 0; l < nl; ++l) {
+        int64_t a = H.lvl_ptr[l];
+        const int64_t e = H.lvl_ptr[l + 1];
+        while (a < e) {
+            int64_t b = a + 1;
+            if (colors)
+                while (b < e && colors[H.p2u[b]] == colors[H.p2u[a]]) ++b;
+            else
+                b = e;
+            for (int64_t p = a; p < b; ++p) {
+                seg_start[p] = a;
+                seg_len[p] = b - a;
+            }
+            a = b;
+        }
+    }
+    auto order = [&](int64_t r0, int64_t r1, std::vector<int32_t> &out) {
+        const int64_t nt = (r1 - r0 + tile_rows - 1) / tile_rows;
+        std::vector<std::vector<int32_t>> byk(8);
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t p = r0 + t * tile_rows;
+            const int k = (int)std::min<int64_t>(7, 8 * (p - seg_start[p]) / seg_len[p]);
+            byk[k].push_back((int32_t)t);
+        }
+        for (auto &v : byk) out.insert(out.end(), v.begin(), v.end());
+    };
+    full.clear();
+    lvl.clear();
+    lvl_off.assign(nl + 1, 0);
+    if (n == 0) return;
+    order(0, n, full);
+    for (int l = 0; l < nl; ++l) {
+        lvl_off[l] = (int64_t)lvl.size();
+        order(H.lvl_ptr[l], H.lvl_ptr[l + 1], lvl);
+    }
+    lvl_off[nl] = (int64_t)lvl.size();
+}
+
 } // namespace esd

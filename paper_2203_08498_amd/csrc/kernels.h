@@ -68,6 +68,7 @@ template <typename T> struct SpmvIt {
     double *slots;
     const T *xit;
     const double *xbase;
+    const int32_t *tmap; // tile order (nullptr: natural)
 };
 
 // x += alpha p; r -= alpha w with w = q (plain, SC) or q - AW mu (deflated);
@@ -84,6 +85,7 @@ template <typename T> struct UpdIt {
     int l0;      // rows of the first sweep level fused here (0 = none)
     const T *dinv;
     T *y;
+    const int32_t *tmap; // tile order (nullptr: natural)
 };
 
 // Tall-skinny s = W^T v with W row-major (n x m, W[i m + k]): lane t of a
@@ -110,6 +112,7 @@ template <typename T> struct Sweep {
     T *y, *z, *zsc;
     const T *W;
     int m;        // > 0: subspace correction adds W u to zsc
+    const int32_t *tmap; // tile order within [r0, r1) (nullptr: natural)
 };
 
 // finalize after the SpMV: alpha = rho / ((p,q) - s^T C^{-1} s), mu = C^{-1} s
@@ -147,6 +150,7 @@ template <typename T> struct Proj {
     const T *z, *W;
     const T *pold;
     T *pnew;
+    const int32_t *tmap; // tile order (nullptr: natural)
 };
 // generic finalize of a per-solve reduction: tot[k] = column sums
 struct FinGen {

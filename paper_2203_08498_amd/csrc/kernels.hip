@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
     const T *z = a.z, *po = a.pold, *vo = a.vold, *pg = a.pnew;
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
-        const int i = t * kBlock + threadIdx.x;
+        const int i = (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= n) continue;
         T sum, vsum = T(0), pi;
         if constexpr (PG) {
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
     }
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
-        const int i = t * kBlock + threadIdx.x;
+        const int i = (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= n) continue;
         T wi = a.q[i];
         if constexpr (KIND == 1) {
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(Sweep<T> a) {
     const T *y = a.y;
     const Tiles tl = my_tiles(a.r1 - a.r0);
     for (int t = tl.t0; t < tl.t1; ++t) {
-        const int i = a.r0 + t * kBlock + threadIdx.x;
+        const int i = a.r0 + (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= a.r1) continue;
         const T ri = a.r[i];
         const T s = ri - ell_dot(a.M, i, a.n, [&](int c) { return y[c]; });
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
     const T *z = a.z;
     const Tiles tl = my_tiles(a.r1 - a.r0);
     for (int t = tl.t0; t < tl.t1; ++t) {
-        const int i = a.r0 + t * kBlock + threadIdx.x;
+        const int i = a.r0 + (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= a.r1) continue;
         const T s = a.y[i] - ell_dot(a.M, i, a.n, [&](int c) { return z[c]; });
         const T zi = s * a.dinv[i];
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_copyz(Sweep<T> a) {
     double acc[1] = {0.0};
     const Tiles tl = my_tiles(a.r1 - a.r0);
     for (int t = tl.t0; t < tl.t1; ++t) {
-        const int i = a.r0 + t * kBlock + threadIdx.x;
+        const int i = a.r0 + (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= a.r1) continue;
         const T ri = a.r[i];
         a.z[i] = ri;
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_proj(Proj<T> a) {
     const int n = a.n;
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
-        const int i = t * kBlock + threadIdx.x;
+        const int i = (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= n) continue;
         double s = (double)a.z[i];
 #pragma unroll
