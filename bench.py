@@ -12,13 +12,16 @@ One step = factor_ic0 + the whole sequence: system 1 is plain ICCG with
 sampling method A and the power iteration, then build_aux (error vectors,
 Gram-Schmidt, Rayleigh-Ritz, W, C = W^T A W), then systems 2..10 deflated.
 `value` = mean seconds per system of that step (sampling and build included).
-The same sequence solved with plain ICCG throughout, and with the FP32/FP64
-mixed deflated solver, is timed beside it (extra fields, not `value`).
+Timed beside it on the same sequence (extra fields, not `value`): plain ICCG
+throughout, the subspace-correction preconditioner, and the FP32/FP64 mixed
+deflated solver.
 
 Roofline: the dominant kernel is the per-iteration SpMV launch; its duration
 is measured with hipEvents on the solver's stream around every executed
 launch of system 2 (the first deflated solve) of each timed step, which runs
 with stream launches; all other solves replay the captured iteration graphs.
+The same events bracket the IC(0) sweep launches of each iteration (sweeps
+GB/s).  `traffic` comes from the committed rocprofv3 counter summary.
 cpu_baseline: the FP64 C oracle, one thread.
 """
 import argparse
@@ -51,21 +54,22 @@ def parse():
 
 
 def run_sequence(s, p, args, mode, esd, P, timing, prec_flags=0):
-    """One step: factor + the whole sequence; returns per-system records."""
+    """One step: factor + the whole sequence; returns per-system records, the
+    wall time and the kernel timings of the timed system."""
     import torch
 
-    # SpMV launch timing (hipEvents between stream launches) on one system of
-    # the step; every other solve replays the captured iteration graphs
+    # kernel timing (hipEvents between stream launches) on one system of the
+    # step; every other solve replays the captured iteration graphs
     t_sys = min(1, args.systems - 1)
     recs = []
+    tm = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.factor_ic0()
     x = None
-    spmv_ms, spmv_n = 0.0, 0
     f = torch.as_tensor(p.f, device=s.device)
     for k in range(args.systems):
-        flags_t = esd.FLAG_TIMING_SPMV if (timing and k == t_sys) else 0
+        flags_t = esd.FLAG_TIMING if (timing and k == t_sys) else 0
         bt = s.sequence_rhs(f, x, 0.1)
         if k == 0 and mode != esd.PLAIN:
             s.sample_errors(args.m)
@@ -76,18 +80,16 @@ def run_sequence(s, p, args, mode, esd, P, timing, prec_flags=0):
             st, ritz, mb, mt = s.build_aux(args.theta)
             info["build_aux_s"] = time.perf_counter() - tb
             info["m_bar"], info["m_tilde_built"] = mb, mt
-            info["ritz_min"] = float(ritz[0]) if len(ritz) else 0.0
+            info["ritz"] = [float(v) for v in ritz[:mb]]
         else:
             pw = esd.FLAG_POWER if k == 0 else 0
             x, info = s.solve(bt, tol=args.tol, maxit=20000, mode=mode, flags=pw | flags_t | prec_flags)
         if flags_t:
             tm = s.timing()
-            spmv_ms += tm["spmv_ms"] * tm["iters"]
-            spmv_n += tm["iters"]
         recs.append(info)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return recs, wall, spmv_ms, spmv_n
+    return recs, wall, tm
 
 
 def counter_traffic(kernel):
@@ -169,42 +171,58 @@ def main():
     print("# workload %s n=%d nnz=%d" % (p.name, p.n, p.nnz), file=sys.stderr, flush=True)
     s = esd.Solver.from_problem(p, m_max=args.m)
     s.set_power_start(P.power_start(2, p.n))
+    seqs = (("deflated", esd.DEFLATED, 0), ("plain", esd.PLAIN, 0), ("subspace", esd.SUBSPACE, 0),
+            ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED))
     for _ in range(args.warmup):
-        run_sequence(s, p, args, esd.DEFLATED, esd, P, False)
-        run_sequence(s, p, args, esd.PLAIN, esd, P, False)
-        run_sequence(s, p, args, esd.DEFLATED, esd, P, False, esd.FLAG_MIXED)
+        for name, mode, pf in seqs:
+            run_sequence(s, p, args, mode, esd, P, False, pf)
         print("# warmup step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    walls, walls_plain, walls_mixed, spmv_ms, spmv_n = [], [], [], 0.0, 0
-    recs = recs_plain = None
+    walls = {name: [] for name, _, _ in seqs}
+    recs = {}
+    spmv_ms = sweep_ms = 0.0
+    spmv_n = 0
     for k in range(args.steps):
-        recs, wall, sm, sn = run_sequence(s, p, args, esd.DEFLATED, esd, P, True)
-        walls.append(wall)
-        spmv_ms += sm
-        spmv_n += sn
-        recs_plain, wall_p, _, _ = run_sequence(s, p, args, esd.PLAIN, esd, P, False)
-        walls_plain.append(wall_p)
-        # the FP32/FP64 mixed deflated solver on the same sequence (context)
-        recs_mixed, wall_m, _, _ = run_sequence(s, p, args, esd.DEFLATED, esd, P, False, esd.FLAG_MIXED)
-        walls_mixed.append(wall_m)
-        print("# step %d: deflated %.4f s, plain %.4f s, mixed deflated %.4f s" % (k, wall, wall_p, wall_m),
+        for name, mode, pf in seqs:
+            r, wall, tm = run_sequence(s, p, args, mode, esd, P, name == "deflated", pf)
+            walls[name].append(wall)
+            recs[name] = r
+            if tm:
+                spmv_ms += tm["spmv_ms"] * tm["iters"]
+                sweep_ms += tm["sweep_ms"] * tm["iters"]
+                spmv_n += tm["iters"]
+        print("# step %d: " % k + ", ".join("%s %.4f s" % (nm, walls[nm][-1]) for nm, _, _ in seqs),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    T = float(np.mean(walls))
-    Tp = float(np.mean(walls_plain))
-    per_sys = T / args.systems
-    per_sys_plain = Tp / args.systems
-    mt = recs[0].get("m_tilde_built", 0)
-    its_defl = [r["iters"] for r in recs[1:]]
-    its_plain = [r["iters"] for r in recs_plain]
-    # roofline of the per-iteration SpMV launch (deflated: W^T q fused in)
+    per = {nm: float(np.mean(w)) / args.systems for nm, w in walls.items()}
+    per_sys, per_sys_plain = per["deflated"], per["plain"]
+    T = per_sys * args.systems
+    rd, rp = recs["deflated"], recs["plain"]
+    mt = rd[0].get("m_tilde_built", 0)
+    its_defl = [r["iters"] for r in rd[1:]]
+    its_plain = [r["iters"] for r in rp]
+    # theta sweep on the same samples (m_tilde only; the timed runs use args.theta)
+    theta_sweep = {}
+    for th in (1e-3, 1e-4, 1e-5, args.theta):
+        theta_sweep["%g" % th] = int(sum(1 for v in rd[0]["ritz"] if v < th))
+    # roofline of the per-iteration SpMV launch of the deflated form
     avg_spmv_s = (spmv_ms / max(spmv_n, 1)) * 1e-3
+    avg_sweep_s = (sweep_ms / max(spmv_n, 1)) * 1e-3
     n, nnz = p.n, p.nnz
     # deflated iterations: the projection has written p = zhat + beta p_old, so
     # the SpMV reads the matrix (8 B value + 4 B index per stored entry) and p,
     # and writes q (the timed system runs without the power iterate)
     bytes_spmv = 12.0 * nnz + 16.0 * n
     achieved = bytes_spmv / avg_spmv_s / 1e9 if avg_spmv_s > 0 else 0.0
+    # what the layout the kernel reads has to move: the class-aligned copy has
+    # no column indices (8 B per slot plus 4 B per 64 slots), the sorted one 12 B
+    lay = s.layout()
+    slots = lay["a_slots"]
+    fmt_spmv = (8.0 * slots + 4.0 * slots / 64 if lay["class_layout"][0] else 12.0 * slots) + 16.0 * n
+    # one forward + backward IC(0) sweep pair: both triangles with their
+    # diagonals (12 B per entry), r read, y written and read, z written
+    bytes_sweeps = 12.0 * (nnz + n) + 32.0 * n
+    sweeps_gbs = bytes_sweeps / avg_sweep_s / 1e9 if avg_sweep_s > 0 else 0.0
     out = {
         "metric": "time-to-solution/system at relres 1e-8, deflated vs plain ICCG; SpMV GB/s",
         "value": per_sys,
@@ -226,18 +244,27 @@ def main():
         },
         "plain_s_per_system": per_sys_plain,
         "speedup_vs_plain": per_sys_plain / per_sys if per_sys > 0 else None,
+        "subspace_s_per_system": per["subspace"],
+        "mixed_deflated_s_per_system": per["mixed_deflated"],
+        "deflated_s_systems_2_to_K": float(np.mean([r["seconds"] for r in rd[1:]])) if len(rd) > 1 else None,
+        "plain_s_systems_2_to_K": float(np.mean([r["seconds"] for r in rp[1:]])) if len(rp) > 1 else None,
+        "iters_sampling_solve": rd[0]["iters"],
+        "build_aux_s": rd[0].get("build_aux_s"),
+        "m_bar": rd[0].get("m_bar"),
+        "m_tilde": mt,
+        "ritz_smallest": rd[0]["ritz"][:8],
+        "theta_sweep_m_tilde": theta_sweep,
         "iters_deflated_mean": float(np.mean(its_defl)) if its_defl else None,
         "iters_plain_mean": float(np.mean(its_plain)),
-        "iters_sampling_solve": recs[0]["iters"],
-        "m_tilde": mt,
-        "build_aux_s": recs[0].get("build_aux_s"),
-        "kappa_cg_last": recs[-1]["kappa"],
-        "kappa_es_last": recs[-1]["kappa_es"],
-        "true_relres_max": max(r["true_relres"] for r in recs),
-        "mixed_deflated_s_per_system": float(np.mean(walls_mixed)) / args.systems,
-        "mixed_iters_mean": float(np.mean([r["iters"] for r in recs_mixed[1:]])) if len(recs_mixed) > 1 else None,
-        "mixed_fp64_iters_mean": float(np.mean([r["fp64_iters"] for r in recs_mixed])),
-        "mixed_true_relres_max": max(r["true_relres"] for r in recs_mixed),
+        "iters_subspace_mean": float(np.mean([r["iters"] for r in recs["subspace"][1:]])) if args.systems > 1 else None,
+        "iters_mixed_deflated_mean": float(np.mean([r["iters"] for r in recs["mixed_deflated"][1:]])) if args.systems > 1 else None,
+        "mixed_fp64_iters_total": int(sum(r["fp64_iters"] for r in recs["mixed_deflated"])),
+        "true_relres_max": max(r["true_relres"] for r in rd),
+        "mixed_true_relres_max": max(r["true_relres"] for r in recs["mixed_deflated"]),
+        "kappa_cg_per_system": [round(r["kappa"], 3) for r in rd],
+        "kappa_es_per_system": [round(r["kappa_es"], 3) for r in rd],
+        "sweeps": {"unit": "GB/s", "achieved": sweeps_gbs, "peak": HBM_PEAK_GBS, "frac": sweeps_gbs / HBM_PEAK_GBS,
+                   "bytes_per_pair": bytes_sweeps, "avg_pair_us": avg_sweep_s * 1e6},
         "roofline": {
             "kernel": "k_spmv_it, deflated form (q = A p for the projected direction p, and (p, q))",
             "bound": "hbm",
@@ -247,6 +274,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": counter_traffic("k_spmv_it<double, false, true>") if args.N == 128 else None,
             "bytes_per_launch": bytes_spmv,
+            "layout_bytes_per_launch": fmt_spmv,
+            "layout_gbs": fmt_spmv / avg_spmv_s / 1e9 if avg_spmv_s > 0 else 0.0,
             "avg_launch_us": avg_spmv_s * 1e6,
             "launches": spmv_n,
         },

@@ -200,8 +200,13 @@ esd_status esd_get_factor_diag(esd_ctx *ctx, double *ldiag); /* (h) float64[n] l
 esd_status esd_get_history(esd_ctx *ctx, double *alpha, double *beta, int32_t cap, int32_t *count);
 /* (h) int32[m]: iteration stored in each sampling slot (0 = empty) */
 esd_status esd_get_samples(esd_ctx *ctx, int32_t *iters_by_slot);
-/* (h) int32[4]: n, nnz, number of sweep levels, number of colours */
-esd_status esd_get_layout(esd_ctx *ctx, int32_t *out4);
+/* (h) int32[8]: n, nnz, number of sweep levels, number of colours,
+ * 1/0 whether the iteration kernels read A, L and U in the class-aligned
+ * layout (per 64-row slice one column offset per slot instead of one column
+ * index per entry; used when no slice needs more than 64 slots), and the
+ * number of stored slots (entries + padding) of A in the layout the
+ * iteration SpMV reads */
+esd_status esd_get_layout(esd_ctx *ctx, int32_t *out8);
 /* (h) double[4] from the last solve run with ESD_FLAG_TIMING: average ms per
  * executed iteration of out[0] the SpMV launch, out[1] all sweep launches,
  * out[2] the vector-update launch; out[3] the number of timed iterations. */

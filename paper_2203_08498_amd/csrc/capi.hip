@@ -26,8 +26,22 @@ struct DevEll {
     double *v64 = nullptr;
     float *v32 = nullptr;
     int64_t size = 0;
-    Ell<double> e64() const { return {sptr, col, v64}; }
-    Ell<float> e32() const { return {sptr, col, v32}; }
+    // class-aligned copy for the iteration kernels (csize == 0: none)
+    int64_t *csptr = nullptr;
+    int32_t *soff = nullptr;
+    int64_t *src = nullptr;
+    double *cv64 = nullptr;
+    float *cv32 = nullptr;
+    int64_t csize = 0;
+    Ell<double> e64() const { return {sptr, col, v64, nullptr}; }
+    Ell<float> e32() const { return {sptr, col, v32, nullptr}; }
+    // the layout the iteration kernels read
+    Ell<double> it64() const { return csize ? Ell<double>{csptr, nullptr, cv64, soff} : e64(); }
+    Ell<float> it32() const { return csize ? Ell<float>{csptr, nullptr, cv32, soff} : e32(); }
+    // refresh the class-aligned values from the sorted layout
+    void repack(hipStream_t s) const {
+        if (csize) esd::launch_repack(csize, src, v64, cv64, cv32, s);
+    }
 };
 
 template <typename T> struct VecSet {
@@ -117,6 +131,7 @@ struct esd_ctx {
     std::vector<GraphEntry> graphs;
     uint32_t epoch = 1;
     bool use_graphs = true;
+    bool class_layout = true; // class-aligned matrix copies for the iteration kernels when they fit
     hipStream_t cap = nullptr; // private stream the chunks are captured on
     // kernel timing
     std::vector<hipEvent_t> ev;
@@ -157,11 +172,28 @@ esd_status upload_ell(esd_ctx *c, DevEll &D, const esd::HostEll &H) {
         HIPCHK(hipMemcpyAsync(D.v64, H.val.data(), sizeof(double) * D.size, hipMemcpyHostToDevice, c->stream));
     }
     esd::launch_cast(D.size, D.v64, D.v32, c->stream);
+    std::vector<int64_t> csptr, src;
+    std::vector<int32_t> soff;
+    if (c->class_layout && D.size && esd::ell_classes(H, c->n, 64, csptr, soff, src)) {
+        D.csize = csptr.back();
+        HIPCHK(dalloc(&D.csptr, (int64_t)csptr.size()));
+        HIPCHK(dalloc(&D.soff, (int64_t)soff.size()));
+        HIPCHK(dalloc(&D.src, D.csize));
+        HIPCHK(dalloc(&D.cv64, D.csize));
+        HIPCHK(dalloc(&D.cv32, D.csize));
+        HIPCHK(hipMemcpyAsync(D.csptr, csptr.data(), sizeof(int64_t) * csptr.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(D.soff, soff.data(), sizeof(int32_t) * soff.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(D.src, src.data(), sizeof(int64_t) * src.size(), hipMemcpyHostToDevice, c->stream));
+        D.repack(c->stream);
+        HIPCHK(hipStreamSynchronize(c->stream)); // the host copies die here
+    }
     return ESD_OK;
 }
 
 void free_ell(DevEll &D) {
-    (void)hipFree(D.sptr); (void)hipFree(D.col); (void)hipFree(D.v64); (void)hipFree(D.v32);
+    void *ptrs[] = {D.sptr, D.col, D.v64, D.v32, D.csptr, D.soff, D.src, D.cv64, D.cv32};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
     D = DevEll();
 }
 
@@ -184,7 +216,7 @@ template <> VecSet<double> vecs<double>(esd_ctx *c) {
     V.x = c->x; V.r = c->r; V.z = c->z; V.zsc = c->zsc; V.y = c->y; V.q = c->q;
     V.p[0] = c->p[0]; V.p[1] = c->p[1]; V.v[0] = c->v[0]; V.v[1] = c->v[1];
     V.W = c->W; V.AW = c->AW; V.Wrm = c->W_rm; V.AWrm = c->AW_rm; V.dinv = c->dinv;
-    V.A = c->A.e64(); V.L = c->L.e64(); V.U = c->U.e64();
+    V.A = c->A.it64(); V.L = c->L.it64(); V.U = c->U.it64();
     return V;
 }
 template <> VecSet<float> vecs<float>(esd_ctx *c) {
@@ -192,7 +224,7 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
     V.x = c->d32; V.r = c->r32; V.z = c->z32; V.zsc = c->zsc32; V.y = c->y32; V.q = c->q32;
     V.p[0] = c->p32[0]; V.p[1] = c->p32[1]; V.v[0] = c->v32[0]; V.v[1] = c->v32[1];
     V.W = c->W32; V.AW = c->AW32; V.Wrm = c->W32_rm; V.AWrm = c->AW32_rm; V.dinv = c->dinv32;
-    V.A = c->A.e32(); V.L = c->L.e32(); V.U = c->U.e32();
+    V.A = c->A.it32(); V.L = c->L.it32(); V.U = c->U.it32();
     return V;
 }
 
@@ -586,6 +618,19 @@ void record_samples(esd_ctx *c, int iters, bool last_sampled) {
     c->have_samples = c->nsamples > 0;
 }
 
+// The class-aligned layout gathers an arbitrary in-range element for the
+// empty slots of a row (multiplied by zero): the sweep outputs must hold finite
+// values before their rows are written, whatever an earlier solve left there.
+void clear_sweep_vectors(esd_ctx *c) {
+    const int nv = (int)c->n + 64;
+    esd::launch_fill(nv, c->y, 0.0, c->stream);
+    esd::launch_fill(nv, c->z, 0.0, c->stream);
+    esd::launch_fill(nv, c->zsc, 0.0, c->stream);
+    esd::launch_fill(nv, c->y32, 0.0f, c->stream);
+    esd::launch_fill(nv, c->z32, 0.0f, c->stream);
+    esd::launch_fill(nv, c->zsc32, 0.0f, c->stream);
+}
+
 esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol, int maxit, int kind,
                       int flags, double *xout, esd_info *info) {
     const int n = (int)c->n;
@@ -594,6 +639,7 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
     const bool power = (flags & ESD_FLAG_POWER) != 0;
     const bool restart = (flags & ESD_FLAG_TRUE_RES) != 0;
     auto V = vecs<double>(c);
+    clear_sweep_vectors(c);
     esd::launch_gather(n, c->p2u, b, c->b, c->stream);
     if (x0) esd::launch_gather(n, c->p2u, x0, c->x, c->stream);
     else esd::launch_fill(n, c->x, 0.0, c->stream);
@@ -700,6 +746,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     const bool sampling = c->armed;
     const bool power = (flags & ESD_FLAG_POWER) != 0;
     auto V = vecs<float>(c);
+    clear_sweep_vectors(c);
     esd::launch_gather(n, c->p2u, b, c->b, c->stream);
     if (x0) esd::launch_gather(n, c->p2u, x0, c->x, c->stream);
     else esd::launch_fill(n, c->x, 0.0, c->stream);
@@ -1068,6 +1115,8 @@ esd_status esd_factor_ic0(esd_ctx *c) {
     esd::launch_gather_u(c->U.size, c->u_from_l, c->L.v64, c->U.v64, c->stream);
     esd::launch_cast(c->L.size, c->L.v64, c->L.v32, c->stream);
     esd::launch_cast(c->U.size, c->U.v64, c->U.v32, c->stream);
+    c->L.repack(c->stream);
+    c->U.repack(c->stream);
     HIPCHK(hipGetLastError());
     int bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -1083,6 +1132,7 @@ esd_status esd_factor_ic0(esd_ctx *c) {
 esd_status esd_update_values(esd_ctx *c, const double *val) {
     if (!c || !val) return ESD_EINVAL;
     esd::launch_map_values(c->A.size, c->a_src, val, c->A.v64, c->A.v32, c->stream);
+    c->A.repack(c->stream);
     esd::launch_map_values(c->L.size, c->l_src, val, c->l_orig, nullptr, c->stream);
     esd::launch_map_values(c->n, c->d_src, val, c->adiag, nullptr, c->stream);
     HIPCHK(hipGetLastError());
@@ -1200,7 +1250,7 @@ esd_status esd_spmv(esd_ctx *c, const double *x, double *y) {
     if (!c || !x || !y) return ESD_EINVAL;
     const int n = (int)c->n;
     esd::launch_gather(n, c->p2u, x, c->t, c->stream);
-    esd::launch_spmv(n, c->A.e64(), c->t, c->q, c->stream);
+    esd::launch_spmv(n, c->A.it64(), c->t, c->q, c->stream); // the layout of the iteration SpMV
     esd::launch_scatter(n, c->p2u, c->q, y, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1211,6 +1261,7 @@ esd_status esd_prec_apply(esd_ctx *c, const double *r, double *z) {
     if (!c || !r || !z) return ESD_EINVAL;
     if (!c->factored) return fail(c, ESD_EINVAL, "factor_ic0 not called");
     const int n = (int)c->n;
+    clear_sweep_vectors(c);
     esd::launch_gather(n, c->p2u, r, c->r, c->stream);
     init_scal(c, 1, 1.0, 0);
     esd_status st = put_scal(c);
@@ -1255,12 +1306,16 @@ esd_status esd_get_samples(esd_ctx *c, int32_t *iters_by_slot) {
     return ESD_OK;
 }
 
-esd_status esd_get_layout(esd_ctx *c, int32_t *out4) {
-    if (!c || !out4) return ESD_EINVAL;
-    out4[0] = (int32_t)c->n;
-    out4[1] = (int32_t)c->nnz;
-    out4[2] = (int32_t)c->lvl.size() - 1;
-    out4[3] = c->ncolors;
+esd_status esd_get_layout(esd_ctx *c, int32_t *out8) {
+    if (!c || !out8) return ESD_EINVAL;
+    out8[0] = (int32_t)c->n;
+    out8[1] = (int32_t)c->nnz;
+    out8[2] = (int32_t)c->lvl.size() - 1;
+    out8[3] = c->ncolors;
+    out8[4] = c->A.csize > 0;
+    out8[5] = c->L.csize > 0;
+    out8[6] = c->U.csize > 0;
+    out8[7] = (int32_t)(c->A.csize ? c->A.csize : c->A.size);
     return ESD_OK;
 }
 

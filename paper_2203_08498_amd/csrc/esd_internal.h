@@ -52,6 +52,19 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
 void tile_orders(const HostLayout &H, const int32_t *colors, int tile_rows, std::vector<int32_t> &full,
                  std::vector<int32_t> &lvl, std::vector<int64_t> &lvl_off);
 
+// Class-aligned copy of a sliced-ELL matrix for the iteration kernels.  In
+// every 64-row slice the distinct offsets col - row of its entries, ascending,
+// become the slots: slot k of the slice holds, for each row, the entry at
+// column row + soff[sptr[s] / 64 + k], or nothing (value 0).  Within a row
+// the slots are in ascending physical column order (for A, whose sorted
+// layout has that order too, a row's dot product adds the same terms in the
+// same order, plus exact zeros).  src[e] is the sorted-layout position of
+// class entry e (-1: none).
+// Returns false when a slice would need more than max_width slots or the
+// copy would exceed 5/4 of the sorted layout's entries.
+bool ell_classes(const HostEll &E, int64_t n, int max_width, std::vector<int64_t> &sptr, std::vector<int32_t> &soff,
+                 std::vector<int64_t> &src);
+
 // Sampling method A: slot of iteration i (>= 1) for m slots, and the table of
 // slots (or -1) for iterations 0..maxit.
 int sampling_slot(int64_t i, int m);

@@ -383,4 +383,47 @@ void tile_orders(const HostLayout &H, const int32_t *colors, int tile_rows, std:
     lvl_off[nl] = (int64_t)lvl.size();
 }
 
+bool ell_classes(const HostEll &E, int64_t n, int max_width, std::vector<int64_t> &sptr, std::vector<int32_t> &soff,
+                 std::vector<int64_t> &src) {
+    const int64_t nsl = (n + kSlice - 1) / kSlice;
+    std::vector<std::vector<int32_t>> offs(nsl);
+    bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
+    for (int64_t s = 0; s < nsl; ++s) {
+        std::vector<int32_t> &o = offs[s];
+        const int64_t b = E.sptr[s], w = (E.sptr[s + 1] - b) / kSlice;
+        for (int64_t k = 0; k < w; ++k)
+            for (int64_t l = 0; l < kSlice; ++l) {
+                const int32_t c = E.col[b + k * kSlice + l];
+                if (c != (int32_t)n) o.push_back((int32_t)(c - (s * kSlice + l)));
+            }
+        std::sort(o.begin(), o.end());
+        o.erase(std::unique(o.begin(), o.end()), o.end());
+        if ((int)o.size() > max_width) ok = false;
+    }
+    sptr.assign(nsl + 1, 0);
+    for (int64_t s = 0; s < nsl && ok; ++s) sptr[s + 1] = sptr[s] + (int64_t)offs[s].size() * kSlice;
+    if (!ok || sptr[nsl] * 4 > (int64_t)E.col.size() * 5) {
+        sptr.clear();
+        return false;
+    }
+    soff.assign(sptr[nsl] / kSlice, 0);
+    src.assign(sptr[nsl], -1);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < nsl; ++s) {
+        const std::vector<int32_t> &o = offs[s];
+        for (size_t k = 0; k < o.size(); ++k) soff[sptr[s] / kSlice + (int64_t)k] = o[k];
+        const int64_t b = E.sptr[s], w = (E.sptr[s + 1] - b) / kSlice;
+        for (int64_t k = 0; k < w; ++k)
+            for (int64_t l = 0; l < kSlice; ++l) {
+                const int64_t pos = b + k * kSlice + l;
+                const int32_t c = E.col[pos];
+                if (c == (int32_t)n) continue;
+                const int64_t kk = std::lower_bound(o.begin(), o.end(), (int32_t)(c - (s * kSlice + l))) - o.begin();
+                src[sptr[s] + kk * kSlice + l] = pos;
+            }
+    }
+    return true;
+}
+
 } // namespace esd

@@ -44,6 +44,13 @@ template <typename T> struct Ell {
     const int64_t *sptr;
     const int32_t *col;
     const T *val;
+    // Class-aligned layout (soff != nullptr, col unused): every row of slice
+    // s keeps the entry at column row + soff[j] in slot k of slice-column
+    // j = sptr[s] / 64 + k, the offsets of a slice ascending; a row without
+    // that entry holds the value 0 there (its column, clamped into [0, n],
+    // is read and multiplied by zero).  The layout moves no column indices,
+    // only one offset per 64 entries.
+    const int32_t *soff;
 };
 
 // Reducing kernels write one row of `stride` doubles per block to `part`
@@ -168,6 +175,9 @@ struct FinGen {
     int store_svec;   // S->svec = s
 };
 
+// to64[e] = from[src[e]] (0 where src[e] < 0), to32 = (float)to64: values of
+// a class-aligned copy from the sorted layout
+void launch_repack(int64_t size, const int64_t *src, const double *from, double *to64, float *to32, hipStream_t s);
 void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s);
 void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s);
 // kind 0 plain / subspace correction, 1 deflated

@@ -136,29 +136,56 @@ __device__ __forceinline__ void fin_colsum(const double *part, int nblk, int str
 // per-iteration kernels
 // ------------------------------------------------------------------------
 
-// sum_k val_k * g(col_k) over one sliced-ELL row; the row's entries are
-// loaded eight at a time before any gather is issued, so a wavefront keeps
-// up to 8 value/index loads and then 8 (or 16) gathers in flight.
+// Loads the columns and values of slots k0 .. k0+7 of row i (slice starting
+// at entry `base`, width w > k0); slots past w get column n and value 0.  No
+// loaded value is used before all loads of the chunk are issued.  Class-
+// aligned layout: column = row + offset of the slot, clamped into [0, n]; a
+// row without an entry in a slot holds the value 0 there, so whatever finite
+// value the clamped column gathers is multiplied by zero.
+template <typename T>
+__device__ __forceinline__ void ell_chunk(const Ell<T> &M, int64_t base, int w, int k0, int i, int n, int (&c)[8],
+                                          T (&a)[8]) {
+    const int lane = i & 63;
+    if (M.soff) {
+        int off[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k0 + k < w) {
+                a[k] = M.val[base + (int64_t)(k0 + k) * 64 + lane];
+                off[k] = M.soff[(base >> 6) + k0 + k];
+            } else {
+                a[k] = T(0);
+                off[k] = n; // clamps to n
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = min(max(i + off[k], 0), n);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k0 + k < w) {
+                const int64_t pos = base + (int64_t)(k0 + k) * 64 + lane;
+                a[k] = M.val[pos];
+                c[k] = M.col[pos];
+            } else {
+                a[k] = T(0);
+                c[k] = n;
+            }
+        }
+    }
+}
+
+// sum_k val_k * g(col_k) over one sliced-ELL row, eight slots at a time: the
+// slot loads, then the eight gathers, then the products.
 template <typename T, typename G>
 __device__ __forceinline__ T ell_dot(const Ell<T> &M, int i, int n, G g) {
-    const int lane = i & 63;
     const int64_t base = M.sptr[i >> 6];
     const int w = (int)((M.sptr[(i >> 6) + 1] - base) >> 6);
     T sum = T(0);
     for (int k0 = 0; k0 < w; k0 += 8) {
         int c[8];
         T a[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k0 + k < w) {
-                const int64_t pos = base + (int64_t)(k0 + k) * 64 + lane;
-                c[k] = M.col[pos];
-                a[k] = M.val[pos];
-            } else {
-                c[k] = n;
-                a[k] = T(0);
-            }
-        }
+        ell_chunk(M, base, w, k0, i, n, c, a);
         T v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] = g(c[k]);
@@ -171,7 +198,6 @@ __device__ __forceinline__ T ell_dot(const Ell<T> &M, int i, int n, G g) {
 // two right-hand sides sharing the matrix loads: (A x, A y)
 template <typename T, typename G1, typename G2>
 __device__ __forceinline__ void ell_dot2(const Ell<T> &M, int i, int n, G1 g1, G2 g2, T &s1, T &s2) {
-    const int lane = i & 63;
     const int64_t base = M.sptr[i >> 6];
     const int w = (int)((M.sptr[(i >> 6) + 1] - base) >> 6);
     s1 = T(0);
@@ -179,17 +205,7 @@ __device__ __forceinline__ void ell_dot2(const Ell<T> &M, int i, int n, G1 g1, G
     for (int k0 = 0; k0 < w; k0 += 8) {
         int c[8];
         T a[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k0 + k < w) {
-                const int64_t pos = base + (int64_t)(k0 + k) * 64 + lane;
-                c[k] = M.col[pos];
-                a[k] = M.val[pos];
-            } else {
-                c[k] = n;
-                a[k] = T(0);
-            }
-        }
+        ell_chunk(M, base, w, k0, i, n, c, a);
         T v1[8], v2[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -587,6 +603,15 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_gen(FinGen f) {
 // per-solve kernels
 // ------------------------------------------------------------------------
 
+__global__ void k_repack(int64_t size, const int64_t *src, const double *from, double *to64, float *to32) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= size) return;
+    const int64_t j = src[e];
+    const double v = j >= 0 ? from[j] : 0.0;
+    to64[e] = v;
+    to32[e] = (float)v;
+}
+
 __global__ void k_gather(int n, const int32_t *idx, const double *src, double *dst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[idx[i]];
@@ -703,18 +728,11 @@ __global__ __launch_bounds__(kBlock) void k_tsdot(int n, const double *W, int m,
     block_partials<MT>(acc, part, MT);
 }
 
+// y = A x in either layout (x holds a zero at index n)
 __global__ __launch_bounds__(kBlock) void k_spmv(int n, Ell<double> A, const double *x, double *y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int lane = i & 63;
-    const int64_t base = A.sptr[i >> 6];
-    const int w = (int)((A.sptr[(i >> 6) + 1] - base) >> 6);
-    double s = 0.0;
-    for (int k = 0; k < w; ++k) {
-        const int64_t pos = base + (int64_t)k * 64 + lane;
-        s += A.val[pos] * x[A.col[pos]];
-    }
-    y[i] = s;
+    y[i] = ell_dot(A, i, n, [&](int c) { return x[c]; });
 }
 
 template <typename T>
@@ -972,6 +990,11 @@ int tsdot_grid(int64_t n, int m) {
     if (g > cap) g = cap;
     if (g > 8) g = g / 8 * 8;
     return g < 1 ? 1 : (int)g;
+}
+
+void launch_repack(int64_t size, const int64_t *src, const double *from, double *to64, float *to32, hipStream_t s) {
+    if (size <= 0) return;
+    k_repack<<<(unsigned)((size + 255) / 256), 256, 0, s>>>(size, src, from, to64, to32);
 }
 
 template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, bool power, int grid, hipStream_t s) {

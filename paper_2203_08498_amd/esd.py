@@ -302,9 +302,10 @@ class Solver:
         return out
 
     def layout(self):
-        out = np.zeros(4, np.int32)
+        out = np.zeros(8, np.int32)
         self._check(self.L.esd_get_layout(self.h, out.ctypes.data_as(C.c_void_p)))
-        return dict(n=int(out[0]), nnz=int(out[1]), levels=int(out[2]), colors=int(out[3]))
+        return dict(n=int(out[0]), nnz=int(out[1]), levels=int(out[2]), colors=int(out[3]),
+                    class_layout=(bool(out[4]), bool(out[5]), bool(out[6])), a_slots=int(out[7]))
 
     def timing(self):
         out = np.zeros(4)

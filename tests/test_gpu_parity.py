@@ -37,6 +37,8 @@ def _cases():
         "fv2d_natural": P.config1(N=40, nbox=2, box=6),
         "fv3d_colors": P.config2(N=13, nsph=2, radius=2.5),   # 2197 rows: several tiles, ragged tail
         "q1_colors": P.config4(Ne=11, nblk=2, blk=3),
+        # 5832 rows, ragged tail; its matrices take the class-aligned layout
+        "fv3d_class": P.config2(N=18, nsph=2, radius=3.0),
     }
 
 
@@ -57,6 +59,15 @@ def case(request):
 def test_permutation_bitexact(case):
     name, p, s, o = case
     assert np.array_equal(s.perm(), o.perm)
+
+
+def test_layout_choice(case):
+    """The iteration kernels read the class-aligned layout where every slice
+    fits it (even-sized 3-D grids, the Q1 case) and the sorted layout
+    otherwise; both paths are covered by the cases."""
+    name, p, s, o = case
+    expect = name in ("q1_colors", "fv3d_class")
+    assert s.layout()["class_layout"] == (expect, expect, expect)
 
 
 def test_spmv(case):
@@ -113,7 +124,14 @@ def test_iccg_at_tolerance_and_matched(case):
     assert info["status"] != esd.NOT_CONVERGED
 
 
-THETA = {"fv2d_natural": 1e-2, "fv3d_colors": 0.06, "q1_colors": 1e-2}
+def _theta(o):
+    """A threshold inside the widest relative gap among the oracle's smallest
+    Ritz values of its current samples (so m_tilde >= 1 and the selection is
+    decided far from rounding)."""
+    _, r0, _, _ = o.build_aux(0.0)
+    k = min(6, len(r0) - 1)
+    g = int(np.argmax(r0[1:k + 1] / r0[:k]))
+    return float(np.sqrt(r0[g] * r0[g + 1]))
 
 
 def test_rayleigh_ritz_on_identical_samples(case):
@@ -131,7 +149,7 @@ def test_rayleigh_ritz_on_identical_samples(case):
     X[:, 5] = X[:, 4]  # a repeated sample: its error vector is dropped
     s.load_samples(X, xN)
     o.load_samples(X, xN)
-    theta = THETA[name]
+    theta = _theta(o)
     st, ritz, mb, mt = s.build_aux(theta)
     ost, oritz, omb, omt = o.build_aux(theta)
     assert (mb, mt) == (omb, omt) and mb == 5
@@ -149,7 +167,7 @@ def test_sampling_build_aux_and_accelerated_solves(case):
     from paper_2203_08498_amd import esd
 
     name, p, s, o = case
-    m, theta = 8, THETA[name]
+    m = 8
     s.sample_errors(m)
     x1, i1 = s.solve(p.f, tol=1e-8, maxit=5000)
     o.arm_sampling(m)
@@ -157,6 +175,7 @@ def test_sampling_build_aux_and_accelerated_solves(case):
     assert i1["iters"] == j1.iters  # needed for identical sample iterations
     samples = o.samples(m)
     assert np.array_equal(s.samples(m), samples)
+    theta = _theta(o)
     st, ritz, mb, mt = s.build_aux(theta)
     ost, oritz, omb, omt = o.build_aux(theta)
     assert (mb, mt) == (omb, omt)
