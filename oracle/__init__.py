@@ -52,7 +52,7 @@ def lib():
         L.orc_spmv.argtypes = [P, P, P]
         L.orc_prec_apply.argtypes = [P, P, P]
         L.orc_sample_schedule.argtypes = [C.c_int, i64, P]
-        L.orc_arm_sampling.argtypes = [P, C.c_int]
+        L.orc_arm_sampling.argtypes = [P, C.c_int, C.c_int]
         L.orc_load_samples.argtypes = [P, P, C.c_int, P]
         L.orc_sym_eig.argtypes = [C.c_int, P, P, P]
         L.orc_build_aux.argtypes = [P, dbl, P, P, P]
@@ -65,6 +65,7 @@ def lib():
         L.orc_solve.argtypes = [P, P, P, dbl, C.c_int, C.c_int, C.c_int, P, P, P]
         L.orc_history.argtypes = [P, P, P]
         L.orc_samples.argtypes = [P, P]
+        L.orc_slot_vectors.argtypes = [P, P]
         L.orc_grad_values.argtypes = [P, P, P, P]
         _lib = L
     return _lib
@@ -165,10 +166,12 @@ class Oracle:
             raise RuntimeError("oracle prec: status %d" % st)
         return z
 
-    def arm_sampling(self, m: int):
-        st = lib().orc_arm_sampling(self.h, m)
+    def arm_sampling(self, m: int, method: int = 0, residuals: bool = False):
+        """method 0: sampling method A (Appendix A); 1: method B (relative-
+        residual thresholds, Sec. 4.3).  residuals: store r_i instead of x_i."""
+        st = lib().orc_arm_sampling(self.h, m, int(method) | (16 if residuals else 0))
         if st != 0:
-            raise ValueError("bad m")
+            raise ValueError("bad m or method")
 
     def load_samples(self, X, xN):
         """X: n x k approximate solutions (taken as iterations 1..k), xN: final solution."""
@@ -208,6 +211,12 @@ class Oracle:
     def samples(self, m):
         out = np.zeros(m, np.int32)
         lib().orc_samples(self.h, _p(out))
+        return out
+
+    def slot_vectors(self, m):
+        """Stored sample vectors, n x m (user order); unfilled slots are undefined."""
+        out = np.zeros((self.n, m), order="F")
+        lib().orc_slot_vectors(self.h, out.ctypes.data_as(C.c_void_p))
         return out
 
     def build_aux(self, theta: float):

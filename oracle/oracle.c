@@ -82,6 +82,8 @@ typedef struct {
     int factored;
     /* sampling */
     int m_req;
+    int samp_method;   /* 0: method A (Appendix A), 1: method B (relative-residual thresholds) */
+    int samp_resid;    /* 1: store residual vectors r_i instead of iterates x_i */
     double *slots; int32_t *slot_iter; double *xN;
     /* auxiliary space (permuted order, column-major n x k) */
     int m_bar, m_tilde;
@@ -346,11 +348,18 @@ int orc_load_samples(orc *o, const double *X_user, int k, const double *xN_user)
     }
     to_perm(o, xN_user, o->xN);
     o->nsamples = k;
+    o->samp_resid = 0;
     return OR_OK;
 }
 
-int orc_arm_sampling(orc *o, int m) {
+/* method: 0 = sampling method A, 1 = sampling method B (Sec. 4.3), plus 16
+ * to store the residual vectors r_i instead of the iterates x_i (the
+ * comparison of Sec. 5.3, "Sampling of residual vectors"). */
+int orc_arm_sampling(orc *o, int m, int method) {
     if (m <= 0 || m > 4096) return OR_EINVAL;
+    if ((method & ~16) != 0 && (method & ~16) != 1) return OR_EINVAL;
+    o->samp_method = method & 1;
+    o->samp_resid = (method & 16) != 0;
     o->m_req = m;
     free(o->slots); free(o->slot_iter);
     o->slots = malloc((size_t)m * o->n * sizeof(double));
@@ -499,7 +508,10 @@ int orc_build_aux(orc *o, double theta, double *ritz_out, int *m_bar, int *m_til
     int kept = 0;
     for (int a = 0; a < cnt; ++a) {
         const double *xs = o->slots + (int64_t)order[a] * n;
-        for (int64_t i = 0; i < n; ++i) v[i] = o->xN[i] - xs[i];      /* eq. (ek) */
+        if (o->samp_resid)
+            for (int64_t i = 0; i < n; ++i) v[i] = xs[i];               /* sampled residual r_s */
+        else
+            for (int64_t i = 0; i < n; ++i) v[i] = o->xN[i] - xs[i];  /* eq. (ek) */
         double nv = sqrt(dot(n, v, v));
         if (!(nv > 0.0)) continue;
         for (int64_t i = 0; i < n; ++i) v[i] /= nv;
@@ -690,7 +702,9 @@ int orc_solve(orc *o, const double *b_user, const double *x0_user, double tol, i
     int power = (flags & FLAG_POWER) != 0;
     if (power && !o->have_v) { free(b); free(x); free(r); free(z); free(p); free(q); free(w); free(t); free(vq); return OR_EINVAL; }
 
-    double bnorm = sqrt(dot(n, b, b));
+    const double bnorm2 = dot(n, b, b);
+    double bnorm = sqrt(bnorm2);
+    int b_next = 0; /* method B: thresholds 0 .. b_next-1 already reached */
     /* r_0 = b - A x_0 */
     spmv(o, x, t);
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
@@ -747,17 +761,32 @@ int orc_solve(orc *o, const double *b_user, const double *x0_user, double tol, i
         for (int64_t i = 0; i < n; ++i) x[i] += alpha * p[i];
         for (int64_t i = 0; i < n; ++i) r[i] -= alpha * w[i];
         rho_prev = rho;
-        rnorm = sqrt(dot(n, r, r));
+        const double rr = dot(n, r, r);
+        rnorm = sqrt(rr);
         if (!isfinite(rnorm) || !isfinite(alpha)) { status = OR_ENUMERIC; break; }
         if (rnorm <= tol * bnorm) { converged = 1; break; }
-        /* sampling method A (Appendix A) after the convergence check */
-        if (sampling && it % h == 0) {
-            int s = sample_slot(it, o->m_req);
-            memcpy(o->slots + (int64_t)s * n, x, n * sizeof(double));
-            o->slot_iter[s] = it;
+        /* sampling after the convergence check */
+        int s_take = -1;
+        if (sampling && o->samp_method == 0 && it % h == 0) {
+            /* method A (Appendix A) */
+            s_take = sample_slot(it, o->m_req);
+            if (it == h * o->m_req) h *= 2;
+        } else if (sampling && o->samp_method == 1) {
+            /* method B (Sec. 4.3): slot s takes the iterate at which the
+             * relative residual first reaches tol^{(s+1)/(m+1)}, compared in
+             * squares; thresholds passed in one iteration share its sample,
+             * which goes to the first of them */
+            const int m = o->m_req;
+            while (b_next < m && rr <= pow(tol, 2.0 * (b_next + 1) / (m + 1)) * bnorm2) {
+                if (s_take < 0) s_take = b_next;
+                ++b_next;
+            }
+        }
+        if (s_take >= 0) {
+            memcpy(o->slots + (int64_t)s_take * n, o->samp_resid ? r : x, n * sizeof(double));
+            o->slot_iter[s_take] = it;
             if (o->nsamples < 4096) o->sample_iters[o->nsamples] = it;
             o->nsamples++;
-            if (it == h * o->m_req) h *= 2;
         }
     }
     o->iters = it;
@@ -812,6 +841,15 @@ int orc_samples(const orc *o, int32_t *iters_by_slot) {
     if (!o->slot_iter) return 0;
     memcpy(iters_by_slot, o->slot_iter, o->m_req * sizeof(int32_t));
     return o->nsamples;
+}
+
+/* The stored sample vectors (n x m, column-major, user order; slots never
+ * filled hold whatever the buffer held).  Returns m. */
+int orc_slot_vectors(const orc *o, double *out_user) {
+    if (!o->slots) return 0;
+    for (int s = 0; s < o->m_req; ++s)
+        for (int64_t l = 0; l < o->n; ++l) out_user[(int64_t)s * o->n + o->perm[l]] = o->slots[(int64_t)s * o->n + l];
+    return o->m_req;
 }
 
 /* ------------------------------------------------------------------ */

@@ -62,6 +62,93 @@ def test_sampling_solve_matches_schedule():
     assert np.array_equal(np.sort(o.samples(8)), np.sort(sched.astype(np.int32)))
 
 
+# ---------------------------------------------------------------- sampling B, residual vectors
+
+def _relres_after(p, o_fresh, its):
+    """True relative residual of the ICCG iterate after `its` iterations (a
+    fresh solve with tol 0 stopped there), computed with scipy."""
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n, p.n))
+    x, _ = o_fresh.solve(p.f, tol=0.0, maxit=its)
+    return x, np.linalg.norm(p.f - A @ x) / np.linalg.norm(p.f)
+
+
+def test_sampling_method_b_takes_first_threshold_crossings():
+    """Sec. 4.3, method B: a sample when the relative residual first reaches
+    10^{-s alpha/(m+1)}, s = 1..m, for the criterion 10^{-alpha}.  Checked with
+    residuals recomputed from fresh solves stopped at and before each sample."""
+    p = P.config1(N=32, nbox=2, box=4)
+    m, tol = 6, 1e-8
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    o.arm_sampling(m, method=1)
+    x, info = o.solve(p.f, tol=tol, maxit=5000, flags=O.SAMPLE)
+    its = o.samples(m)
+    X = o.slot_vectors(m)
+    ref = O.Oracle.from_problem(p)
+    ref.factor_ic0()
+    taken = [(s, int(i)) for s, i in enumerate(its) if i > 0]
+    assert taken and all(i < info.iters for _, i in taken)
+    thr = [10.0 ** (-(s + 1) * 8.0 / (m + 1)) for s in range(m)]
+    last = 0
+    for s, i in taken:
+        assert i > last  # later thresholds, later (or equal, then skipped) iterations
+        xi, rel = _relres_after(p, ref, i)
+        _, rel_before = _relres_after(p, ref, i - 1)
+        assert rel <= thr[s] * (1 + 1e-6)
+        assert rel_before > thr[s] * (1 - 1e-6)
+        assert np.array_equal(X[:, s], xi)  # the stored vector is the iterate x_i
+        last = i
+    # every threshold is passed before convergence; thresholds passed in the
+    # same iteration leave later slots empty
+    for s in range(m):
+        if its[s] == 0:
+            assert s > 0 and any(i > 0 for i in its[:s])
+
+
+def test_residual_sampling_stores_residuals_and_spans_them():
+    """Residual-vector sampling (Sec. 5.3): the stored vectors are r_i = b - A x_i
+    and the auxiliary basis spans them (no x_N - x_i)."""
+    p = P.config1(N=32, nbox=2, box=4)
+    m = 5
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    o.arm_sampling(m, residuals=True)
+    x, info = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE)
+    its = o.samples(m)
+    R = o.slot_vectors(m)
+    ref = O.Oracle.from_problem(p)
+    ref.factor_ic0()
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n, p.n))
+    cols = []
+    for s, i in enumerate(its):
+        if i == 0:
+            continue
+        xi, _ = ref.solve(p.f, tol=0.0, maxit=int(i))
+        assert np.linalg.norm(R[:, s] - (p.f - A @ xi)) <= 1e-11 * np.linalg.norm(p.f)
+        cols.append(R[:, s])
+    st, ritz, mb, mt = o.build_aux(1.0)
+    E, _, _, _ = o.aux()
+    Q, _ = np.linalg.qr(np.column_stack(cols))
+    assert mb == len(cols)
+    assert np.abs(E @ E.T - Q @ Q.T).max() <= 1e-10
+
+
+def test_residual_sampling_misses_the_small_eigenvalues():
+    """Sec. 5.3: since r_s = A e_s damps the small-eigenvalue components, the
+    residual samples give no small Ritz value where the error samples do
+    (floating high-coefficient blocks: near-null modes)."""
+    p = P.config4(Ne=11, nblk=2, blk=3)
+    mins = {}
+    for resid in (False, True):
+        o = O.Oracle.from_problem(p)
+        assert o.factor_ic0() == 0
+        o.arm_sampling(8, residuals=resid)
+        o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE)
+        _, ritz, _, _ = o.build_aux(1.0)
+        mins[resid] = ritz[0]
+    assert mins[False] < 1e-5 and mins[True] > 1e-1
+
+
 # ---------------------------------------------------------------- permutation, SpMV
 
 def test_permutation_is_stable_colour_sort():
