@@ -124,11 +124,23 @@ esd_status esd_update_values(esd_ctx *ctx, const double *val);
  * ESD_ENOTSPD on a non-positive pivot. */
 esd_status esd_factor_ic0(esd_ctx *ctx);
 
-/* esd_sample_errors - arm sampling method A (Appendix A) with m slots for the
- * next solve: x_i is stored in slot (sum_l (-1)^l floor((i-1)/m^l)) mod m when
- * i mod h == 0, h doubling at i = h m; only iterations that did not meet the
- * stop test are sampled.  1 <= m <= m_max. */
-esd_status esd_sample_errors(esd_ctx *ctx, int32_t m);
+/* esd_sample_errors - arm sampling with m slots (1 <= m <= m_max) for the next
+ * solve; only iterations that did not meet the stop test are sampled.
+ *   method ESD_SAMPLING_A (Appendix A): x_i is stored in slot
+ *     (sum_l (-1)^l floor((i-1)/m^l)) mod m when i mod h == 0, h doubling at
+ *     i = h m.
+ *   method ESD_SAMPLING_B (Sec. 4.3): slot s-1 (s = 1..m) takes x_i at the
+ *     first i with ||r_i|| / ||b|| <= tol^{s/(m+1)} (tol = the solve's
+ *     tolerance, squares compared); thresholds passed in one iteration share
+ *     that sample, stored in the first of them, the others stay empty.
+ *   | ESD_SAMPLE_RESIDUALS: store the residual r_i instead of x_i; build_aux
+ *     then uses the residuals themselves instead of e = x_N - x_i (the
+ *     residual-vector sampling of Sec. 5.3).
+ * ESD_EINVAL for an unknown method. */
+#define ESD_SAMPLING_A 0
+#define ESD_SAMPLING_B 1
+#define ESD_SAMPLE_RESIDUALS 16
+esd_status esd_sample_errors(esd_ctx *ctx, int32_t m, int32_t method);
 
 /* esd_load_samples - install k approximate solutions X(d) (n x k, column-major,
  * float64, user order; taken as sampled at iterations 1..k) and the final
@@ -200,6 +212,10 @@ esd_status esd_get_factor_diag(esd_ctx *ctx, double *ldiag); /* (h) float64[n] l
 esd_status esd_get_history(esd_ctx *ctx, double *alpha, double *beta, int32_t cap, int32_t *count);
 /* (h) int32[m]: iteration stored in each sampling slot (0 = empty) */
 esd_status esd_get_samples(esd_ctx *ctx, int32_t *iters_by_slot);
+/* (d) float64[n] out, user order: the vector stored in sampling slot `slot`
+ * (0 <= slot < m of the last esd_sample_errors / esd_load_samples; the
+ * content of an empty slot is undefined) */
+esd_status esd_get_sample_vector(esd_ctx *ctx, int32_t slot, double *out);
 /* (h) int32[8]: n, nnz, number of sweep levels, number of colours,
  * 1/0 whether the iteration kernels read A, L and U in the class-aligned
  * layout (per 64-row slice one column offset per slot instead of one column

@@ -87,6 +87,12 @@ struct esd_ctx {
     // sampling
     int m_req = 0;
     bool armed = false;
+    int samp_method = 0;      // 0 method A, 1 method B
+    bool samp_resid = false;  // store residual vectors instead of iterates
+    // method B state carried across the Krylov runs of one solve
+    int b_next = 0;
+    std::vector<int32_t> b_slot_iter;
+    std::vector<double> b_thr2;
     double *slots = nullptr;
     int32_t *slot_table = nullptr;
     int64_t slot_table_cap = 0;
@@ -353,6 +359,8 @@ struct KrylovOpts {
     bool timing = false;
     bool timing_all = false;
     const double *xbase = nullptr; // mixed inner solves sample xbase + S.xscale * iterate
+    bool resid = false;    // sampling stores residuals (no xbase)
+    bool method_b = false; // sampling method B: slots chosen on the device
 };
 
 // Runs the CG loop from the state prepared by the caller (x, r, S with
@@ -402,8 +410,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     sa.z = defl ? nullptr : (sc ? V.zsc : V.z); // deflation: p_new given by the projection
     sa.slot_table = o.sampling ? c->slot_table : nullptr;
     sa.slots = c->slots;
-    sa.xit = V.x;
-    sa.xbase = o.xbase;
+    sa.xit = o.resid ? V.r : V.x;
+    sa.xbase = o.resid ? nullptr : o.xbase;
     sa.q = V.q;
     esd::FinAlpha fa{};
     fa.S = c->S; fa.part = c->part_spmv; fa.nblk = gs; fa.stride = sstride; fa.power = o.power;
@@ -417,6 +425,10 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = 1;
     fr.part_sweep = c->part_sweep; fr.hist_beta = c->hb; fr.init = 0;
     fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
+    if (o.sampling && o.method_b) {
+        fr.slot_table = c->slot_table;
+        fr.nslots = c->m_req;
+    }
     const bool timing = o.timing;
     // one chunk of iterations; `it0` must be even so that a replay of the
     // chunk reuses the same ping-pong buffers
@@ -473,7 +485,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     if (c->use_graphs && !o.sync_every && !o.stream_only && !timing) {
         const uint32_t key = (sizeof(T) == 4 ? 1u : 0u) | ((uint32_t)o.kind << 1) | ((uint32_t)o.noprec << 3) |
                              ((uint32_t)o.power << 4) | ((uint32_t)o.sampling << 5) | ((uint32_t)(*vbase & 1) << 6) |
-                             ((uint32_t)fuse_l0 << 7);
+                             ((uint32_t)fuse_l0 << 7) | ((uint32_t)o.resid << 8) | ((uint32_t)o.method_b << 9);
         for (auto &g : c->graphs)
             if (g.key == key && g.epoch == c->epoch) { ex = g.exec; known = true; }
         if (!known && !c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -584,7 +596,8 @@ esd_status ensure_tables(esd_ctx *c, int maxit) {
         c->epoch++;
     }
     if (c->armed) {
-        esd::sampling_table(c->m_req, (int64_t)maxit + 2, c->table_h);
+        if (c->samp_method == 0) esd::sampling_table(c->m_req, (int64_t)maxit + 2, c->table_h);
+        else c->table_h.assign((size_t)maxit + 2, -1); // method B: slots set on the device
         if (c->slot_table_cap < (int64_t)c->table_h.size()) {
             (void)hipFree(c->slot_table);
             c->slot_table = nullptr;
@@ -609,6 +622,15 @@ esd_status ensure_tables(esd_ctx *c, int maxit) {
 void record_samples(esd_ctx *c, int iters, bool last_sampled) {
     c->slot_iter.assign(c->m_req, 0);
     c->nsamples = 0;
+    if (c->samp_method == 1) {
+        for (int s = 0; s < c->m_req; ++s)
+            if (c->b_slot_iter[s] > 0 && (c->b_slot_iter[s] < iters || last_sampled)) {
+                c->slot_iter[s] = c->b_slot_iter[s];
+                c->nsamples++;
+            }
+        c->have_samples = c->nsamples > 0;
+        return;
+    }
     const int upto = last_sampled ? iters : iters - 1;
     for (int i = 1; i <= upto && i < (int)c->table_h.size(); ++i)
         if (c->table_h[i] >= 0) {
@@ -629,6 +651,29 @@ void clear_sweep_vectors(esd_ctx *c) {
     esd::launch_fill(nv, c->y32, 0.0f, c->stream);
     esd::launch_fill(nv, c->z32, 0.0f, c->stream);
     esd::launch_fill(nv, c->zsc32, 0.0f, c->stream);
+}
+
+// Sampling method B state lives in the device scalar block during a Krylov
+// run and on the host between runs (init_scal clears the block).
+void arm_method_b(esd_ctx *c, double tol) {
+    c->b_next = 0;
+    c->b_slot_iter.assign(64, 0);
+    c->b_thr2.assign(64, 0.0);
+    for (int s = 0; s < c->m_req; ++s) c->b_thr2[s] = std::pow(tol, 2.0 * (s + 1) / (c->m_req + 1));
+}
+void put_method_b(esd_ctx *c) {
+    Scal &S = *c->Sh;
+    S.smethod = 1;
+    S.bnext = c->b_next;
+    for (int s = 0; s < 64; ++s) {
+        S.slot_iter[s] = c->b_slot_iter[s];
+        S.bthr2[s] = c->b_thr2[s];
+    }
+}
+void get_method_b(esd_ctx *c) {
+    const Scal &S = *c->Sh;
+    c->b_next = S.bnext;
+    for (int s = 0; s < 64; ++s) c->b_slot_iter[s] = S.slot_iter[s];
 }
 
 esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol, int maxit, int kind,
@@ -657,6 +702,8 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
     if (st) return st;
     const double bn2 = c->Sh->bnorm2, tol2 = c->Sh->tol2;
     c->segments.clear();
+    const bool method_b = sampling && c->samp_method == 1;
+    if (method_b) arm_method_b(c, tol);
     int total = 0, done = 0, cycles = 0;
     double rr = 0.0, tr2 = 0.0;
     for (;;) {
@@ -667,6 +714,7 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
         c->Sh->tol2 = tol2;
         c->Sh->hist_base = total;
         c->Sh->sample_base = total;
+        if (method_b && cycles == 0) put_method_b(c);
         if ((st = put_scal(c))) return st;
         double *coef = (kind == 1) ? c->S->mu : (kind == 2 ? c->S->u : nullptr);
         dev_resid(c, c->b, c->x, c->r, m ? c->W : nullptr, m, coef, nullptr, kind != 1);
@@ -676,6 +724,8 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
         o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
         o.power = power;
         o.sampling = sampling && cycles == 0;
+        o.resid = c->samp_resid;
+        o.method_b = method_b;
         o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
         o.stream_only = (flags & ESD_FLAG_STREAM) != 0;
         o.timing = (flags & kFlagTiming) != 0;
@@ -688,8 +738,16 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
         if (power) c->vs64 = c->Sh->vscale;
         c->segments.push_back({total, iters});
         if (o.sampling) {
-            if (done == 2 && iters < (int)c->table_h.size() && c->table_h[iters] >= 0)
-                esd::launch_sample_store(n, c->slots + (size_t)c->table_h[iters] * n, c->x, c->stream);
+            // a solve stopped by maxit: its last vector has no next SpMV to store it
+            double *last = c->samp_resid ? c->r : c->x;
+            if (method_b) {
+                get_method_b(c);
+                for (int sl = 0; sl < c->m_req; ++sl)
+                    if (done == 2 && c->b_slot_iter[sl] == iters)
+                        esd::launch_sample_store(n, c->slots + (size_t)sl * n, last, c->stream);
+            } else if (done == 2 && iters < (int)c->table_h.size() && c->table_h[iters] >= 0) {
+                esd::launch_sample_store(n, c->slots + (size_t)c->table_h[iters] * n, last, c->stream);
+            }
             record_samples(c, iters, done == 2);
         }
         total += iters;
@@ -765,6 +823,8 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     const double bn2 = c->Sh->bnorm2, tol2 = c->Sh->tol2;
     int total = 0, outer = 0, done_in = 0, fp64_iters = 0;
     bool converged = false, fp64 = false;
+    const bool method_b = sampling && c->samp_method == 1;
+    if (method_b) arm_method_b(c, tol);
     double rn2 = 0.0, rn2_prev = -1.0;
     c->segments.clear();
     for (outer = 0; outer <= c->max_outer; ++outer) {
@@ -832,6 +892,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         c->Sh->hist_base = total;
         c->Sh->sample_base = total;
         c->Sh->xscale = rn;
+        if (method_b) put_method_b(c);
         st = put_scal(c);
         if (st) return st;
         // u = C^{-1} W^T r / ||r|| for the first preconditioned inner residual
@@ -841,6 +902,8 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
         o.power = power;
         o.sampling = sampling;
+        o.resid = c->samp_resid;
+        o.method_b = method_b;
         o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
         o.stream_only = (flags & ESD_FLAG_STREAM) != 0;
         o.timing = (flags & kFlagTiming) != 0;
@@ -849,6 +912,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         int it_in = 0;
         st = krylov<float>(c, V, o, &it_in, &c->vb32);
         if (st) return st;
+        if (method_b) get_method_b(c);
         done_in = c->Sh->done;
         c->segments.push_back({total, it_in});
         total += it_in;
@@ -874,7 +938,13 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         for (auto &sg : c->segments)
             for (int i = 1; i < sg.second; ++i) {
                 const int tot = sg.first + i;
-                if (tot < (int)c->table_h.size() && c->table_h[tot] >= 0) {
+                if (method_b) {
+                    for (int sl = 0; sl < c->m_req; ++sl)
+                        if (c->b_slot_iter[sl] == tot) {
+                            c->slot_iter[sl] = tot;
+                            c->nsamples++;
+                        }
+                } else if (tot < (int)c->table_h.size() && c->table_h[tot] >= 0) {
                     c->slot_iter[c->table_h[tot]] = tot;
                     c->nsamples++;
                 }
@@ -1147,10 +1217,14 @@ esd_status esd_update_values(esd_ctx *c, const double *val) {
     return ESD_OK;
 }
 
-esd_status esd_sample_errors(esd_ctx *c, int32_t m) {
+esd_status esd_sample_errors(esd_ctx *c, int32_t m, int32_t method) {
     if (!c) return ESD_EINVAL;
     if (m < 1 || m > c->m_max) return fail(c, ESD_EINVAL, "m must be in [1, m_max]");
+    const int base = method & ~ESD_SAMPLE_RESIDUALS;
+    if (base != ESD_SAMPLING_A && base != ESD_SAMPLING_B) return fail(c, ESD_EINVAL, "unknown sampling method");
     c->m_req = m;
+    c->samp_method = base;
+    c->samp_resid = (method & ESD_SAMPLE_RESIDUALS) != 0;
     c->armed = true;
     return ESD_OK;
 }
@@ -1169,6 +1243,7 @@ esd_status esd_load_samples(esd_ctx *c, const double *X, int32_t k, const double
     for (int s = 0; s < k; ++s) c->slot_iter[s] = s + 1;
     c->nsamples = k;
     c->have_samples = true;
+    c->samp_resid = false;
     c->armed = false;
     return ESD_OK;
 }
@@ -1306,6 +1381,15 @@ esd_status esd_get_samples(esd_ctx *c, int32_t *iters_by_slot) {
     return ESD_OK;
 }
 
+esd_status esd_get_sample_vector(esd_ctx *c, int32_t slot, double *out) {
+    if (!c || !out) return ESD_EINVAL;
+    if (slot < 0 || slot >= c->m_req || !c->slots) return fail(c, ESD_EINVAL, "slot out of range");
+    esd::launch_scatter((int)c->n, c->p2u, c->slots + (size_t)slot * c->n, out, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ESD_OK;
+}
+
 esd_status esd_get_layout(esd_ctx *c, int32_t *out8) {
     if (!c || !out8) return ESD_EINVAL;
     out8[0] = (int32_t)c->n;
@@ -1343,8 +1427,10 @@ esd_status esd_build_aux(esd_ctx *c, double theta, double *ritz, int32_t *m_bar,
     esd_status st;
     for (int s : order) {
         double *v = c->E + (size_t)kept * n;
-        // eq. (ek): e = x_1 - x~, normalised, then classical Gram-Schmidt twice
-        esd::launch_sub(n, c->xN, c->slots + (size_t)s * n, v, c->stream);
+        // eq. (ek): e = x_1 - x~ (or the sampled residual itself), normalised,
+        // then classical Gram-Schmidt twice
+        if (c->samp_resid) esd::launch_scale_copy(n, c->slots + (size_t)s * n, v, 1.0, c->stream);
+        else esd::launch_sub(n, c->xN, c->slots + (size_t)s * n, v, c->stream);
         dev_norm2(c, v, &c->S->out);
         if ((st = sync_read(c))) return st;
         double nv2 = c->Sh->out;

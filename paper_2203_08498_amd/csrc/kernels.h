@@ -34,7 +34,11 @@ struct Scal {
     int32_t hist_base;   // offset of this Krylov run in the alpha/beta history
     int32_t sample_base; // offset of this Krylov run in the sampling schedule
     int32_t pad;
-    double xscale;       // sampled value = xbase + xscale * iterate (mixed inner solves)
+    double xscale;       // sampled value = xbase + xscale * vector (mixed inner solves)
+    int32_t smethod;     // sampling: 0 method A (iteration table from the host), 1 method B
+    int32_t bnext;       // method B: thresholds already reached
+    int32_t slot_iter[64]; // method B: iteration (counted from the solve's start) in each slot
+    double bthr2[64];    // method B: squared relative thresholds tol^{2(s+1)/(m+1)}
     double mu[64];   // C^{-1} W^T q (deflation) or generic coarse coefficients
     double u[64];    // C^{-1} W^T r (subspace correction)
     double svec[64]; // last tall-skinny product W^T v
@@ -146,6 +150,8 @@ struct FinRho {
     const double *part_s; // (AW)^T z partials (deflated), nblk_s x stride_s
     int nblk_s, stride_s, m;
     const double *Cinv;
+    int32_t *slot_table;  // sampling method B: slot of the next store, set here (nullptr: none)
+    int nslots;
 };
 
 // zhat = z - W mu (W column-major n x m, mu = S->mu), the projected

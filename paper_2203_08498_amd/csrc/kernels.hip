@@ -267,8 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
             acc[1] += (double)vn * (double)vn;
         }
         if (slot >= 0)
-            a.slots[(size_t)slot * n + i] =
-                a.xbase ? a.xbase[i] + S->xscale * (double)a.xit[i] : (double)a.xit[i];
+            a.slots[(size_t)slot * n + i] = (a.xbase ? a.xbase[i] : 0.0) + S->xscale * (double)a.xit[i];
     }
     block_partials<NV>(acc, a.part, NV);
 }
@@ -490,11 +489,12 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
     // `done` is set
     const int done0 = S->done;
     const int t = threadIdx.x;
-    double rho_old = 0.0, tol2 = 0.0, rr_ref = 0.0;
-    int iter = 0, maxit = 0, stag = 0, it_ref = 0, hbase = 0;
+    double rho_old = 0.0, tol2 = 0.0, rr_ref = 0.0, bnorm2 = 0.0, xs = 1.0;
+    int iter = 0, maxit = 0, stag = 0, it_ref = 0, hbase = 0, sbase = 0, bnext = 0;
     if (t == 0) {
         rho_old = S->rho; tol2 = S->tol2; rr_ref = S->rr_ref;
         iter = S->iter; maxit = S->maxit; stag = S->stag_window; it_ref = S->it_ref; hbase = S->hist_base;
+        if (f.slot_table) { bnorm2 = S->bnorm2; xs = S->xscale; sbase = S->sample_base; bnext = S->bnext; }
     }
     const int mm = f.m * f.m;
     for (int k = t; k < mm; k += kFinThreads) cinv[k] = f.Cinv[k];
@@ -545,6 +545,22 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
         S->beta = b;
         if (f.hist_beta) f.hist_beta[hbase + it - 1] = b;
         S->rho = rn;
+        // sampling method B (Sec. 4.3): after the stop test, a sample when the
+        // relative residual first reaches tol^{(s+1)/(m+1)} (squares compared);
+        // thresholds passed together share the sample, stored in the first
+        if (f.slot_table && (d == 0 || d == 2)) {
+            const double lhs = rr * xs * xs;
+            int take = -1, bn = bnext;
+            while (bn < f.nslots && lhs <= S->bthr2[bn] * bnorm2) {
+                if (take < 0) take = bn;
+                ++bn;
+            }
+            if (take >= 0) {
+                S->bnext = bn;
+                f.slot_table[sbase + it] = take;
+                S->slot_iter[take] = sbase + it;
+            }
+        }
     }
 }
 

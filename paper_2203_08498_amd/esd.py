@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libesd.so")
 PLAIN, DEFLATED, SUBSPACE = 0, 1, 2
 FLAG_NOPREC, FLAG_POWER, FLAG_MIXED, FLAG_SYNC_EVERY, FLAG_TIMING, FLAG_TIMING_SPMV, FLAG_TRUE_RES = 1, 2, 4, 8, 16, 32, 64
 FLAG_STREAM = 128
+SAMPLING_A, SAMPLING_B, SAMPLE_RESIDUALS = 0, 1, 16
 OK, NOT_CONVERGED, AUX_EMPTY = 0, 1, 2
 EINVAL, ENOTSPD, EHIP, ENUMERIC, ENOAUX, ENOSAMPLES = -1, -2, -3, -4, -5, -6
 
@@ -40,6 +41,7 @@ EXPORTS = [
     "esd_setup", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
     "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
     "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag", "esd_get_history", "esd_get_samples",
+    "esd_get_sample_vector",
     "esd_get_layout", "esd_get_timing", "esd_status_string", "esd_last_error", "esd_destroy",
 ]
 
@@ -59,7 +61,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_setup.argtypes = [C.POINTER(P), P, i64, P, P, P, P, i32]
     L.esd_factor_ic0.argtypes = [P]
     L.esd_update_values.argtypes = [P, P]
-    L.esd_sample_errors.argtypes = [P, i32]
+    L.esd_sample_errors.argtypes = [P, i32, i32]
     L.esd_load_samples.argtypes = [P, P, i32, P]
     L.esd_build_aux.argtypes = [P, dbl, P, P, P]
     L.esd_set_aux.argtypes = [P, P, i32]
@@ -75,6 +77,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_get_factor_diag.argtypes = [P, P]
     L.esd_get_history.argtypes = [P, P, P, i32, P]
     L.esd_get_samples.argtypes = [P, P]
+    L.esd_get_sample_vector.argtypes = [P, i32, P]
     L.esd_get_layout.argtypes = [P, P]
     L.esd_get_timing.argtypes = [P, P]
     L.esd_status_string.argtypes = [C.c_int]
@@ -86,7 +89,7 @@ def load_library(path: str = LIB_PATH):
                  "esd_set_aux",
                  "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs",
                  "esd_grad_values", "esd_spmv", "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag",
-                 "esd_get_history", "esd_get_samples", "esd_get_layout", "esd_get_timing"):
+                 "esd_get_history", "esd_get_samples", "esd_get_sample_vector", "esd_get_layout", "esd_get_timing"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -180,8 +183,12 @@ class Solver:
             raise ValueError("expected %d values" % self.nnz)
         self._check(self.L.esd_update_values(self.h, _dptr(v)))
 
-    def sample_errors(self, m: int):
-        st = self.L.esd_sample_errors(self.h, int(m))
+    def sample_errors(self, m: int, method: int = 0, residuals: bool = False):
+        """Arm sampling for the next solve: method 0 = sampling method A
+        (Appendix A), 1 = method B (relative-residual thresholds, Sec. 4.3);
+        residuals=True stores r_i instead of x_i (Sec. 5.3)."""
+        code = int(method) | (SAMPLE_RESIDUALS if residuals else 0)
+        st = self.L.esd_sample_errors(self.h, int(m), code)
         if st != 0:
             raise EsdError(st, self.L.esd_last_error(self.h).decode())
 
@@ -299,6 +306,14 @@ class Solver:
     def samples(self, m):
         out = np.zeros(m, np.int32)
         self._check(self.L.esd_get_samples(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def sample_vector(self, slot: int):
+        """The vector stored in sampling slot `slot` (user order, float64 tensor)."""
+        import torch
+
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self._check(self.L.esd_get_sample_vector(self.h, int(slot), _dptr(out)))
         return out
 
     def layout(self):

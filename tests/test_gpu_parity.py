@@ -201,6 +201,44 @@ def test_sampling_build_aux_and_accelerated_solves(case):
         assert abs(info["kappa"] / oi2.kappa - 1) <= 1e-6
 
 
+@pytest.mark.parametrize("method,residuals", [(1, False), (0, True), (1, True)])
+def test_sampling_method_b_and_residual_vectors(case, method, residuals):
+    """Sampling method B (Sec. 4.3) and residual-vector sampling (Sec. 5.3):
+    the same sampled iterations as the oracle, the stored vectors to the
+    solution-parity bar, and Ritz values within the perturbation of the
+    sampled vectors."""
+    name, p, s, o = case
+    m = 6
+    s.sample_errors(m, method=method, residuals=residuals)
+    x1, i1 = s.solve(p.f, tol=1e-8, maxit=5000)
+    o.arm_sampling(m, method=method, residuals=residuals)
+    y1, j1 = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE)
+    assert i1["iters"] == j1.iters and _relerr(x1, y1) <= 1e-10
+    its = o.samples(m)
+    print(name, "method", method, "residuals", residuals, "sampled", its.tolist(), flush=True)
+    assert np.array_equal(s.samples(m), its) and (its > 0).sum() >= 2
+    X = o.slot_vectors(m)
+    # ||A||_2 <= max absolute row sum (symmetric A)
+    norm_a = np.add.reduceat(np.abs(p.val), p.rowptr[:-1]).max()
+    delta = 0.0
+    for sl in range(m):
+        if its[sl] == 0:
+            continue
+        g = s.sample_vector(sl).cpu().numpy()
+        d = np.linalg.norm(g - X[:, sl])
+        # iterates to the solution bar; residuals r = b - A x to that bar
+        # carried through A (||x_i|| grows along CG from x_0 = 0: <= ||x_N||)
+        assert d <= 1e-10 * (norm_a * np.linalg.norm(y1) if residuals else np.linalg.norm(X[:, sl]))
+        if residuals:
+            delta = max(delta, d / np.linalg.norm(X[:, sl]))
+        else:  # e = x_N - x_s: both ends differ
+            delta = max(delta, (d + np.linalg.norm(x1.cpu().numpy() - y1)) / np.linalg.norm(y1 - X[:, sl]))
+    st, ritz, mb, mt = s.build_aux(1.0)
+    ost, oritz, omb, omt = o.build_aux(1.0)
+    assert mb == omb
+    assert np.abs(ritz - oritz).max() <= 10 * max(delta, 1e-13) * 2.0 + 1e-12
+
+
 def test_power_iteration_kappa_es(case):
     from paper_2203_08498_amd import esd
 

@@ -42,6 +42,24 @@ def test_binding_covers_header(lib):
     assert L.esd_status_string(-2).decode().startswith("IC(0)")
 
 
+def test_binding_argument_counts_match_header():
+    """Every ctypes signature in the binding has as many parameters as the C
+    declaration in include/esd.h."""
+    from paper_2203_08498_amd import esd
+
+    src = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    L = esd.load_library()
+    checked = 0
+    for name, params in re.findall(r"\b(esd_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", src):
+        params = params.strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        fn = getattr(L, name)
+        if fn.argtypes is not None:
+            assert len(fn.argtypes) == n, (name, len(fn.argtypes), n)
+            checked += 1
+    assert checked >= 20
+
+
 def test_info_struct_layout():
     from paper_2203_08498_amd import esd
 
