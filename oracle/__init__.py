@@ -66,6 +66,7 @@ def lib():
         L.orc_history.argtypes = [P, P, P]
         L.orc_samples.argtypes = [P, P]
         L.orc_slot_vectors.argtypes = [P, P]
+        L.orc_set_rr.argtypes = [P, C.c_int]
         L.orc_grad_values.argtypes = [P, P, P, P]
         _lib = L
     return _lib
@@ -218,6 +219,12 @@ class Oracle:
         out = np.zeros((self.n, m), order="F")
         lib().orc_slot_vectors(self.h, out.ctypes.data_as(C.c_void_p))
         return out
+
+    def set_rayleigh_ritz(self, op: int):
+        """Operator of the next build_aux: 0 = A (eq. (Rayleigh-Ritz)), 1 = the
+        preconditioned matrix M^{-1}A in the M inner product (its footnote)."""
+        if lib().orc_set_rr(self.h, int(op)) != 0:
+            raise ValueError("bad Rayleigh-Ritz operator (or no IC(0) factor)")
 
     def build_aux(self, theta: float):
         ritz = np.zeros(4096)

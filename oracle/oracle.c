@@ -84,6 +84,7 @@ typedef struct {
     int m_req;
     int samp_method;   /* 0: method A (Appendix A), 1: method B (relative-residual thresholds) */
     int samp_resid;    /* 1: store residual vectors r_i instead of iterates x_i */
+    int rr_op;         /* Rayleigh-Ritz operator: 0 A (eq. (Rayleigh-Ritz)), 1 M^{-1}A (its footnote) */
     double *slots; int32_t *slot_iter; double *xN;
     /* auxiliary space (permuted order, column-major n x k) */
     int m_bar, m_tilde;
@@ -487,6 +488,30 @@ static int finish_aux(orc *o) {
     return cholesky(k, o->C, o->R);
 }
 
+/* y = M x = L (L^T x) with the IC(0) factor L (lower, diagonal included). */
+static void apply_M_product(const orc *o, const double *x, double *y) {
+    int64_t n = o->n;
+    double *t = calloc(n, sizeof(double));
+    for (int64_t i = 0; i < n; ++i)              /* t = L^T x, row i of L scattered */
+        for (int64_t a = o->lrp[i]; a < o->lrp[i + 1]; ++a) t[o->lcol[a]] += o->lval[a] * x[i];
+    for (int64_t i = 0; i < n; ++i) {            /* y = L t */
+        double s = 0.0;
+        for (int64_t a = o->lrp[i]; a < o->lrp[i + 1]; ++a) s += o->lval[a] * t[o->lcol[a]];
+        y[i] = s;
+    }
+    free(t);
+}
+
+/* Operator of the next build_aux's Rayleigh-Ritz step: 0 = A, 1 = the
+ * preconditioned matrix M^{-1}A (footnote of eq. (Rayleigh-Ritz)), taken in
+ * the M inner product where it is self-adjoint: E^T A E t = lambda E^T M E t. */
+int orc_set_rr(orc *o, int op) {
+    if (op != 0 && op != 1) return OR_EINVAL;
+    if (op == 1 && !o->factored) return OR_EINVAL;
+    o->rr_op = op;
+    return OR_OK;
+}
+
 /* Rayleigh-Ritz on the span of the sampled error vectors (Sec. 4.2):
  * eq. (ek) error vectors, eq. (ekd) Gram-Schmidt, eq. (Rayleigh-Ritz) the
  * projected eigenproblem with A itself, eq. (bk) selection below theta. */
@@ -540,7 +565,58 @@ int orc_build_aux(orc *o, double theta, double *ritz_out, int *m_bar, int *m_til
             double s = 0.5 * (G[a * kept + b] + G[b * kept + a]);
             G[a * kept + b] = G[b * kept + a] = s;
         }
-    orc_sym_eig(kept, G, o->ritz, V);
+    if (o->rr_op == 1) {
+        /* generalised problem G t = lambda B t with B = E^T M E = R R^T:
+         * eig of R^{-1} G R^{-T}, then t = R^{-T} v */
+        double *ME = malloc(n * sizeof(double));
+        double *B = malloc((size_t)kept * kept * sizeof(double));
+        double *R = malloc((size_t)kept * kept * sizeof(double));
+        double *H = malloc((size_t)kept * kept * sizeof(double));
+        for (int b = 0; b < kept; ++b) {
+            apply_M_product(o, E + (int64_t)b * n, ME);
+            for (int a = 0; a < kept; ++a) B[a * kept + b] = dot(n, E + (int64_t)a * n, ME);
+        }
+        for (int a = 0; a < kept; ++a)
+            for (int b = 0; b < a; ++b) {
+                double sb = 0.5 * (B[a * kept + b] + B[b * kept + a]);
+                B[a * kept + b] = B[b * kept + a] = sb;
+            }
+        if (cholesky(kept, B, R) != OR_OK) {
+            free(ME); free(B); free(R); free(H); free(G); free(V); free(v); free(E); free(AE);
+            return OR_ENUMERIC;
+        }
+        /* H = R^{-1} G R^{-T}: solve R X = G, then R H^T = X^T */
+        for (int c2 = 0; c2 < kept; ++c2)
+            for (int i = 0; i < kept; ++i) {
+                double sx = G[i * kept + c2];
+                for (int t = 0; t < i; ++t) sx -= R[i * kept + t] * H[t * kept + c2];
+                H[i * kept + c2] = sx / R[i * kept + i];
+            }
+        for (int a = 0; a < kept; ++a)
+            for (int b = 0; b < kept; ++b) G[a * kept + b] = H[b * kept + a]; /* G <- X^T */
+        for (int c2 = 0; c2 < kept; ++c2)
+            for (int i = 0; i < kept; ++i) {
+                double sx = G[i * kept + c2];
+                for (int t = 0; t < i; ++t) sx -= R[i * kept + t] * H[t * kept + c2];
+                H[i * kept + c2] = sx / R[i * kept + i];
+            }
+        for (int a = 0; a < kept; ++a)
+            for (int b = 0; b < a; ++b) {
+                double sh = 0.5 * (H[a * kept + b] + H[b * kept + a]);
+                H[a * kept + b] = H[b * kept + a] = sh;
+            }
+        double *Vh = malloc((size_t)kept * kept * sizeof(double));
+        orc_sym_eig(kept, H, o->ritz, Vh);
+        for (int j = 0; j < kept; ++j)           /* t_j = R^{-T} v_j */
+            for (int i = kept - 1; i >= 0; --i) {
+                double sv = Vh[i * kept + j];
+                for (int t = i + 1; t < kept; ++t) sv -= R[t * kept + i] * V[t * kept + j];
+                V[i * kept + j] = sv / R[i * kept + i];
+            }
+        free(ME); free(B); free(R); free(H); free(Vh);
+    } else {
+        orc_sym_eig(kept, G, o->ritz, V);
+    }
     if (ritz_out) memcpy(ritz_out, o->ritz, kept * sizeof(double));
     int sel = 0;
     while (sel < kept && o->ritz[sel] < theta) ++sel;                   /* eq. (bk) */

@@ -381,6 +381,62 @@ def test_gram_schmidt_and_rayleigh_ritz():
     assert np.abs(Cm - W.T @ A @ W).max() < 1e-14
 
 
+def _dense_M(o, n):
+    """M = L L^T from the oracle's IC(0) factor (logical order), in user order."""
+    rp, c, v = o.factor_csr()
+    L = np.zeros((n, n))
+    for i in range(n):
+        L[i, c[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    M = L @ L.T
+    perm = o.perm  # logical position -> user row
+    Mu = np.zeros((n, n))
+    Mu[np.ix_(perm, perm)] = M
+    return Mu
+
+
+def test_rayleigh_ritz_on_the_preconditioned_matrix():
+    """Footnote of eq. (Rayleigh-Ritz): the preconditioned matrix M^{-1}A, in
+    the M inner product.  Ritz values = generalised eigenvalues of
+    (E^T A E, E^T M E) (scipy), bounded below by lambda_min(M^{-1}A); W is
+    M-orthonormal and C = W^T A W = diag(Ritz)."""
+    p = P.config1(N=24, nbox=2, box=4)
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    o.arm_sampling(8)
+    o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE)
+    o.set_rayleigh_ritz(1)
+    st, ritz, mb, mt = o.build_aux(0.5)
+    E, W, AW, Cm = o.aux()
+    A = dense(p)
+    M = _dense_M(o, p.n)
+    want = sla.eigh(E.T @ A @ E, E.T @ M @ E, eigvals_only=True)
+    assert np.abs(ritz - want).max() <= 1e-10 * want.max()
+    lam = sla.eigh(A, M, eigvals_only=True)
+    assert ritz[0] >= lam[0] * (1 - 1e-10) and ritz[-1] <= lam[-1] * (1 + 1e-10)
+    assert mt == int(np.sum(ritz < 0.5)) and mt > 0
+    assert np.abs(W.T @ M @ W - np.eye(mt)).max() <= 1e-10
+    assert np.abs(Cm - np.diag(ritz[:mt])).max() <= 1e-10
+
+
+def test_rayleigh_ritz_preconditioned_recovers_exact_generalised_eigenpairs():
+    """Samples whose errors are exact eigenvectors of A v = lambda M v give
+    exactly those eigenvalues as Ritz values (the A-based problem does not)."""
+    p = P.config1(N=16, nbox=1, box=4)
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    A = dense(p)
+    M = _dense_M(o, p.n)
+    lam, V = sla.eigh(A, M)
+    xN = np.random.default_rng(3).standard_normal(p.n)
+    o.load_samples(xN[:, None] - V[:, :4], xN)
+    o.set_rayleigh_ritz(1)
+    st, ritz, mb, mt = o.build_aux(1.0)
+    assert np.abs(ritz - lam[:4]).max() <= 1e-10 * lam[3]
+    o.set_rayleigh_ritz(0)
+    st, ritz_a, _, _ = o.build_aux(1.0)
+    assert np.abs(ritz_a - lam[:4]).max() > 1e-3 * lam[3]
+
+
 def test_error_vectors_span_contains_errors():
     p = P.config1()
     o = O.Oracle.from_problem(p)
