@@ -159,6 +159,17 @@ esd_status esd_load_samples(esd_ctx *ctx, const double *X, int32_t k, const doub
 esd_status esd_build_aux(esd_ctx *ctx, double theta, double *ritz, int32_t *m_bar,
                          int32_t *m_tilde);
 
+/* esd_set_rayleigh_ritz - operator of the Rayleigh-Ritz step of the next
+ * esd_build_aux calls: ESD_RR_A (default) solves E^T A E t = lambda t (eq.
+ * (Rayleigh-Ritz)); ESD_RR_PRECONDITIONED uses the preconditioned matrix
+ * M^{-1}A (the footnote of that equation) in the M inner product, where it
+ * is self-adjoint: E^T A E t = lambda E^T M E t with M = L L^T the IC(0)
+ * factor (esd_build_aux then needs esd_factor_ic0); theta then thresholds
+ * Ritz values of M^{-1}A.  ESD_EINVAL for another op. */
+#define ESD_RR_A 0
+#define ESD_RR_PRECONDITIONED 1
+esd_status esd_set_rayleigh_ritz(esd_ctx *ctx, int32_t op);
+
 /* esd_set_aux - use a caller-given auxiliary matrix W(d): n x k, column-major,
  * float64, user row order, full column rank, 1 <= k <= 64.  Replaces any W. */
 esd_status esd_set_aux(esd_ctx *ctx, const double *W, int32_t k);

@@ -138,6 +138,8 @@ struct esd_ctx {
     uint32_t epoch = 1;
     bool use_graphs = true;
     bool class_layout = true; // class-aligned matrix copies for the iteration kernels when they fit
+    int rr_op = 0;            // Rayleigh-Ritz operator of build_aux: 0 A, 1 M^{-1}A
+    double *ME = nullptr;     // M E for the preconditioned Rayleigh-Ritz (allocated on first use)
     hipStream_t cap = nullptr; // private stream the chunks are captured on
     // kernel timing
     std::vector<hipEvent_t> ev;
@@ -1033,7 +1035,7 @@ void esd_destroy(esd_ctx *c) {
                     c->b, c->x, c->r, c->z, c->zsc, c->y, c->q, c->p[0], c->p[1], c->t, c->v[0], c->v[1],
                     c->r32, c->z32, c->zsc32, c->y32, c->q32, c->p32[0], c->p32[1], c->d32, c->v32[0], c->v32[1],
                     c->tmap, c->tmap_lvl, c->part_spmv, c->part_upd, c->part_gen, c->part_sweep, c->part_ts, c->W_rm, c->W32_rm, c->AW_rm, c->AW32_rm, c->S, c->slots, c->slot_table, c->xN,
-                    c->E, c->AE, c->W, c->AW, c->W32, c->AW32, c->Cinv, c->gram_part, c->G, c->Tm, c->ha, c->hb};
+                    c->E, c->AE, c->ME, c->W, c->AW, c->W32, c->AW32, c->Cinv, c->gram_part, c->G, c->Tm, c->ha, c->hb};
     for (void *p : ptrs) if (p) hipFree(p);
     if (c->Sh) hipHostFree(c->Sh);
     for (auto &e : c->ev) (void)hipEventDestroy(e);
@@ -1469,7 +1471,29 @@ esd_status esd_build_aux(esd_ctx *c, double theta, double *ritz, int32_t *m_bar,
             const double s = 0.5 * (G[(size_t)i * kept + j] + G[(size_t)j * kept + i]);
             G[(size_t)i * kept + j] = G[(size_t)j * kept + i] = s;
         }
-    esd::jacobi_eigh(kept, G, w, V);
+    if (c->rr_op == 1) {
+        // preconditioned matrix (footnote of eq. (Rayleigh-Ritz)) in the M
+        // inner product: G t = lambda B t with B = E^T M E, M e = L (L^T e)
+        if (!c->factored) return fail(c, ESD_EINVAL, "Rayleigh-Ritz on M^{-1}A needs the IC(0) factor");
+        if (!c->ME) HIPCHK(dalloc(&c->ME, (int64_t)c->m_max * n));
+        for (int j = 0; j < kept; ++j) {
+            esd::launch_tri_mul(n, c->U.e64(), c->ldiag, c->E + (size_t)j * n, c->t, c->stream);
+            esd::launch_tri_mul(n, c->L.e64(), c->ldiag, c->t, c->ME + (size_t)j * n, c->stream);
+        }
+        esd::launch_gram(n, c->E, kept, c->ME, kept, c->gram_part, c->G, esd::gram_grid(n), c->stream);
+        std::vector<double> B((size_t)kept * kept);
+        HIPCHK(hipMemcpyAsync(B.data(), c->G, sizeof(double) * kept * kept, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < kept; ++i)
+            for (int j = 0; j < i; ++j) {
+                const double sb = 0.5 * (B[(size_t)i * kept + j] + B[(size_t)j * kept + i]);
+                B[(size_t)i * kept + j] = B[(size_t)j * kept + i] = sb;
+            }
+        if (!esd::generalized_eigh(kept, G, B, w, V))
+            return fail(c, ESD_ENUMERIC, "E^T M E is not positive definite");
+    } else {
+        esd::jacobi_eigh(kept, G, w, V);
+    }
     c->ritz = w;
     if (ritz) std::memcpy(ritz, w.data(), sizeof(double) * kept);
     int sel = 0;
@@ -1485,6 +1509,13 @@ esd_status esd_build_aux(esd_ctx *c, double theta, double *ritz, int32_t *m_bar,
     esd::launch_tsgemm(n, c->AE, kept, c->Tm, sel, c->AW, c->stream);
     HIPCHK(hipGetLastError());
     return finish_aux(c, sel);
+}
+
+esd_status esd_set_rayleigh_ritz(esd_ctx *c, int32_t op) {
+    if (!c) return ESD_EINVAL;
+    if (op != ESD_RR_A && op != ESD_RR_PRECONDITIONED) return fail(c, ESD_EINVAL, "unknown Rayleigh-Ritz operator");
+    c->rr_op = op;
+    return ESD_OK;
 }
 
 esd_status esd_set_aux(esd_ctx *c, const double *W, int32_t k) {

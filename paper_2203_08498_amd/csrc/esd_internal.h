@@ -73,6 +73,12 @@ void sampling_table(int m, int64_t maxit, std::vector<int32_t> &slot_of_iter);
 // Small dense kernels of the host side (own implementations).
 void jacobi_eigh(int k, std::vector<double> &a, std::vector<double> &w, std::vector<double> &V);
 bool cholesky_inverse(int k, const std::vector<double> &C, std::vector<double> &Cinv);
+// G t = lambda B t for symmetric G and SPD B (k x k, column-major): B = R R^T,
+// eigenpairs of R^{-1} G R^{-T} (Jacobi), t = R^{-T} v, so T^T B T = I.
+// Eigenvalues ascending in w, vectors in the columns of T.  False when B is
+// not positive definite.
+bool generalized_eigh(int k, const std::vector<double> &G, const std::vector<double> &B, std::vector<double> &w,
+                      std::vector<double> &T);
 void tridiag_extremes(int k, const double *alpha, const double *beta, double *tmin, double *tmax);
 
 } // namespace esd

@@ -426,4 +426,54 @@ bool ell_classes(const HostEll &E, int64_t n, int max_width, std::vector<int64_t
     return true;
 }
 
+bool generalized_eigh(int k, const std::vector<double> &G, const std::vector<double> &B, std::vector<double> &w,
+                      std::vector<double> &T) {
+    auto at = [k](const std::vector<double> &a, int i, int j) { return a[(size_t)j * k + i]; };
+    std::vector<double> R((size_t)k * k, 0.0); // lower, column-major
+    auto r = [&](int i, int j) -> double & { return R[(size_t)j * k + i]; };
+    for (int j = 0; j < k; ++j) {
+        double s = at(B, j, j);
+        for (int t = 0; t < j; ++t) s -= r(j, t) * r(j, t);
+        if (!(s > 0.0)) return false;
+        r(j, j) = std::sqrt(s);
+        for (int i = j + 1; i < k; ++i) {
+            double u = at(B, i, j);
+            for (int t = 0; t < j; ++t) u -= r(i, t) * r(j, t);
+            r(i, j) = u / r(j, j);
+        }
+    }
+    // X = R^{-1} G (forward substitution, column by column)
+    std::vector<double> X((size_t)k * k);
+    for (int c = 0; c < k; ++c)
+        for (int i = 0; i < k; ++i) {
+            double s = at(G, i, c);
+            for (int t = 0; t < i; ++t) s -= r(i, t) * X[(size_t)c * k + t];
+            X[(size_t)c * k + i] = s / r(i, i);
+        }
+    // H = X R^{-T}: row i of H solves R h = (row i of X)^T
+    std::vector<double> H((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+        for (int c = 0; c < k; ++c) {
+            double s = X[(size_t)c * k + i];
+            for (int t = 0; t < c; ++t) s -= r(c, t) * H[(size_t)t * k + i];
+            H[(size_t)c * k + i] = s / r(c, c);
+        }
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double s = 0.5 * (H[(size_t)j * k + i] + H[(size_t)i * k + j]);
+            H[(size_t)j * k + i] = H[(size_t)i * k + j] = s;
+        }
+    std::vector<double> V;
+    jacobi_eigh(k, H, w, V);
+    // T = R^{-T} V (back substitution, column by column)
+    T.assign((size_t)k * k, 0.0);
+    for (int c = 0; c < k; ++c)
+        for (int i = k - 1; i >= 0; --i) {
+            double s = V[(size_t)c * k + i];
+            for (int t = i + 1; t < k; ++t) s -= r(t, i) * T[(size_t)c * k + t];
+            T[(size_t)c * k + i] = s / r(i, i);
+        }
+    return true;
+}
+
 } // namespace esd

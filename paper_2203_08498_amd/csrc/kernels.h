@@ -181,6 +181,9 @@ struct FinGen {
     int store_svec;   // S->svec = s
 };
 
+// y = diag(d) x + M x over the stored entries (sorted layout): L^T x with
+// M = U, L x with M = L, d = diag(L)
+void launch_tri_mul(int n, Ell<double> M, const double *d, const double *x, double *y, hipStream_t s);
 // to64[e] = from[src[e]] (0 where src[e] < 0), to32 = (float)to64: values of
 // a class-aligned copy from the sorted layout
 void launch_repack(int64_t size, const int64_t *src, const double *from, double *to64, float *to32, hipStream_t s);

@@ -881,6 +881,25 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int n, Ell<double> A, const dou
     }
 }
 
+// y_i = d_i x_i + sum_j M_ij x_j over the stored entries of row i (sorted
+// layout; padding skipped): with M = U and d = diag(L) this is L^T x, with
+// M = L it is L x.
+__global__ __launch_bounds__(kBlock) void k_tri_mul(int n, Ell<double> M, const double *d, const double *x,
+                                                    double *y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int lane = i & 63;
+    const int64_t base = M.sptr[i >> 6];
+    const int w = (int)((M.sptr[(i >> 6) + 1] - base) >> 6);
+    double s = d[i] * x[i];
+    for (int e = 0; e < w; ++e) {
+        const int64_t pos = base + (int64_t)e * 64 + lane;
+        const int c = M.col[pos];
+        if (c < n) s += M.val[pos] * x[c];
+    }
+    y[i] = s;
+}
+
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // Block partial of G = E^T F (E: n x ma, F: n x mb, column-major, ma, mb <= 64)
@@ -1006,6 +1025,10 @@ int tsdot_grid(int64_t n, int m) {
     if (g > cap) g = cap;
     if (g > 8) g = g / 8 * 8;
     return g < 1 ? 1 : (int)g;
+}
+
+void launch_tri_mul(int n, Ell<double> M, const double *d, const double *x, double *y, hipStream_t s) {
+    k_tri_mul<<<blocks(n), kBlock, 0, s>>>(n, M, d, x, y);
 }
 
 void launch_repack(int64_t size, const int64_t *src, const double *from, double *to64, float *to32, hipStream_t s) {

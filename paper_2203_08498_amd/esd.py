@@ -19,6 +19,7 @@ PLAIN, DEFLATED, SUBSPACE = 0, 1, 2
 FLAG_NOPREC, FLAG_POWER, FLAG_MIXED, FLAG_SYNC_EVERY, FLAG_TIMING, FLAG_TIMING_SPMV, FLAG_TRUE_RES = 1, 2, 4, 8, 16, 32, 64
 FLAG_STREAM = 128
 SAMPLING_A, SAMPLING_B, SAMPLE_RESIDUALS = 0, 1, 16
+RR_A, RR_PRECONDITIONED = 0, 1
 OK, NOT_CONVERGED, AUX_EMPTY = 0, 1, 2
 EINVAL, ENOTSPD, EHIP, ENUMERIC, ENOAUX, ENOSAMPLES = -1, -2, -3, -4, -5, -6
 
@@ -41,7 +42,7 @@ EXPORTS = [
     "esd_setup", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
     "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
     "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag", "esd_get_history", "esd_get_samples",
-    "esd_get_sample_vector",
+    "esd_get_sample_vector", "esd_set_rayleigh_ritz",
     "esd_get_layout", "esd_get_timing", "esd_status_string", "esd_last_error", "esd_destroy",
 ]
 
@@ -78,6 +79,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_get_history.argtypes = [P, P, P, i32, P]
     L.esd_get_samples.argtypes = [P, P]
     L.esd_get_sample_vector.argtypes = [P, i32, P]
+    L.esd_set_rayleigh_ritz.argtypes = [P, i32]
     L.esd_get_layout.argtypes = [P, P]
     L.esd_get_timing.argtypes = [P, P]
     L.esd_status_string.argtypes = [C.c_int]
@@ -89,7 +91,8 @@ def load_library(path: str = LIB_PATH):
                  "esd_set_aux",
                  "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs",
                  "esd_grad_values", "esd_spmv", "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag",
-                 "esd_get_history", "esd_get_samples", "esd_get_sample_vector", "esd_get_layout", "esd_get_timing"):
+                 "esd_get_history", "esd_get_samples", "esd_get_sample_vector", "esd_get_layout", "esd_get_timing",
+                 "esd_set_rayleigh_ritz"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -307,6 +310,11 @@ class Solver:
         out = np.zeros(m, np.int32)
         self._check(self.L.esd_get_samples(self.h, out.ctypes.data_as(C.c_void_p)))
         return out
+
+    def set_rayleigh_ritz(self, op: int):
+        """0: Rayleigh-Ritz with A (eq. (Rayleigh-Ritz)); 1: with the
+        preconditioned matrix M^{-1}A in the M inner product (its footnote)."""
+        self._check(self.L.esd_set_rayleigh_ritz(self.h, int(op)))
 
     def sample_vector(self, slot: int):
         """The vector stored in sampling slot `slot` (user order, float64 tensor)."""

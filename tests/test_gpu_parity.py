@@ -163,6 +163,44 @@ def test_rayleigh_ritz_on_identical_samples(case):
         assert np.abs(Cm - np.diag(ritz[:mt])).max() <= 1e-12
 
 
+def test_rayleigh_ritz_preconditioned_on_identical_samples(case):
+    """build_aux with the preconditioned matrix (footnote of eq. (Rayleigh-Ritz))
+    on the same samples: Ritz values to 1e-10, the same selected subspace, and a
+    deflated solve with that W against the oracle."""
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    rng = np.random.default_rng(12)
+    xN = rng.standard_normal(p.n)
+    E0 = rng.standard_normal((p.n, 6))
+    for _ in range(3):
+        E0 = E0 - 0.5 * np.column_stack([o.spmv(E0[:, j]) for j in range(E0.shape[1])])
+    s.load_samples(xN[:, None] - E0, xN)
+    o.load_samples(xN[:, None] - E0, xN)
+    s.set_rayleigh_ritz(esd.RR_PRECONDITIONED)
+    o.set_rayleigh_ritz(1)
+    try:
+        theta = _theta(o)
+        st, ritz, mb, mt = s.build_aux(theta)
+        ost, oritz, omb, omt = o.build_aux(theta)
+        print(name, "preconditioned Ritz", ritz[:4], "m_tilde", mt, flush=True)
+        assert (mb, mt) == (omb, omt) and mt > 0
+        assert np.max(np.abs(ritz - oritz) / np.abs(oritz)) <= 1e-10
+        W, Cm = s.get_aux()
+        _, Wo, _, _ = o.aux()
+        Wn = W.cpu().numpy()
+        Pg = Wn @ np.linalg.solve(Wn.T @ Wn, Wn.T)
+        Po = Wo @ np.linalg.solve(Wo.T @ Wo, Wo.T)
+        assert np.abs(Pg - Po).max() <= 1e-9
+        b = P.sequence_rhs(p.f, np.zeros(p.n))
+        x, info = s.solve(b, tol=1e-8, maxit=5000, mode=esd.DEFLATED)
+        y, oi = o.solve(b, tol=1e-8, maxit=5000, mode=O.DEFLATED)
+        assert abs(info["iters"] - oi.iters) <= 2 and _relerr(x, y) <= 1e-10
+    finally:
+        s.set_rayleigh_ritz(esd.RR_A)
+        o.set_rayleigh_ritz(0)
+
+
 def test_sampling_build_aux_and_accelerated_solves(case):
     from paper_2203_08498_amd import esd
 
