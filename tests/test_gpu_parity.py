@@ -201,6 +201,58 @@ def test_rayleigh_ritz_preconditioned_on_identical_samples(case):
         o.set_rayleigh_ritz(0)
 
 
+def test_w_reuse_after_value_update(case):
+    """A slowly varying coefficient matrix (the use the paper anticipates in
+    Sec. 2): new values on the same pattern, the IC(0) factor redone, W kept
+    while AW and C = W^T A W follow the new values; deflated solves against the
+    oracle given the same W on the new matrix."""
+    import scipy.sparse as sp
+
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    # identical samples, so both sides build the same W on the old values
+    rng = np.random.default_rng(13)
+    xN = rng.standard_normal(p.n)
+    E0 = rng.standard_normal((p.n, 5))
+    for _ in range(3):
+        E0 = E0 - 0.5 * np.column_stack([o.spmv(E0[:, j]) for j in range(E0.shape[1])])
+    s.load_samples(xN[:, None] - E0, xN)
+    o.load_samples(xN[:, None] - E0, xN)
+    theta = _theta(o)
+    st, ritz, mb, mt = s.build_aux(theta)
+    ost, oritz, omb, omt = o.build_aux(theta)
+    assert mt == omt and mt > 0
+    _, Wo, _, _ = o.aux()
+    # new values: a symmetric +-5% perturbation of the off-diagonal couplings
+    # with the diagonal raised to keep the matrix diagonally dominant
+    d = rng.uniform(-0.05, 0.05, p.nnz)
+    Mx = sp.csr_matrix((d, p.col, p.rowptr), shape=(p.n, p.n))
+    Ms = (0.5 * (Mx + Mx.T)).tocsr()
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    dsym = np.asarray(Ms[rows, p.col]).ravel()
+    off = rows != p.col
+    val2 = p.val.copy()
+    val2[off] *= 1.0 + dsym[off]
+    val2[~off] *= 1.05
+    try:
+        s.update_values(val2)
+        s.factor_ic0()
+        o2 = O.Oracle(p.rowptr, p.col, val2, p.colors)
+        assert o2.factor_ic0() == 0
+        o2.set_aux(Wo)
+        b = P.sequence_rhs(p.f, np.zeros(p.n))
+        for mode, omode in ((esd.DEFLATED, O.DEFLATED), (esd.SUBSPACE, O.SUBSPACE)):
+            x, info = s.solve(b, tol=1e-8, maxit=5000, mode=mode)
+            y, oi = o2.solve(b, tol=1e-8, maxit=5000, mode=omode)
+            print(name, "W reuse mode", mode, "its", info["iters"], oi.iters, flush=True)
+            assert abs(info["iters"] - oi.iters) <= 2 and _relerr(x, y) <= 1e-10
+            assert info["true_relres"] <= 1.01e-8
+    finally:
+        s.update_values(p.val)
+        s.factor_ic0()
+
+
 def test_sampling_build_aux_and_accelerated_solves(case):
     from paper_2203_08498_amd import esd
 
