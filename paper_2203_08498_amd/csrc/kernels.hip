@@ -175,12 +175,24 @@ __device__ __forceinline__ void ell_chunk(const Ell<T> &M, int64_t base, int w, 
     }
 }
 
+// Start entry and width of row i's slice.  U: the caller guarantees that all
+// active lanes of the wavefront lie in the same 64-row slice (the row range
+// starts on a slice boundary), so the slice is read once per wavefront as a
+// scalar and the per-slot column offsets become scalar loads too.
+template <bool U, typename T>
+__device__ __forceinline__ void ell_slice(const Ell<T> &M, int i, int64_t &base, int &w) {
+    const int s = U ? __builtin_amdgcn_readfirstlane(i >> 6) : (i >> 6);
+    base = M.sptr[s];
+    w = (int)((M.sptr[s + 1] - base) >> 6);
+}
+
 // sum_k val_k * g(col_k) over one sliced-ELL row, eight slots at a time: the
 // slot loads, then the eight gathers, then the products.
-template <typename T, typename G>
+template <bool U = false, typename T, typename G>
 __device__ __forceinline__ T ell_dot(const Ell<T> &M, int i, int n, G g) {
-    const int64_t base = M.sptr[i >> 6];
-    const int w = (int)((M.sptr[(i >> 6) + 1] - base) >> 6);
+    int64_t base;
+    int w;
+    ell_slice<U>(M, i, base, w);
     T sum = T(0);
     for (int k0 = 0; k0 < w; k0 += 8) {
         int c[8];
@@ -196,10 +208,11 @@ __device__ __forceinline__ T ell_dot(const Ell<T> &M, int i, int n, G g) {
 }
 
 // two right-hand sides sharing the matrix loads: (A x, A y)
-template <typename T, typename G1, typename G2>
+template <bool U = false, typename T, typename G1, typename G2>
 __device__ __forceinline__ void ell_dot2(const Ell<T> &M, int i, int n, G1 g1, G2 g2, T &s1, T &s2) {
-    const int64_t base = M.sptr[i >> 6];
-    const int w = (int)((M.sptr[(i >> 6) + 1] - base) >> 6);
+    int64_t base;
+    int w;
+    ell_slice<U>(M, i, base, w);
     s1 = T(0);
     s2 = T(0);
     for (int k0 = 0; k0 < w; k0 += 8) {
@@ -242,19 +255,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
         if (i >= n) continue;
         T sum, vsum = T(0), pi;
         if constexpr (PG) {
-            if constexpr (POW) ell_dot2(a.A, i, n, [&](int c) { return pg[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
-            else sum = ell_dot(a.A, i, n, [&](int c) { return pg[c]; });
+            if constexpr (POW) ell_dot2<true>(a.A, i, n, [&](int c) { return pg[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
+            else sum = ell_dot<true>(a.A, i, n, [&](int c) { return pg[c]; });
             pi = pg[i];
         } else {
             if (first) {
                 if constexpr (POW)
-                    ell_dot2(a.A, i, n, [&](int c) { return z[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
-                else sum = ell_dot(a.A, i, n, [&](int c) { return z[c]; });
+                    ell_dot2<true>(a.A, i, n, [&](int c) { return z[c]; }, [&](int c) { return vo[c]; }, sum, vsum);
+                else sum = ell_dot<true>(a.A, i, n, [&](int c) { return z[c]; });
             } else {
                 if constexpr (POW)
-                    ell_dot2(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; }, [&](int c) { return vo[c]; },
+                    ell_dot2<true>(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; }, [&](int c) { return vo[c]; },
                              sum, vsum);
-                else sum = ell_dot(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; });
+                else sum = ell_dot<true>(a.A, i, n, [&](int c) { return z[c] + beta * po[c]; });
             }
             pi = first ? z[i] : z[i] + beta * po[i];
             a.pnew[i] = pi;
@@ -366,12 +379,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd(Sweep<T> a) {
     if (a.S->done) return;
     double acc[1] = {0.0};
     const T *y = a.y;
+    const bool aligned = (a.r0 & 63) == 0; // wavefronts then never straddle a slice
     const Tiles tl = my_tiles(a.r1 - a.r0);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = a.r0 + (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= a.r1) continue;
         const T ri = a.r[i];
-        const T s = ri - ell_dot(a.M, i, a.n, [&](int c) { return y[c]; });
+        const auto gy = [&](int c) { return y[c]; };
+        const T s = ri - (aligned ? ell_dot<true>(a.M, i, a.n, gy) : ell_dot<false>(a.M, i, a.n, gy));
         const T yi = s * a.dinv[i];
         if constexpr (!LAST) {
             a.y[i] = yi;
@@ -392,11 +407,13 @@ __global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
     if (a.S->done) return;
     double acc[1] = {0.0};
     const T *z = a.z;
+    const bool aligned = (a.r0 & 63) == 0; // wavefronts then never straddle a slice
     const Tiles tl = my_tiles(a.r1 - a.r0);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = a.r0 + (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= a.r1) continue;
-        const T s = a.y[i] - ell_dot(a.M, i, a.n, [&](int c) { return z[c]; });
+        const auto gz = [&](int c) { return z[c]; };
+        const T s = a.y[i] - (aligned ? ell_dot<true>(a.M, i, a.n, gz) : ell_dot<false>(a.M, i, a.n, gz));
         const T zi = s * a.dinv[i];
         a.z[i] = zi;
         const T zs = add_coarse<T, SC>(a, i, zi);
@@ -748,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_tsdot(int n, const double *W, int m,
 __global__ __launch_bounds__(kBlock) void k_spmv(int n, Ell<double> A, const double *x, double *y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    y[i] = ell_dot(A, i, n, [&](int c) { return x[c]; });
+    y[i] = ell_dot<true>(A, i, n, [&](int c) { return x[c]; });
 }
 
 template <typename T>
