@@ -259,6 +259,8 @@ int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_
         esd::launch_copyz(s, sc, g, c->stream);
         return g;
     }
+    // rho partial rows: every forward launch (||y||^2) without subspace
+    // correction; the last forward and every backward launch with it
     int off = 0;
     const int nl = (int)c->lvl.size() - 1;
     s.M = V.L;
@@ -269,7 +271,7 @@ int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_
         const int g = esd::grid_red(s.r1 - s.r0, 1);
         s.part = c->part_sweep + off;
         esd::launch_fwd(s, last, sc, g, c->stream);
-        if (last) off += g;
+        if (last || !sc) off += g;
     }
     s.M = V.U;
     for (int l = nl - 2; l >= 0; --l) {
@@ -278,7 +280,7 @@ int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_
         const int g = esd::grid_red(s.r1 - s.r0, 1);
         s.part = c->part_sweep + off;
         esd::launch_bwd(s, sc, g, c->stream);
-        off += g;
+        if (sc) off += g;
     }
     return off;
 }
@@ -424,7 +426,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     ua.AW = V.AW; ua.m = 0;
     ua.l0 = fuse_l0 ? (int)c->lvl[1] : 0; ua.dinv = V.dinv; ua.y = V.y;
     esd::FinRho fr{};
-    fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = 1;
+    fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = 2;
+    fr.rho_upd = (fuse_l0 && !sc) ? 1 : 0;
     fr.part_sweep = c->part_sweep; fr.hist_beta = c->hb; fr.init = 0;
     fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
     if (o.sampling && o.method_b) {

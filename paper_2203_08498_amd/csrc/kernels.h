@@ -97,6 +97,7 @@ template <typename T> struct UpdIt {
     const T *dinv;
     T *y;
     const int32_t *tmap; // tile order (nullptr: natural)
+    // partials: column 0 ||r||^2, column 1 ||y||^2 of the fused level-0 rows
 };
 
 // Tall-skinny s = W^T v with W row-major (n x m, W[i m + k]): lane t of a
@@ -110,6 +111,10 @@ template <typename T> struct TsDot {
     const Scal *S; // skip when S->done (may be null)
 };
 
+// rho = (r, z) of z = M^{-1} r: without subspace correction it equals ||y||^2
+// with y = L^{-1} r (M = L L^T), so the forward launches reduce y^2 and the
+// backward ones reduce nothing; with subspace correction (z + W u) the last
+// forward level and the backward levels reduce (r, z + W u) as before.
 // one level of the forward (L y = r) or backward (L^T z = y) IC(0) sweep;
 // launches that finish rows of z write one (r, z) partial per block
 template <typename T> struct Sweep {
@@ -141,10 +146,11 @@ struct FinAlpha {
 // deflation also mu = C^{-1} (AW)^T z for the projected direction
 struct FinRho {
     Scal *S;
-    const double *part_upd; // column 0 = ||r||^2 partials
+    const double *part_upd; // column 0 = ||r||^2 partials, column 1 = ||y||^2 of the fused level-0 rows
     int nblk_upd, stride_upd;
-    const double *part_sweep;
+    const double *part_sweep; // rho partials of the preconditioner launches
     int nsweep;
+    int rho_upd; // rho also takes column 1 of the update partials (level 0 fused there)
     double *hist_beta;
     int init; // first preconditioner application of a solve: only rho
     const double *part_s; // (AW)^T z partials (deflated), nblk_s x stride_s

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
     const T ta = (T)S->alpha;
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
     const int n = a.n, m = a.m;
     double mu[KIND == 1 ? MT : 1];
     if constexpr (KIND == 1) {
@@ -314,9 +314,13 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
         const T ri = a.r[i] - ta * wi;
         a.r[i] = ri;
         acc[0] += (double)ri * (double)ri;
-        if (i < a.l0) a.y[i] = ri * a.dinv[i];
+        if (i < a.l0) {
+            const T yi = ri * a.dinv[i];
+            a.y[i] = yi;
+            acc[1] += (double)yi * (double)yi;
+        }
     }
-    block_partials<1>(acc, a.part, 1);
+    block_partials<2>(acc, a.part, 2);
 }
 
 // s = W^T v, W row-major n x m; P = next power of two >= m.  Lane l of a
@@ -388,18 +392,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd(Sweep<T> a) {
         const auto gy = [&](int c) { return y[c]; };
         const T s = ri - (aligned ? ell_dot<true>(a.M, i, a.n, gy) : ell_dot<false>(a.M, i, a.n, gy));
         const T yi = s * a.dinv[i];
+        if constexpr (!SC) acc[0] += (double)yi * (double)yi;
         if constexpr (!LAST) {
             a.y[i] = yi;
         } else {
             // no logically-later neighbour: the backward solve of this row is immediate
             const T zi = yi * a.dinv[i];
             a.z[i] = zi;
-            const T zs = add_coarse<T, SC>(a, i, zi);
-            if constexpr (SC) a.zsc[i] = zs;
-            acc[0] += (double)ri * (double)zs;
+            if constexpr (SC) {
+                const T zs = add_coarse<T, SC>(a, i, zi);
+                a.zsc[i] = zs;
+                acc[0] += (double)ri * (double)zs;
+            }
         }
     }
-    if constexpr (LAST) block_partials<1>(acc, a.part, 1);
+    if constexpr (!SC || LAST) block_partials<1>(acc, a.part, 1);
 }
 
 template <typename T, bool SC>
@@ -416,11 +423,13 @@ __global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
         const T s = a.y[i] - (aligned ? ell_dot<true>(a.M, i, a.n, gz) : ell_dot<false>(a.M, i, a.n, gz));
         const T zi = s * a.dinv[i];
         a.z[i] = zi;
-        const T zs = add_coarse<T, SC>(a, i, zi);
-        if constexpr (SC) a.zsc[i] = zs;
-        acc[0] += (double)a.r[i] * (double)zs;
+        if constexpr (SC) {
+            const T zs = add_coarse<T, SC>(a, i, zi);
+            a.zsc[i] = zs;
+            acc[0] += (double)a.r[i] * (double)zs;
+        }
     }
-    block_partials<1>(acc, a.part, 1);
+    if constexpr (SC) block_partials<1>(acc, a.part, 1);
 }
 
 // M = I: z = r (+ W u for subspace correction)
@@ -498,7 +507,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_u(Scal *S, const double *pa
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
     Scal *S = f.S;
-    __shared__ double tot[2];
+    __shared__ double tot[3];
     __shared__ double sv[64];
     __shared__ double cinv[64 * 64];
     // every load of the scalar block and of C^{-1} is issued before the
@@ -516,15 +525,17 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
     const int mm = f.m * f.m;
     for (int k = t; k < mm; k += kFinThreads) cinv[k] = f.Cinv[k];
     {
-        // (r, z), (r, r) and, for deflation, (AW)^T z in one pass
+        // rho partials, (r, r) and level-0 ||y||^2, and for deflation (AW)^T z
+        // in one pass; tot = {(r, r), level-0 ||y||^2, preconditioner rho}
         const int nu = f.init ? 0 : f.nblk_upd;
         if (f.m > 0) {
-            const ColTab tab[3] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 1},
-                                   {f.part_upd, nu, f.stride_upd, 0, 1, tot},
+            const ColTab tab[3] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 2},
+                                   {f.part_upd, nu, f.stride_upd, 0, 2, tot + 0},
                                    {f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv}};
             fin_colsums<3>(tab);
         } else {
-            const ColTab tab[2] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 1}, {f.part_upd, nu, f.stride_upd, 0, 1, tot}};
+            const ColTab tab[2] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 2},
+                                   {f.part_upd, nu, f.stride_upd, 0, 2, tot + 0}};
             fin_colsums<2>(tab);
         }
     }
@@ -535,7 +546,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
         S->mu[t] = acc;
     }
     if (t == 0) {
-        const double rn = tot[1];
+        const double rn = tot[2] + (f.rho_upd ? tot[1] : 0.0);
         if (f.init) {
             S->rho = rn;
             if (!isfinite(rn)) S->done = 3;
