@@ -14,7 +14,7 @@ Gram-Schmidt, Rayleigh-Ritz, W, C = W^T A W), then systems 2..10 deflated.
 `value` = mean seconds per system of that step (sampling and build included).
 Timed beside it on the same sequence (extra fields, not `value`): plain ICCG
 throughout, the subspace-correction preconditioner, and the FP32/FP64 mixed
-deflated solver.
+solver, deflated and plain.
 
 Roofline: the dominant kernel is the per-iteration SpMV launch; its duration
 is measured with hipEvents on the solver's stream around every executed
@@ -172,7 +172,7 @@ def main():
     s = esd.Solver.from_problem(p, m_max=args.m)
     s.set_power_start(P.power_start(2, p.n))
     seqs = (("deflated", esd.DEFLATED, 0), ("plain", esd.PLAIN, 0), ("subspace", esd.SUBSPACE, 0),
-            ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED))
+            ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED), ("mixed_plain", esd.PLAIN, esd.FLAG_MIXED))
     for _ in range(args.warmup):
         for name, mode, pf in seqs:
             run_sequence(s, p, args, mode, esd, P, False, pf)
@@ -246,6 +246,7 @@ def main():
         "speedup_vs_plain": per_sys_plain / per_sys if per_sys > 0 else None,
         "subspace_s_per_system": per["subspace"],
         "mixed_deflated_s_per_system": per["mixed_deflated"],
+        "mixed_plain_s_per_system": per["mixed_plain"],
         "deflated_s_systems_2_to_K": float(np.mean([r["seconds"] for r in rd[1:]])) if len(rd) > 1 else None,
         "plain_s_systems_2_to_K": float(np.mean([r["seconds"] for r in rp[1:]])) if len(rp) > 1 else None,
         "iters_sampling_solve": rd[0]["iters"],
@@ -258,6 +259,7 @@ def main():
         "iters_plain_mean": float(np.mean(its_plain)),
         "iters_subspace_mean": float(np.mean([r["iters"] for r in recs["subspace"][1:]])) if args.systems > 1 else None,
         "iters_mixed_deflated_mean": float(np.mean([r["iters"] for r in recs["mixed_deflated"][1:]])) if args.systems > 1 else None,
+        "iters_mixed_plain_mean": float(np.mean([r["iters"] for r in recs["mixed_plain"]])),
         "mixed_fp64_iters_total": int(sum(r["fp64_iters"] for r in recs["mixed_deflated"])),
         "true_relres_max": max(r["true_relres"] for r in rd),
         "mixed_true_relres_max": max(r["true_relres"] for r in recs["mixed_deflated"]),
