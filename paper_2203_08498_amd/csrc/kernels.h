@@ -239,13 +239,11 @@ void launch_axpy_cols(int n, double *y, const double *M, int m, const double *co
 // partials W^T v (stride bucket(m))
 void launch_tsdot(int n, const double *W, int m, const double *v, double *part, int *nblk, int *stride,
                   hipStream_t s);
-// y = A x (FP64)
+// y = A x (FP64, either layout)
 void launch_spmv(int n, Ell<double> A, const double *x, double *y, hipStream_t s);
 // partials (v, A v)
 void launch_rayleigh(int n, Ell<double> A, const double *v, double *part, int *nblk, hipStream_t s);
 void launch_rayleigh(int n, Ell<float> A, const float *v, double *part, int *nblk, hipStream_t s);
-// out[k] = scale * sum_j Cinv[k m + j] s[j] (one block)
-void launch_coarse(int m, const double *Cinv, const double *s, double scale, double *out, hipStream_t st);
 // sample store of the iterate (used when a solve stops at maxit)
 void launch_sample_store(int n, double *slot, const double *x, hipStream_t s);
 // casts

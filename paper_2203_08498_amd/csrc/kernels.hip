@@ -799,15 +799,6 @@ __global__ __launch_bounds__(kBlock) void k_rayleigh(int n, Ell<T> A, const T *v
     block_partials<1>(acc, part, 1);
 }
 
-__global__ void k_coarse(int m, const double *Cinv, const double *s, double scale, double *out) {
-    const int k = threadIdx.x;
-    if (k < m) {
-        double acc = 0.0;
-        for (int j = 0; j < m; ++j) acc += Cinv[k * m + j] * s[j];
-        out[k] = scale * acc;
-    }
-}
-
 // ------------------------------------------------------------------------
 // IC(0) factor, one level of rows at a time
 // ------------------------------------------------------------------------
@@ -1190,9 +1181,6 @@ void launch_rayleigh(int n, Ell<float> A, const float *v, double *part, int *nbl
     const int g = grid_red(n, 1);
     k_rayleigh<float><<<g, kBlock, 0, s>>>(n, A, v, part);
     *nblk = g;
-}
-void launch_coarse(int m, const double *Cinv, const double *s, double scale, double *out, hipStream_t st) {
-    if (m > 0) k_coarse<<<1, 64, 0, st>>>(m, Cinv, s, scale, out);
 }
 void launch_sample_store(int n, double *slot, const double *x, hipStream_t s) {
     k_scale_copy<<<blocks(n), kBlock, 0, s>>>(n, x, slot, 1.0);
