@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -138,6 +139,7 @@ struct esd_ctx {
     uint32_t epoch = 1;
     bool use_graphs = true;
     bool class_layout = true; // class-aligned matrix copies for the iteration kernels when they fit
+    bool trace = false;       // ESD_TRACE set: one stderr line per refinement step of the mixed solver
     int rr_op = 0;            // Rayleigh-Ritz operator of build_aux: 0 A, 1 M^{-1}A
     double *ME = nullptr;     // M E for the preconditioned Rayleigh-Ritz (allocated on first use)
     hipStream_t cap = nullptr; // private stream the chunks are captured on
@@ -844,6 +846,9 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         st = sync_read(c);
         if (st) return st;
         rn2 = c->Sh->out;
+        if (c->trace)
+            fprintf(stderr, "esd mixed: step %d relres %.3e after %d iterations (%d FP64), last inner exit %d\n",
+                    outer, bn2 > 0 ? std::sqrt(rn2 / bn2) : std::sqrt(rn2), total, fp64_iters, done_in);
         if (!(rn2 <= 1e300)) return fail(c, ESD_ENUMERIC, "non-finite residual");
         if (rn2 <= tol2) { converged = true; break; }
         if (total >= maxit || outer == c->max_outer) break;
@@ -1056,6 +1061,7 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     if (!c) return ESD_EINVAL;
     c->stream = (hipStream_t)hip_stream;
     c->m_max = m_max;
+    c->trace = std::getenv("ESD_TRACE") != nullptr;
     esd::HostLayout H;
     std::string why = esd::build_layout(n, rowptr, col, val, colors, H);
     if (!why.empty()) {

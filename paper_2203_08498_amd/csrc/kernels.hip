@@ -561,10 +561,14 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
         else if (rr <= tol2) d = 1;
         else if (it >= maxit) d = 2;
         else if (stag > 0) {
+            // FP32 inner solves: no 10% drop of ||r|| for `stag` iterations once
+            // the residual is within 100x of the target (the rounding floor),
+            // or for 10 x stag iterations before (CG residual norms may stall
+            // for a while early on without the iteration being stuck)
             if (rr < 0.81 * rr_ref) {
                 S->rr_ref = rr;
                 S->it_ref = it;
-            } else if (it - it_ref >= stag) {
+            } else if (it - it_ref >= (rr_ref <= 1e4 * tol2 ? stag : 10 * stag)) {
                 d = 4;
             }
         }
