@@ -135,7 +135,7 @@ esd_status esd_factor_ic0(esd_ctx *ctx);
  *     that sample, stored in the first of them, the others stay empty.
  *   | ESD_SAMPLE_RESIDUALS: store the residual r_i instead of x_i; build_aux
  *     then uses the residuals themselves instead of e = x_N - x_i (the
- *     residual-vector sampling of Sec. 5.3).
+ *     residual-vector sampling of Sec. 5.2).
  * ESD_EINVAL for an unknown method. */
 #define ESD_SAMPLING_A 0
 #define ESD_SAMPLING_B 1

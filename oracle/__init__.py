@@ -42,6 +42,8 @@ def lib():
         i64, i32, dbl = C.c_int64, C.c_int32, C.c_double
         L.orc_create.restype = P
         L.orc_create.argtypes = [i64, P, P, P, P]
+        L.orc_create_bj.restype = P
+        L.orc_create_bj.argtypes = [i64, P, P, P, i64]
         L.orc_free.argtypes = [P]
         L.orc_perm.argtypes = [P, P]
         L.orc_permuted_csr.argtypes = [P, P, P, P]
@@ -108,19 +110,29 @@ class SolveInfo(dict):
 class Oracle:
     """One matrix, in the given ordering, with its IC(0) factor and auxiliary space."""
 
-    def __init__(self, rowptr, col, val, colors=None):
+    def __init__(self, rowptr, col, val, colors=None, block_rows=None):
+        """colors: ordering by a stable sort on colour (None: natural order).
+        block_rows: block-Jacobi IC(0) (Sec. 5.3) with blocks of that many
+        consecutive rows in natural order (colors must then be None)."""
         self.rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.val = np.ascontiguousarray(val, dtype=np.float64)
         self.colors = None if colors is None else np.ascontiguousarray(colors, dtype=np.int32)
+        self.block_rows = block_rows
         self.n = self.rowptr.shape[0] - 1
-        self.h = lib().orc_create(self.n, _p(self.rowptr), _p(self.col), _p(self.val), _p(self.colors))
+        if block_rows is not None:
+            if colors is not None:
+                raise ValueError("oracle: block Jacobi takes the natural order")
+            self.h = lib().orc_create_bj(self.n, _p(self.rowptr), _p(self.col), _p(self.val), int(block_rows))
+        else:
+            self.h = lib().orc_create(self.n, _p(self.rowptr), _p(self.col), _p(self.val), _p(self.colors))
         if not self.h:
             raise ValueError("oracle: bad matrix")
 
     @classmethod
-    def from_problem(cls, prob):
-        return cls(prob.rowptr, prob.col, prob.val, prob.colors)
+    def from_problem(cls, prob, block_rows=None):
+        return cls(prob.rowptr, prob.col, prob.val, None if block_rows is not None else prob.colors,
+                   block_rows=block_rows)
 
     def __del__(self):
         h = getattr(self, "h", None)

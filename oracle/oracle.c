@@ -27,7 +27,11 @@
  *     value (Sec. 5.4); (K1) extreme eigenvalues of the Lanczos tridiagonal
  *     matrix built from the CG coefficients (textbook CG-Lanczos relation,
  *     Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Sec. 6.7.3);
- *   - adjoint gradient of a linear solve with respect to stored values.
+ *   - adjoint gradient of a linear solve with respect to stored values;
+ *   - block-Jacobi IC(0), the paper's parallel preconditioner (Sec. 5.3, with
+ *     Saad's block Jacobi): rows split into blocks of consecutive rows, IC(0)
+ *     of the block-diagonal part of A, i.e. every coupling between two blocks
+ *     is left out of the factor (A itself keeps them).
  *
  * Readings where the paper is silent or garbled are taken as follows:
  *   - beta carries a plus sign (the minus printed in Alg. "Deflated PCG
@@ -80,6 +84,9 @@ typedef struct {
     /* IC(0) factor: lower triangle incl. diagonal, permuted order */
     int64_t *lrp; int32_t *lcol; double *lval;
     int factored;
+    /* block-Jacobi IC(0): > 0 = rows per block (blocks of consecutive rows of
+       the natural order); 0 = IC(0) of the whole matrix */
+    int64_t block_rows;
     /* sampling */
     int m_req;
     int samp_method;   /* 0: method A (Appendix A), 1: method B (relative-residual thresholds) */
@@ -178,6 +185,20 @@ orc *orc_create(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
     return o;
 }
 
+/* Block-Jacobi IC(0) preconditioner (Sec. 5.3): natural order, blocks of
+ * block_rows consecutive rows (the last one may be shorter). */
+orc *orc_create_bj(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t block_rows) {
+    if (block_rows <= 0) return NULL;
+    orc *o = orc_create(n, rowptr, col, val, NULL);
+    if (o) o->block_rows = block_rows;
+    return o;
+}
+
+/* entry (i, j) belongs to the matrix the preconditioner is built from */
+static int in_factor(const orc *o, int64_t i, int64_t j) {
+    return o->block_rows <= 0 || i / o->block_rows == j / o->block_rows;
+}
+
 static void free_aux(orc *o) {
     free(o->E); free(o->AE); free(o->W); free(o->AW); free(o->C); free(o->R);
     o->E = o->AE = o->W = o->AW = o->C = o->R = NULL;
@@ -207,6 +228,7 @@ int64_t orc_permuted_csr(const orc *o, int64_t *rp, int32_t *col, double *val) {
 
 /* ------------------------------------------------------------------ */
 /* IC(0): incomplete Cholesky on the stored lower pattern               */
+/* (block Jacobi: of the block-diagonal part of the matrix)              */
 /* ------------------------------------------------------------------ */
 
 int orc_factor_ic0(orc *o) {
@@ -216,14 +238,14 @@ int orc_factor_ic0(orc *o) {
     int64_t cnt = 0;
     for (int64_t i = 0; i < n; ++i)
         for (int64_t k = o->rp[i]; k < o->rp[i + 1]; ++k)
-            if (o->col[k] <= i) ++cnt;
+            if (o->col[k] <= i && in_factor(o, i, o->col[k])) ++cnt;
     o->lcol = malloc(cnt * sizeof(int32_t));
     o->lval = malloc(cnt * sizeof(double));
     o->lrp[0] = 0;
     int64_t p = 0;
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t k = o->rp[i]; k < o->rp[i + 1]; ++k)
-            if (o->col[k] <= i) { o->lcol[p] = o->col[k]; o->lval[p] = o->val[k]; ++p; }
+            if (o->col[k] <= i && in_factor(o, i, o->col[k])) { o->lcol[p] = o->col[k]; o->lval[p] = o->val[k]; ++p; }
         o->lrp[i + 1] = p;
     }
     o->factored = 0;
@@ -355,7 +377,7 @@ int orc_load_samples(orc *o, const double *X_user, int k, const double *xN_user)
 
 /* method: 0 = sampling method A, 1 = sampling method B (Sec. 4.3), plus 16
  * to store the residual vectors r_i instead of the iterates x_i (the
- * comparison of Sec. 5.3, "Sampling of residual vectors"). */
+ * comparison of Sec. 5.2, "Sampling of residual vectors"). */
 int orc_arm_sampling(orc *o, int m, int method) {
     if (m <= 0 || m > 4096) return OR_EINVAL;
     if ((method & ~16) != 0 && (method & ~16) != 1) return OR_EINVAL;

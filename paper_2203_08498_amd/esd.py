@@ -189,7 +189,7 @@ class Solver:
     def sample_errors(self, m: int, method: int = 0, residuals: bool = False):
         """Arm sampling for the next solve: method 0 = sampling method A
         (Appendix A), 1 = method B (relative-residual thresholds, Sec. 4.3);
-        residuals=True stores r_i instead of x_i (Sec. 5.3)."""
+        residuals=True stores r_i instead of x_i (Sec. 5.2)."""
         code = int(method) | (SAMPLE_RESIDUALS if residuals else 0)
         st = self.L.esd_sample_errors(self.h, int(m), code)
         if st != 0:

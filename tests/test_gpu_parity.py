@@ -293,7 +293,7 @@ def test_sampling_build_aux_and_accelerated_solves(case):
 
 @pytest.mark.parametrize("method,residuals", [(1, False), (0, True), (1, True)])
 def test_sampling_method_b_and_residual_vectors(case, method, residuals):
-    """Sampling method B (Sec. 4.3) and residual-vector sampling (Sec. 5.3):
+    """Sampling method B (Sec. 4.3) and residual-vector sampling (Sec. 5.2):
     the same sampled iterations as the oracle, the stored vectors to the
     solution-parity bar, and Ritz values within the perturbation of the
     sampled vectors."""

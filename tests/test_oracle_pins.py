@@ -106,7 +106,7 @@ def test_sampling_method_b_takes_first_threshold_crossings():
 
 
 def test_residual_sampling_stores_residuals_and_spans_them():
-    """Residual-vector sampling (Sec. 5.3): the stored vectors are r_i = b - A x_i
+    """Residual-vector sampling (Sec. 5.2): the stored vectors are r_i = b - A x_i
     and the auxiliary basis spans them (no x_N - x_i)."""
     p = P.config1(N=32, nbox=2, box=4)
     m = 5
@@ -134,7 +134,7 @@ def test_residual_sampling_stores_residuals_and_spans_them():
 
 
 def test_residual_sampling_misses_the_small_eigenvalues():
-    """Sec. 5.3: since r_s = A e_s damps the small-eigenvalue components, the
+    """Sec. 5.2: since r_s = A e_s damps the small-eigenvalue components, the
     residual samples give no small Ritz value where the error samples do
     (floating high-coefficient blocks: near-null modes)."""
     p = P.config4(Ne=11, nblk=2, blk=3)
@@ -248,6 +248,88 @@ def test_prec_apply_is_inverse_of_LLt():
     pm = o.perm
     zp = np.linalg.solve(L @ L.T, r[pm])
     assert np.abs(z[pm] - zp).max() < 1e-12 * np.abs(zp).max()
+
+
+# ---------------------------------------------------------------- block-Jacobi IC(0) (Sec. 5.3)
+
+def _block_diag(A, s):
+    """Block-diagonal part of A for blocks of s consecutive rows (last one ragged)."""
+    blk = np.arange(A.shape[0]) // s
+    return np.where(blk[:, None] == blk[None, :], A, 0.0)
+
+
+def test_block_jacobi_one_row_blocks_is_jacobi():
+    p = small3d(5)
+    o = O.Oracle.from_problem(p, block_rows=1)
+    assert o.factor_ic0() == 0
+    r = np.random.default_rng(3).standard_normal(p.n)
+    d = dense(p).diagonal()
+    assert np.abs(o.prec(r) - r / d).max() <= 1e-15 * np.abs(r / d).max()
+
+
+@pytest.mark.parametrize("case", ["2d_lines", "3d_lines", "3d_ragged5", "2d_ragged7"])
+def test_block_jacobi_short_blocks_are_exact_block_solves(case):
+    """Blocks of at most N consecutive rows of a natural-order grid hold only
+    x-couplings, so each diagonal block is tridiagonal, IC(0) has no fill to
+    drop and the preconditioner is the exact block-diagonal solve."""
+    if case.startswith("2d"):
+        p = P.config1(N=16, nbox=1, box=4)
+        N = 16
+    else:
+        p = small3d(6)
+        N = 6
+    s = {"2d_lines": N, "3d_lines": N, "3d_ragged5": 5, "2d_ragged7": 7}[case]
+    o = O.Oracle.from_problem(p, block_rows=s)
+    assert o.factor_ic0() == 0
+    r = np.random.default_rng(4).standard_normal(p.n)
+    Abd = _block_diag(dense(p), s)
+    want = np.linalg.solve(Abd, r)
+    assert np.abs(o.prec(r) - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_block_jacobi_defining_property_on_wide_blocks():
+    """Blocks of 2 N^2 + 3 rows (x-, y- and z-couplings inside, ragged last
+    block): the factor has no entry between blocks, (L L^T)_ij = a_ij on every
+    stored in-block position, and it equals the right-looking incomplete
+    Cholesky of the block-diagonal matrix; one block of n rows is IC(0) of A."""
+    p = small3d(5)
+    A = dense(p)
+    pat = P.csr_to_dense(p.rowptr, p.col, np.ones_like(p.val)) != 0
+    s = 2 * 25 + 3
+    o = O.Oracle.from_problem(p, block_rows=s)
+    assert o.factor_ic0() == 0
+    rp, c, v = o.factor_csr()
+    L = P.csr_to_dense(rp, c, v)
+    blk = np.arange(p.n) // s
+    same = blk[:, None] == blk[None, :]
+    assert np.all(L[~same] == 0) and np.all(np.diag(L) > 0)
+    R = L @ L.T
+    assert np.abs((R - A)[pat & same]).max() < 1e-13
+    assert np.abs(L - _ic0_dense_kij(_block_diag(A, s), pat & same)).max() < 1e-13
+    # the coupled entries between blocks are where M differs from A
+    assert np.abs((R - A)[pat & ~same]).min() > 0
+    # one block covering every row: IC(0) of the whole matrix in natural order
+    o1 = O.Oracle.from_problem(p, block_rows=p.n)
+    o1.factor_ic0()
+    L1 = P.csr_to_dense(*o1.factor_csr())
+    assert np.abs(L1 - _ic0_dense_kij(A, pat)).max() < 1e-13
+
+
+def test_block_jacobi_pcg_against_dense_solve():
+    p = small3d(7)
+    o = O.Oracle.from_problem(p, block_rows=7)
+    o.factor_ic0()
+    x, info = o.solve(p.f, tol=1e-10, maxit=2000)
+    A = dense(p)
+    xs = np.linalg.solve(A, p.f)
+    assert info.converged and info.relres <= 1e-10
+    assert abs(info.true_relres - info.relres) <= 1e-12
+    assert np.linalg.norm(x - xs) <= np.linalg.cond(A) * 1e-10 * np.linalg.norm(xs)
+    # the iterated operator is M^{-1} A with the block-diagonal M: K1 from
+    # the CG coefficients matches its dense generalised eigenvalues
+    lam = sla.eigh(A, _block_diag(A, 7), eigvals_only=True)
+    x2, info2 = o.solve(p.f, tol=1e-14, maxit=2000)
+    assert abs(info2.kappa / (lam[-1] / lam[0]) - 1) < 1e-6
 
 
 # ---------------------------------------------------------------- CG / ICCG
