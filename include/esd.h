@@ -112,6 +112,25 @@ typedef struct {
 esd_status esd_setup(esd_ctx **ctx, void *hip_stream, int64_t n, const int64_t *rowptr,
                      const int32_t *col, const double *val, const int32_t *colors, int32_t m_max);
 
+/*
+ * esd_setup_block_jacobi - as esd_setup, with the block-Jacobi IC(0)
+ * preconditioner of the paper's parallel solver (Sec. 5.3) instead of IC(0)
+ * of the whole matrix.  Rows stay in the natural order and are split into
+ * blocks of block_rows consecutive rows (the last block may be shorter);
+ * esd_factor_ic0 then computes IC(0) of the block-diagonal part of A, i.e.
+ * every coupling between two blocks is left out of the preconditioner (A,
+ * the SpMV and everything else keep them).
+ *   block_rows: 1 .. 512.  Every coupling inside a block must join two
+ *     consecutive rows (tridiagonal blocks; on a natural-order grid, blocks of
+ *     at most one grid line), so that each block's factor is its exact
+ *     Cholesky factor and M^{-1} r is two recurrences per block; otherwise
+ *     ESD_EINVAL.
+ * Sampling, auxiliary space, all solver modes, mixed precision and the
+ * gradient work as after esd_setup.
+ */
+esd_status esd_setup_block_jacobi(esd_ctx **ctx, void *hip_stream, int64_t n, const int64_t *rowptr,
+                                  const int32_t *col, const double *val, int32_t block_rows, int32_t m_max);
+
 /* esd_update_values - new values val(d) float64[nnz] for the same pattern, in
  * the caller's CSR order (a slowly varying matrix A_k, Sec. 2; finite-
  * difference checks).  The IC(0) factor must be recomputed with

@@ -47,7 +47,7 @@ struct DevEll {
 
 template <typename T> struct VecSet {
     T *x, *r, *z, *zsc, *y, *q, *p[2], *v[2];
-    const T *W, *AW, *Wrm, *AWrm, *dinv;
+    const T *W, *AW, *Wrm, *AWrm, *dinv, *lsub;
     Ell<T> A, L, U;
 };
 
@@ -69,6 +69,12 @@ struct esd_ctx {
     int32_t *a_src = nullptr, *l_src = nullptr, *d_src = nullptr; // caller-CSR positions
     double *adiag = nullptr, *ldiag = nullptr, *dinv = nullptr;
     float *dinv32 = nullptr;
+    // block-Jacobi IC(0) (bj_rows > 0): blocks of bj_rows consecutive rows,
+    // sub-diagonal of every block's bidiagonal factor
+    int64_t bj_rows = 0;
+    int bj_nb = 0;
+    double *lsub = nullptr;
+    float *lsub32 = nullptr;
     int32_t *p2u = nullptr;
     int32_t *tmap = nullptr, *tmap_lvl = nullptr; // XCD-local tile orders (whole range, per level)
     std::vector<int64_t> tmap_off;                 // start of every level's order in tmap_lvl
@@ -225,7 +231,7 @@ template <> VecSet<double> vecs<double>(esd_ctx *c) {
     VecSet<double> V;
     V.x = c->x; V.r = c->r; V.z = c->z; V.zsc = c->zsc; V.y = c->y; V.q = c->q;
     V.p[0] = c->p[0]; V.p[1] = c->p[1]; V.v[0] = c->v[0]; V.v[1] = c->v[1];
-    V.W = c->W; V.AW = c->AW; V.Wrm = c->W_rm; V.AWrm = c->AW_rm; V.dinv = c->dinv;
+    V.W = c->W; V.AW = c->AW; V.Wrm = c->W_rm; V.AWrm = c->AW_rm; V.dinv = c->dinv; V.lsub = c->lsub;
     V.A = c->A.it64(); V.L = c->L.it64(); V.U = c->U.it64();
     return V;
 }
@@ -233,7 +239,7 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
     VecSet<float> V;
     V.x = c->d32; V.r = c->r32; V.z = c->z32; V.zsc = c->zsc32; V.y = c->y32; V.q = c->q32;
     V.p[0] = c->p32[0]; V.p[1] = c->p32[1]; V.v[0] = c->v32[0]; V.v[1] = c->v32[1];
-    V.W = c->W32; V.AW = c->AW32; V.Wrm = c->W32_rm; V.AWrm = c->AW32_rm; V.dinv = c->dinv32;
+    V.W = c->W32; V.AW = c->AW32; V.Wrm = c->W32_rm; V.AWrm = c->AW32_rm; V.dinv = c->dinv32; V.lsub = c->lsub32;
     V.A = c->A.it32(); V.L = c->L.it32(); V.U = c->U.it32();
     return V;
 }
@@ -260,6 +266,14 @@ int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_
         const int g = esd::grid_red(c->n, 1);
         esd::launch_copyz(s, sc, g, c->stream);
         return g;
+    }
+    if (c->bj_rows > 0) {
+        esd::BjSweep<T> bj{};
+        bj.n = (int)c->n; bj.s = (int)c->bj_rows; bj.nb = c->bj_nb;
+        bj.S = c->S; bj.part = c->part_sweep;
+        bj.lsub = V.lsub; bj.dinv = V.dinv; bj.r = V.r; bj.z = V.z; bj.zsc = sc ? V.zsc : V.z;
+        bj.W = V.W; bj.m = sc ? c->m_tilde : 0;
+        return esd::launch_bj(bj, sc, c->stream);
     }
     // rho partial rows: every forward launch (||y||^2) without subspace
     // correction; the last forward and every backward launch with it
@@ -1039,7 +1053,7 @@ void esd_destroy(esd_ctx *c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     free_ell(c->A); free_ell(c->L); free_ell(c->U);
-    void *ptrs[] = {c->u_from_l, c->l_orig, c->a_src, c->l_src, c->d_src, c->adiag, c->ldiag, c->dinv, c->dinv32, c->p2u, c->urp, c->ucol, c->bad,
+    void *ptrs[] = {c->u_from_l, c->l_orig, c->a_src, c->l_src, c->d_src, c->adiag, c->ldiag, c->dinv, c->dinv32, c->lsub, c->lsub32, c->p2u, c->urp, c->ucol, c->bad,
                     c->b, c->x, c->r, c->z, c->zsc, c->y, c->q, c->p[0], c->p[1], c->t, c->v[0], c->v[1],
                     c->r32, c->z32, c->zsc32, c->y32, c->q32, c->p32[0], c->p32[1], c->d32, c->v32[0], c->v32[1],
                     c->tmap, c->tmap_lvl, c->part_spmv, c->part_upd, c->part_gen, c->part_sweep, c->part_ts, c->W_rm, c->W32_rm, c->AW_rm, c->AW32_rm, c->S, c->slots, c->slot_table, c->xN,
@@ -1053,8 +1067,9 @@ void esd_destroy(esd_ctx *c) {
     delete c;
 }
 
-esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr, const int32_t *col,
-                     const double *val, const int32_t *colors, int32_t m_max) {
+namespace {
+esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr, const int32_t *col,
+                      const double *val, const int32_t *colors, int64_t block_rows, int32_t m_max) {
     if (!out || !rowptr || !col || !val || n <= 0 || m_max < 0 || m_max > esd::kMaxCols) return ESD_EINVAL;
     *out = nullptr;
     esd_ctx *c = new (std::nothrow) esd_ctx();
@@ -1063,7 +1078,7 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     c->m_max = m_max;
     c->trace = std::getenv("ESD_TRACE") != nullptr;
     esd::HostLayout H;
-    std::string why = esd::build_layout(n, rowptr, col, val, colors, H);
+    std::string why = esd::build_layout(n, rowptr, col, val, colors, block_rows, H);
     if (!why.empty()) {
         fprintf(stderr, "esd_setup: %s\n", why.c_str());
         delete c;
@@ -1072,6 +1087,8 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     c->n = n;
     c->nnz = H.nnz;
     c->ncolors = H.ncolors;
+    c->bj_rows = H.block_rows;
+    c->bj_nb = H.block_rows > 0 ? (int)((n + H.block_rows - 1) / H.block_rows) : 0;
     c->lvl = H.lvl_ptr;
     c->p2u_h = H.p2u;
     c->lperm_h = H.lperm;
@@ -1109,6 +1126,10 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     SETUP_HIP(dalloc(&c->ldiag, nv));
     SETUP_HIP(dalloc(&c->dinv, nv));
     SETUP_HIP(dalloc(&c->dinv32, nv));
+    SETUP_HIP(dalloc(&c->lsub, nv));
+    SETUP_HIP(dalloc(&c->lsub32, nv));
+    esd::launch_fill((int)nv, c->lsub, 0.0, c->stream);
+    esd::launch_fill((int)nv, c->lsub32, 0.0f, c->stream);
     SETUP_HIP(dalloc(&c->p2u, nv));
     SETUP_HIP(hipMemcpyAsync(c->p2u, H.p2u.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
     {
@@ -1147,6 +1168,7 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
         int64_t tot = 0;
         for (size_t l = 0; l + 1 < c->lvl.size(); ++l) tot += esd::grid_red(c->lvl[l + 1] - c->lvl[l], 1);
         c->sweep_cap = std::max(cap, tot);
+        if (c->bj_nb > 0) c->sweep_cap = std::max<int64_t>(c->sweep_cap, (c->bj_nb + esd::kBlock / 64 - 1) / (esd::kBlock / 64));
         SETUP_HIP(dalloc(&c->part_sweep, c->sweep_cap));
     }
     SETUP_HIP(dalloc(&c->S, 1));
@@ -1179,6 +1201,19 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
     *out = c;
     return ESD_OK;
 }
+} // namespace
+
+esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr, const int32_t *col,
+                     const double *val, const int32_t *colors, int32_t m_max) {
+    return setup_impl(out, hip_stream, n, rowptr, col, val, colors, 0, m_max);
+}
+
+esd_status esd_setup_block_jacobi(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr,
+                                  const int32_t *col, const double *val, int32_t block_rows, int32_t m_max) {
+    if (block_rows < 1 || block_rows > esd::kMaxBlockRows) return ESD_EINVAL;
+    return setup_impl(out, hip_stream, n, rowptr, col, val, nullptr, block_rows, m_max);
+}
+
 
 esd_status esd_factor_ic0(esd_ctx *c) {
     if (!c) return ESD_EINVAL;
@@ -1189,9 +1224,13 @@ esd_status esd_factor_ic0(esd_ctx *c) {
         HIPCHK(hipMemcpyAsync(c->L.v64, c->l_orig, sizeof(double) * c->L.size, hipMemcpyDeviceToDevice, c->stream));
     const int nl = (int)c->lvl.size() - 1;
     Ell<double> L = c->L.e64();
-    for (int l = 0; l < nl; ++l)
-        esd::launch_factor_level((int)c->lvl[l], (int)c->lvl[l + 1], n, L, c->L.v64, c->adiag, c->ldiag, c->bad,
-                                 c->stream);
+    if (c->bj_rows > 0)
+        esd::launch_factor_bj(n, (int)c->bj_rows, L, c->L.v64, c->adiag, c->ldiag, c->lsub, c->lsub32, c->bad,
+                              c->stream);
+    else
+        for (int l = 0; l < nl; ++l)
+            esd::launch_factor_level((int)c->lvl[l], (int)c->lvl[l + 1], n, L, c->L.v64, c->adiag, c->ldiag,
+                                     c->bad, c->stream);
     esd::launch_finish_factor(n, c->ldiag, c->dinv, c->dinv32, c->stream);
     esd::launch_gather_u(c->U.size, c->u_from_l, c->L.v64, c->U.v64, c->stream);
     esd::launch_cast(c->L.size, c->L.v64, c->L.v32, c->stream);

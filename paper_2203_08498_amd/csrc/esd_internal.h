@@ -8,6 +8,7 @@ namespace esd {
 
 constexpr int kSlice = 64;   // sliced-ELL slice height = wavefront size
 constexpr int kMaxCols = 64; // largest auxiliary-space dimension
+constexpr int kMaxBlockRows = 512; // largest block-Jacobi block (one wavefront, 8 rows per lane)
 
 // Sliced-ELL matrix on the host while it is being built: slice s holds rows
 // [64 s, 64 s + 64); entry k of lane t sits at sptr[s] + 64 k + t.  Padding
@@ -22,6 +23,7 @@ struct HostEll {
 struct HostLayout {
     int64_t n = 0, nnz = 0;
     int ncolors = 0;
+    int64_t block_rows = 0;        // > 0: block-Jacobi IC(0) with blocks of that many consecutive rows
     std::vector<int32_t> lperm;    // logical position -> user row
     std::vector<int32_t> p2u;      // physical row -> user row
     std::vector<int32_t> u2p;      // user row -> physical row
@@ -38,8 +40,11 @@ struct HostLayout {
 };
 
 // Builds the layout; returns an empty string on success, else the reason.
+// block_rows > 0 (block-Jacobi IC(0)): natural order, one level, and L / U
+// hold only couplings inside a block of block_rows consecutive rows, which
+// must join consecutive rows (tridiagonal blocks); A keeps every entry.
 std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
-                         const int32_t *colors, HostLayout &out);
+                         const int32_t *colors, int64_t block_rows, HostLayout &out);
 
 // Order in which row tiles of `tile_rows` rows are handed to blocks, for the
 // whole row range and for every level.  Rows are grouped in segments of equal

@@ -41,7 +41,7 @@ inline int64_t ell_pos(const HostEll &E, int64_t row, int64_t k) {
 } // namespace
 
 std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
-                         const int32_t *colors, HostLayout &H) {
+                         const int32_t *colors, int64_t block_rows, HostLayout &H) {
     if (n <= 0 || n >= (int64_t(1) << 31) - 64) return "n out of range";
     if (rowptr[n] >= (int64_t(1) << 31)) return "nnz out of range";
     if (rowptr[0] != 0) return "rowptr[0] != 0";
@@ -50,6 +50,13 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
     const int64_t nnz = rowptr[n];
     H.n = n;
     H.nnz = nnz;
+    H.block_rows = block_rows;
+    if (block_rows < 0 || block_rows > kMaxBlockRows) return "block size out of range";
+    if (block_rows > 0 && colors) return "block Jacobi keeps the natural order (no colours)";
+    // block Jacobi: the factor keeps only couplings inside a block of
+    // block_rows consecutive rows; every such coupling must join consecutive
+    // rows (tridiagonal blocks)
+    const auto in_blk = [block_rows](int64_t u, int64_t c) { return block_rows == 0 || u / block_rows == c / block_rows; };
     // validate rows: columns in range, strictly increasing, diagonal present
     for (int64_t i = 0; i < n; ++i) {
         bool diag = false;
@@ -60,6 +67,11 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
         }
         if (!diag) return "missing diagonal entry";
     }
+    if (block_rows > 0)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (col[k] != i && in_blk(i, col[k]) && col[k] != i - 1 && col[k] != i + 1)
+                    return "block Jacobi needs tridiagonal blocks (couplings inside a block only between consecutive rows)";
     // logical order: stable counting sort by colour
     H.lperm.resize(n);
     std::vector<int32_t> lpos(n);
@@ -85,7 +97,8 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
     // level of every logical row: longest chain of logically-lower couplings
     std::vector<int32_t> lev(n, 0);
     int32_t nlev = 1;
-    for (int64_t l = 0; l < n; ++l) {
+    // block Jacobi: one level (the block sweeps do not use the level schedule)
+    for (int64_t l = 0; l < (block_rows > 0 ? 0 : n); ++l) {
         int32_t u = H.lperm[l], lv = 0;
         for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
             int32_t lc = lpos[col[k]];
@@ -121,6 +134,7 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
         for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
             ++a;
             int32_t q = lpos[col[k]];
+            if (!in_blk(u, col[k])) continue;
             if (q < l) ++lo; else if (q > l) ++up;
         }
         lenA[p] = a; lenL[p] = lo; lenU[p] = up;
@@ -142,6 +156,7 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
             for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
                 int32_t cu = col[k], q = lpos[cu], pc = ppos[q];
                 ea.push_back({pc, pc, val[k], (int32_t)k});
+                if (!in_blk(u, cu)) continue;
                 if (q < l) el.push_back({q, pc, val[k], (int32_t)k});
                 else if (q > l) eu.push_back({q, pc, val[k], (int32_t)k});
                 else { H.adiag[p] = val[k]; H.d_src[p] = (int32_t)k; }

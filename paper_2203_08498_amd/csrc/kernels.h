@@ -131,6 +131,25 @@ template <typename T> struct Sweep {
     const int32_t *tmap; // tile order within [r0, r1) (nullptr: natural)
 };
 
+// Block-Jacobi IC(0) (Sec. 5.3) with tridiagonal blocks: blocks of s
+// consecutive rows whose only couplings inside the block join consecutive
+// rows, so that the block's IC(0) factor is its exact Cholesky factor, lower
+// bidiagonal: l_k = L(k, k-1) (0 at a block start) and d_k = L(k, k).  One
+// wavefront per block, R consecutive rows per lane (s <= 64 R); z = M^{-1} r
+// in one launch.  rho partials: ||y||^2 (y = L^{-1} r), or (r, z + W u) with
+// subspace correction; one partial per block of kBlock threads.
+template <typename T> struct BjSweep {
+    int n, s, nb; // rows, rows per block, blocks
+    Scal *S;
+    double *part;
+    const T *lsub; // l_k per row (0 at block starts)
+    const T *dinv; // 1 / d_k
+    const T *r;
+    T *z, *zsc;
+    const T *W;
+    int m; // > 0: subspace correction adds W u to zsc
+};
+
 // finalize after the SpMV: alpha = rho / ((p,q) - s^T C^{-1} s), mu = C^{-1} s
 // with s = W^T q from a TsDot partial table
 struct FinAlpha {
@@ -210,6 +229,9 @@ void launch_fwd(const Sweep<double> &a, bool last, bool sc, int grid, hipStream_
 void launch_fwd(const Sweep<float> &a, bool last, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
+// block-Jacobi z = M^{-1} r; returns the number of rho partials written
+int launch_bj(const BjSweep<double> &a, bool sc, hipStream_t s);
+int launch_bj(const BjSweep<float> &a, bool sc, hipStream_t s);
 void launch_copyz(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_copyz(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
 void launch_fin_alpha(const FinAlpha &f, hipStream_t s);
@@ -259,6 +281,10 @@ void launch_scale_copy(int n, const double *src, double *dst, double scale, hipS
 void launch_factor_level(int r0, int r1, int n, Ell<double> L, double *lval, const double *adiag,
                          double *ldiag, int *bad, hipStream_t s);
 void launch_finish_factor(int n, const double *ldiag, double *dinv, float *dinv32, hipStream_t s);
+// block-Jacobi factor of tridiagonal blocks (one lane per block, in place on
+// lval = a_ij of L's sorted layout): ldiag, l_k as lsub / lsub32
+void launch_factor_bj(int n, int s, Ell<double> L, double *lval, const double *adiag, double *ldiag, double *lsub,
+                      float *lsub32, int *bad, hipStream_t st);
 void launch_gather_u(int64_t cnt, const int64_t *map, const double *lval, double *uval,
                      hipStream_t s);
 // dst[i] = val[src[i]] (0 where src < 0), optional FP32 copy

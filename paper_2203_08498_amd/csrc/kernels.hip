@@ -432,6 +432,103 @@ __global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
     if constexpr (SC) block_partials<1>(acc, a.part, 1);
 }
 
+// Block-Jacobi z = M^{-1} r with tridiagonal blocks, one wavefront per block,
+// lane t holding rows t R .. t R + R - 1 of it.  Forward y_k = (r_k - l_k
+// y_{k-1}) / d_k and backward z_k = (y_k - l_{k+1} z_{k+1}) / d_k are
+// first-order linear recurrences: every lane composes the affine maps of its
+// rows, an inclusive 64-lane scan of the compositions (towards higher lanes
+// for the forward sweep, towards lower lanes for the backward one) gives the
+// value entering each lane's rows, and the lane then runs the substitution
+// over its rows from that value, so every row is computed by the sequential
+// sweep's own formula.  y stays in registers between the two sweeps.  Rows
+// past the block's end carry d = l = r = 0 and hence y = z = 0.
+template <typename T, int R, bool SC>
+__global__ __launch_bounds__(kBlock) void k_bj(BjSweep<T> a) {
+    if (a.S->done) return;
+    const int lane = threadIdx.x & 63;
+    const int blk = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    double acc[1] = {0.0};
+    if (blk < a.nb) { // uniform over the wavefront
+        const int r0 = blk * a.s;
+        const int len = min(a.s, a.n - r0);
+        const int k0 = lane * R;
+        T l[R], di[R], rr[R], y[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (k0 + j < len) {
+                const int p = r0 + k0 + j;
+                l[j] = a.lsub[p];
+                di[j] = a.dinv[p];
+                rr[j] = a.r[p];
+            } else {
+                l[j] = T(0);
+                di[j] = T(0);
+                rr[j] = T(0);
+            }
+        }
+        // forward: y leaving the lane's rows = A * (y entering) + C
+        T A = T(1), C = T(0);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const T aj = -l[j] * di[j];
+            C = aj * C + rr[j] * di[j];
+            A = aj * A;
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const T Ap = __shfl_up(A, d, 64), Cp = __shfl_up(C, d, 64);
+            if (lane >= d) {
+                C = A * Cp + C;
+                A = A * Ap;
+            }
+        }
+        T yv = __shfl_up(C, 1, 64);
+        if (lane == 0) yv = T(0); // l = 0 at the block start: nothing enters
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            yv = (rr[j] - l[j] * yv) * di[j];
+            y[j] = yv;
+            if constexpr (!SC) acc[0] += (double)yv * (double)yv;
+        }
+        // backward: l_{k+1} of the lane's last row is the next lane's first l
+        T lnext = __shfl_down(l[0], 1, 64);
+        if (lane == 63) lnext = T(0);
+        T E = T(1), G = T(0);
+#pragma unroll
+        for (int j = R - 1; j >= 0; --j) {
+            const T ej = -((j + 1 < R) ? l[j + 1] : lnext) * di[j];
+            G = ej * G + y[j] * di[j];
+            E = ej * E;
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const T Ep = __shfl_down(E, d, 64), Gp = __shfl_down(G, d, 64);
+            if (lane + d < 64) {
+                G = E * Gp + G;
+                E = E * Ep;
+            }
+        }
+        T zv = __shfl_down(G, 1, 64);
+        if (lane == 63) zv = T(0);
+#pragma unroll
+        for (int j = R - 1; j >= 0; --j) {
+            zv = (y[j] - ((j + 1 < R) ? l[j + 1] : lnext) * zv) * di[j];
+            if (k0 + j < len) {
+                const int p = r0 + k0 + j;
+                a.z[p] = zv;
+                if constexpr (SC) {
+                    double sc = (double)zv;
+                    for (int q = 0; q < a.m; ++q) sc += (double)a.W[(size_t)q * a.n + p] * a.S->u[q];
+                    const T zs = (T)sc;
+                    a.zsc[p] = zs;
+                    acc[0] += (double)rr[j] * (double)zs;
+                }
+            }
+        }
+    }
+    block_partials<1>(acc, a.part, 1);
+}
+
 // M = I: z = r (+ W u for subspace correction)
 template <typename T, bool SC>
 __global__ __launch_bounds__(kBlock) void k_copyz(Sweep<T> a) {
@@ -856,6 +953,40 @@ __global__ void k_finish_factor(int n, const double *ldiag, double *dinv, float 
     }
 }
 
+// Block-Jacobi factor of tridiagonal blocks, one lane per block walking its
+// rows in order: l_k = a_{k,k-1} / d_{k-1}, d_k = sqrt(a_kk - l_k^2) (IC(0) of
+// the block, which has no fill to drop).  lval holds a_ij of L's sorted layout
+// on entry, whose only entry in row k is column k - 1 (or none).
+__global__ void k_factor_bj(int n, int s, Ell<double> L, double *lval, const double *adiag, double *ldiag,
+                            double *lsub, float *lsub32, int *bad) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nb = (n + s - 1) / s;
+    if (b >= nb) return;
+    const int r0 = b * s, r1 = min(n, r0 + s);
+    double dprev = 1.0;
+    for (int p = r0; p < r1; ++p) {
+        double l = 0.0;
+        if (p > r0) {
+            const int64_t base = L.sptr[p >> 6];
+            const int w = (int)((L.sptr[(p >> 6) + 1] - base) >> 6);
+            const int64_t pe = base + (p & 63);
+            if (w > 0 && L.col[pe] == p - 1) {
+                l = lval[pe] / dprev;
+                lval[pe] = l;
+            }
+        }
+        double d = adiag[p] - l * l;
+        if (!(d > 0.0)) {
+            *bad = 1;
+            d = 1.0;
+        }
+        dprev = sqrt(d);
+        ldiag[p] = dprev;
+        lsub[p] = l;
+        lsub32[p] = (float)l;
+    }
+}
+
 __global__ void k_map_values(int64_t cnt, const int32_t *src, const double *val, double *dst, float *dst32) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) {
@@ -1119,6 +1250,26 @@ template <typename T> static void bwd_impl(const Sweep<T> &a, bool sc, int grid,
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
 
+template <typename T> static int bj_impl(const BjSweep<T> &a, bool sc, hipStream_t s) {
+    const int grid = (a.nb + kBlock / 64 - 1) / (kBlock / 64);
+    if (a.s <= 64) {
+        if (sc) k_bj<T, 1, true><<<grid, kBlock, 0, s>>>(a);
+        else k_bj<T, 1, false><<<grid, kBlock, 0, s>>>(a);
+    } else if (a.s <= 128) {
+        if (sc) k_bj<T, 2, true><<<grid, kBlock, 0, s>>>(a);
+        else k_bj<T, 2, false><<<grid, kBlock, 0, s>>>(a);
+    } else if (a.s <= 256) {
+        if (sc) k_bj<T, 4, true><<<grid, kBlock, 0, s>>>(a);
+        else k_bj<T, 4, false><<<grid, kBlock, 0, s>>>(a);
+    } else {
+        if (sc) k_bj<T, 8, true><<<grid, kBlock, 0, s>>>(a);
+        else k_bj<T, 8, false><<<grid, kBlock, 0, s>>>(a);
+    }
+    return grid;
+}
+int launch_bj(const BjSweep<double> &a, bool sc, hipStream_t s) { return bj_impl(a, sc, s); }
+int launch_bj(const BjSweep<float> &a, bool sc, hipStream_t s) { return bj_impl(a, sc, s); }
+
 template <typename T> static void copyz_impl(const Sweep<T> &a, bool sc, int grid, hipStream_t s) {
     if (sc) k_copyz<T, true><<<grid, kBlock, 0, s>>>(a);
     else k_copyz<T, false><<<grid, kBlock, 0, s>>>(a);
@@ -1212,6 +1363,11 @@ void launch_factor_level(int r0, int r1, int n, Ell<double> L, double *lval, con
     // padding slots carry column n
     const int rows = r1 - r0;
     k_factor_level<<<blocks(rows), kBlock, 0, s>>>(r0, r1, n, L, lval, adiag, ldiag, bad);
+}
+void launch_factor_bj(int n, int s, Ell<double> L, double *lval, const double *adiag, double *ldiag, double *lsub,
+                      float *lsub32, int *bad, hipStream_t st) {
+    const int nb = (n + s - 1) / s;
+    k_factor_bj<<<(nb + 63) / 64, 64, 0, st>>>(n, s, L, lval, adiag, ldiag, lsub, lsub32, bad);
 }
 void launch_finish_factor(int n, const double *ldiag, double *dinv, float *dinv32, hipStream_t s) {
     k_finish_factor<<<blocks(n), kBlock, 0, s>>>(n, ldiag, dinv, dinv32);

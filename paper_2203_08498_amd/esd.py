@@ -39,7 +39,7 @@ class EsdInfo(C.Structure):
 
 
 EXPORTS = [
-    "esd_setup", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
+    "esd_setup", "esd_setup_block_jacobi", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
     "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
     "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag", "esd_get_history", "esd_get_samples",
     "esd_get_sample_vector", "esd_set_rayleigh_ritz",
@@ -60,6 +60,7 @@ def load_library(path: str = LIB_PATH):
     L = C.CDLL(path)
     P, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.esd_setup.argtypes = [C.POINTER(P), P, i64, P, P, P, P, i32]
+    L.esd_setup_block_jacobi.argtypes = [C.POINTER(P), P, i64, P, P, P, i32, i32]
     L.esd_factor_ic0.argtypes = [P]
     L.esd_update_values.argtypes = [P, P]
     L.esd_sample_errors.argtypes = [P, i32, i32]
@@ -87,7 +88,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_last_error.argtypes = [P]
     L.esd_last_error.restype = C.c_char_p
     L.esd_destroy.argtypes = [P]
-    for name in ("esd_setup", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
+    for name in ("esd_setup", "esd_setup_block_jacobi", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
                  "esd_set_aux",
                  "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs",
                  "esd_grad_values", "esd_spmv", "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag",
@@ -115,7 +116,10 @@ def _dptr(t):
 class Solver:
     """One SPD matrix on the GPU: ordering, IC(0) factor, auxiliary space W."""
 
-    def __init__(self, rowptr, col, val, colors=None, m_max: int = 16, device="cuda:0"):
+    def __init__(self, rowptr, col, val, colors=None, m_max: int = 16, device="cuda:0", block_rows=None):
+        """colors: ordering by a stable sort on colour (None: natural order).
+        block_rows: block-Jacobi IC(0) (Sec. 5.3) with tridiagonal blocks of
+        that many consecutive rows (natural order; colors must be None)."""
         import torch
 
         if not torch.cuda.is_available():
@@ -130,22 +134,28 @@ class Solver:
         self.n = self.rowptr.shape[0] - 1
         self.nnz = int(self.rowptr[-1])
         self.m_max = m_max
+        self.block_rows = block_rows
+        if block_rows is not None and colors is not None:
+            raise ValueError("block Jacobi keeps the natural order: pass colors=None")
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             h = C.c_void_p()
-            st = self.L.esd_setup(C.byref(h), C.c_void_p(self.stream.cuda_stream), self.n,
-                                  self.rowptr.ctypes.data_as(C.c_void_p), self.col.ctypes.data_as(C.c_void_p),
-                                  self.val.ctypes.data_as(C.c_void_p),
-                                  None if self.colors is None else self.colors.ctypes.data_as(C.c_void_p),
-                                  int(m_max))
+            args = (C.byref(h), C.c_void_p(self.stream.cuda_stream), self.n,
+                    self.rowptr.ctypes.data_as(C.c_void_p), self.col.ctypes.data_as(C.c_void_p),
+                    self.val.ctypes.data_as(C.c_void_p))
+            if block_rows is None:
+                st = self.L.esd_setup(*args, None if self.colors is None else self.colors.ctypes.data_as(C.c_void_p),
+                                      int(m_max))
+            else:
+                st = self.L.esd_setup_block_jacobi(*args, int(block_rows), int(m_max))
         if st != 0:
             raise EsdError(st, self.L.esd_status_string(st).decode())
         self.h = h
 
     @classmethod
-    def from_problem(cls, prob, m_max=None, **kw):
-        return cls(prob.rowptr, prob.col, prob.val, prob.colors,
-                   m_max=prob.params.get("m", 16) if m_max is None else m_max, **kw)
+    def from_problem(cls, prob, m_max=None, block_rows=None, **kw):
+        return cls(prob.rowptr, prob.col, prob.val, None if block_rows is not None else prob.colors,
+                   m_max=prob.params.get("m", 16) if m_max is None else m_max, block_rows=block_rows, **kw)
 
     # -------------------------------------------------------------- plumbing
     def _check(self, st):

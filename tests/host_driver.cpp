@@ -73,6 +73,7 @@ int layout(const char *in, const char *out) {
     if (!f) return 2;
     const int64_t n = read_one<int64_t>(f), nnz = read_one<int64_t>(f);
     const int32_t has_colors = read_one<int32_t>(f);
+    const int64_t block_rows = read_one<int64_t>(f);
     auto rp = read_vec<int64_t>(f, n + 1);
     auto col = read_vec<int32_t>(f, nnz);
     auto val = read_vec<double>(f, nnz);
@@ -80,11 +81,13 @@ int layout(const char *in, const char *out) {
     if (has_colors) colors = read_vec<int32_t>(f, n);
     fclose(f);
     esd::HostLayout H;
-    const std::string why = esd::build_layout(n, rp.data(), col.data(), val.data(), has_colors ? colors.data() : nullptr, H);
+    const std::string why = esd::build_layout(n, rp.data(), col.data(), val.data(), has_colors ? colors.data() : nullptr,
+                                              block_rows, H);
     FILE *o = fopen(out, "wb");
     const int32_t ok = why.empty() ? 1 : 0;
     fwrite(&ok, sizeof(ok), 1, o);
     if (!ok) {
+        fprintf(o, "%s", why.c_str());
         fclose(o);
         return 0;
     }

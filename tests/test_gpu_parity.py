@@ -15,16 +15,32 @@ from paper_2203_08498_amd import problems as P
 pytestmark = pytest.mark.gpu
 
 
+def _bj(p):
+    """Rows per block of a block-Jacobi case (None: IC(0) of the whole matrix)."""
+    return p.params.get("block_rows")
+
+
 def _solver(p, m_max=16):
     from paper_2203_08498_amd import esd
 
-    return esd.Solver.from_problem(p, m_max=m_max)
+    return esd.Solver.from_problem(p, m_max=m_max, block_rows=_bj(p))
+
+
+def _oracle_new(p, val=None):
+    return O.Oracle(p.rowptr, p.col, p.val if val is None else val, p.colors, block_rows=_bj(p))
 
 
 def _oracle(p):
-    o = O.Oracle.from_problem(p)
+    o = _oracle_new(p)
     assert o.factor_ic0() == 0
     return o
+
+
+def _block_jacobi(p, block_rows):
+    """The same matrix with the block-Jacobi IC(0) preconditioner (Sec. 5.3):
+    natural order, blocks of block_rows consecutive rows."""
+    return P.Problem(name=p.name + "_bj", n=p.n, rowptr=p.rowptr, col=p.col, val=p.val, colors=None, f=p.f,
+                     shape=p.shape, params=dict(p.params, block_rows=block_rows))
 
 
 def _relerr(a, b):
@@ -39,6 +55,12 @@ def _cases():
         "q1_colors": P.config4(Ne=11, nblk=2, blk=3),
         # 5832 rows, ragged tail; its matrices take the class-aligned layout
         "fv3d_class": P.config2(N=18, nsph=2, radius=3.0),
+        # block-Jacobi IC(0): one grid line per block (324 blocks of 18 rows)
+        "fv3d_bj": _block_jacobi(P.config2(N=18, nsph=2, radius=3.0), 18),
+        # 27-point, blocks of 7 rows straddling grid lines, ragged last block
+        "q1_bj": _block_jacobi(P.config4(Ne=11, nblk=2, blk=3), 7),
+        # 130 rows per block: four rows per lane
+        "fv2d_bj": _block_jacobi(P.config1(N=130, nbox=2, box=6), 130),
     }
 
 
@@ -66,7 +88,7 @@ def test_layout_choice(case):
     fits it (even-sized 3-D grids, the Q1 case) and the sorted layout
     otherwise; both paths are covered by the cases."""
     name, p, s, o = case
-    expect = name in ("q1_colors", "fv3d_class")
+    expect = name in ("q1_colors", "fv3d_class") or name.endswith("_bj")
     assert s.layout()["class_layout"] == (expect, expect, expect)
 
 
@@ -238,7 +260,7 @@ def test_w_reuse_after_value_update(case):
     try:
         s.update_values(val2)
         s.factor_ic0()
-        o2 = O.Oracle(p.rowptr, p.col, val2, p.colors)
+        o2 = _oracle_new(p, val2)
         assert o2.factor_ic0() == 0
         o2.set_aux(Wo)
         b = P.sequence_rhs(p.f, np.zeros(p.n))
@@ -272,7 +294,7 @@ def test_sampling_build_aux_and_accelerated_solves(case):
     # The two sampling solves agree to dx = ||x_gpu - x_oracle||; the error
     # vector of the last sample, e = x_N - x_k, is the smallest, so the basis is
     # perturbed by about dx / ||e||, and Ritz values by that times ||A|| <= 2.
-    ok_ = O.Oracle.from_problem(p); ok_.factor_ic0()
+    ok_ = _oracle(p)
     xk, _ = ok_.solve(p.f, tol=0.0, maxit=int(samples.max()))
     delta = np.linalg.norm(x1.cpu().numpy() - y1) / np.linalg.norm(y1 - xk)
     print(name, "sampled-basis perturbation", delta, "max ritz diff", np.abs(ritz - oritz).max(), flush=True)
@@ -394,6 +416,41 @@ def test_gradient_values(case):
     x = rng.standard_normal(p.n)
     g = s.grad_values(lam, x).cpu().numpy()
     assert np.array_equal(g, o.grad_values(lam, x))
+
+
+# ---------------------------------------------------------------- block Jacobi
+
+@pytest.mark.parametrize("s_rows", [70, 100, 130, 290, 300])
+def test_block_jacobi_preconditioner_lane_widths(s_rows):
+    """Block-Jacobi M^{-1} r and its factor against the oracle for blocks of
+    1, 2, 4 and 8 rows per lane (ragged last block for 70, 130 and 290 rows)
+    on a 300 x 300 grid, and a solve at tolerance."""
+    p = _block_jacobi(P.config1(N=300, nbox=4, box=10), s_rows)
+    print("block jacobi lane widths: n", p.n, "block rows", s_rows, flush=True)
+    s = _solver(p, m_max=1)
+    s.factor_ic0()
+    o = _oracle(p)
+    rp, c, v = o.factor_csr()
+    assert np.abs(s.factor_diag() - v[rp[1:] - 1]).max() <= 1e-14
+    r = np.random.default_rng(7).standard_normal(p.n)
+    assert _relerr(s.prec(r), o.prec(r)) <= 1e-13
+    x, info = s.solve(p.f, tol=1e-8, maxit=20000)
+    y, oi = o.solve(p.f, tol=1e-8, maxit=20000)
+    print("  its gpu/oracle", info["iters"], oi.iters, flush=True)
+    assert info["converged"] and abs(info["iters"] - oi.iters) <= 2 and _relerr(x, y) <= 1e-10
+    s.close()
+
+
+def test_block_jacobi_setup_errors():
+    from paper_2203_08498_amd import esd
+
+    p = CASES["fv3d_colors"]
+    with pytest.raises(esd.EsdError):  # a block of 14 rows reaches a y-neighbour: not tridiagonal
+        esd.Solver(p.rowptr, p.col, p.val, None, m_max=1, block_rows=14)
+    with pytest.raises(esd.EsdError):
+        esd.Solver(p.rowptr, p.col, p.val, None, m_max=1, block_rows=513)
+    with pytest.raises(ValueError):
+        esd.Solver(p.rowptr, p.col, p.val, p.colors, m_max=1, block_rows=13)
 
 
 # ---------------------------------------------------------------- edge cases

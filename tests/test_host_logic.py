@@ -47,12 +47,13 @@ class _Reader:
         return v
 
 
-def _run_layout(driver, tmp, p):
+def _run_layout(driver, tmp, p, block_rows=0):
     fin, fout = os.path.join(tmp, "csr.bin"), os.path.join(tmp, "layout.bin")
     with open(fin, "wb") as f:
         f.write(np.int64(p.n).tobytes())
         f.write(np.int64(p.nnz).tobytes())
         f.write(np.int32(0 if p.colors is None else 1).tobytes())
+        f.write(np.int64(block_rows).tobytes())
         f.write(np.asarray(p.rowptr, np.int64).tobytes())
         f.write(np.asarray(p.col, np.int32).tobytes())
         f.write(np.asarray(p.val, np.float64).tobytes())
@@ -62,6 +63,7 @@ def _run_layout(driver, tmp, p):
     R = _Reader(fout)
     out = {"ok": int(R.one(np.int32))}
     if not out["ok"]:
+        out["why"] = R.b[R.o:].decode()
         return out
     for k, dt in (("lperm", np.int32), ("p2u", np.int32), ("p2l", np.int32), ("lvl", np.int64)):
         out[k] = R.vec(dt)
@@ -173,6 +175,41 @@ def test_layout_rejects_coupled_rows_of_one_colour(driver, tmp_path):
     bad = P.Problem(name="bad", n=p.n, rowptr=p.rowptr, col=p.col, val=p.val, colors=np.zeros(p.n, np.int32),
                     f=p.f, shape=p.shape, params={})
     assert _run_layout(driver, str(tmp_path), bad)["ok"] == 0
+
+
+@pytest.mark.parametrize("name,s", [("fv3d_12", 12), ("fv3d_12", 5), ("fv2d_natural", 24), ("q1_7", 6)])
+def test_block_jacobi_layout(driver, tmp_path, name, s):
+    """Block Jacobi: natural order in one level; A keeps every entry, L / U
+    hold exactly the couplings inside blocks of s consecutive rows."""
+    base = CASES[name]
+    p = P.Problem(name=name, n=base.n, rowptr=base.rowptr, col=base.col, val=base.val, colors=None, f=base.f,
+                  shape=base.shape, params={})
+    out = _run_layout(driver, str(tmp_path), p, block_rows=s)
+    assert out["ok"] == 1, out.get("why")
+    n = p.n
+    assert np.array_equal(out["p2u"], np.arange(n)) and list(out["lvl"]) == [0, n]
+    coo = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(n, n)).tocoo()
+    ref = {(int(i), int(j)): v for i, j, v in zip(coo.row, coo.col, coo.data)}
+
+    def as_set(t):
+        r, c, v = t
+        return {(int(a), int(b)): x for a, b, x in zip(r, c, v)}
+
+    assert as_set(out["A"]) == ref
+    low = {k: v for k, v in ref.items() if k[1] < k[0] and k[0] // s == k[1] // s}
+    assert as_set(out["L"]) == low and all(i - j == 1 for (i, j) in low)
+    assert set(as_set(out["U"])) == {(j, i) for (i, j) in low}
+
+
+def test_block_jacobi_layout_rejects_non_tridiagonal_blocks_and_colours(driver, tmp_path):
+    p = CASES["fv3d_12"]
+    q = P.Problem(name="x", n=p.n, rowptr=p.rowptr, col=p.col, val=p.val, colors=None, f=p.f, shape=p.shape, params={})
+    out = _run_layout(driver, str(tmp_path), q, block_rows=13)  # a block reaches the y-neighbour
+    assert out["ok"] == 0 and "tridiagonal" in out["why"]
+    out = _run_layout(driver, str(tmp_path), p, block_rows=12)  # colours given
+    assert out["ok"] == 0
+    out = _run_layout(driver, str(tmp_path), q, block_rows=513)
+    assert out["ok"] == 0
 
 
 def test_sampling_table_matches_worked_examples_and_oracle(driver, tmp_path):
