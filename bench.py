@@ -13,8 +13,11 @@ sampling method A and the power iteration, then build_aux (error vectors,
 Gram-Schmidt, Rayleigh-Ritz, W, C = W^T A W), then systems 2..10 deflated.
 `value` = mean seconds per system of that step (sampling and build included).
 Timed beside it on the same sequence (extra fields, not `value`): plain ICCG
-throughout, the subspace-correction preconditioner, and the FP32/FP64 mixed
-solver, deflated and plain.
+throughout, the subspace-correction preconditioner, the FP32/FP64 mixed
+solver, deflated and plain, and the block-Jacobi IC(0) preconditioner of the
+paper's parallel solver (natural order, one grid line of N rows per block),
+plain and deflated, with the duration of its one launch per iteration that
+updates x and r and applies the preconditioner to the new r.
 
 Roofline: the dominant kernel is the per-iteration SpMV launch; its duration
 is measured with hipEvents on the solver's stream around every executed
@@ -47,6 +50,7 @@ def parse():
     ap.add_argument("--theta", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-bj", action="store_true", help="skip the block-Jacobi sequences")
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
@@ -171,26 +175,39 @@ def main():
     print("# workload %s n=%d nnz=%d" % (p.name, p.n, p.nnz), file=sys.stderr, flush=True)
     s = esd.Solver.from_problem(p, m_max=args.m)
     s.set_power_start(P.power_start(2, p.n))
+    # block-Jacobi IC(0), one grid line (N consecutive rows) per block
+    sbj = None
+    if not args.no_bj:
+        sbj = esd.Solver.from_problem(p, m_max=args.m, block_rows=args.N)
+        sbj.set_power_start(P.power_start(2, p.n))
     seqs = (("deflated", esd.DEFLATED, 0), ("plain", esd.PLAIN, 0), ("subspace", esd.SUBSPACE, 0),
             ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED), ("mixed_plain", esd.PLAIN, esd.FLAG_MIXED))
+    if sbj is not None:
+        seqs = seqs + (("bj_deflated", esd.DEFLATED, 0), ("bj_plain", esd.PLAIN, 0))
+    solver_of = lambda name: sbj if name.startswith("bj_") else s
     for _ in range(args.warmup):
         for name, mode, pf in seqs:
-            run_sequence(s, p, args, mode, esd, P, False, pf)
+            run_sequence(solver_of(name), p, args, mode, esd, P, False, pf)
         print("# warmup step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     walls = {name: [] for name, _, _ in seqs}
     recs = {}
     spmv_ms = sweep_ms = 0.0
     spmv_n = 0
+    bj_ms = 0.0
+    bj_n = 0
     for k in range(args.steps):
         for name, mode, pf in seqs:
-            r, wall, tm = run_sequence(s, p, args, mode, esd, P, name == "deflated", pf)
+            r, wall, tm = run_sequence(solver_of(name), p, args, mode, esd, P, name in ("deflated", "bj_deflated"), pf)
             walls[name].append(wall)
             recs[name] = r
-            if tm:
+            if tm and name == "deflated":
                 spmv_ms += tm["spmv_ms"] * tm["iters"]
                 sweep_ms += tm["sweep_ms"] * tm["iters"]
                 spmv_n += tm["iters"]
+            elif tm:
+                bj_ms += tm["sweep_ms"] * tm["iters"]
+                bj_n += tm["iters"]
         print("# step %d: " % k + ", ".join("%s %.4f s" % (nm, walls[nm][-1]) for nm, _, _ in seqs),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -223,6 +240,31 @@ def main():
     # diagonals (12 B per entry), r read, y written and read, z written
     bytes_sweeps = 12.0 * (nnz + n) + 32.0 * n
     sweeps_gbs = bytes_sweeps / avg_sweep_s / 1e9 if avg_sweep_s > 0 else 0.0
+    bj = None
+    if sbj is not None:
+        # x += alpha p, r -= alpha q and z = M^{-1} r (block Jacobi) in one
+        # launch: x, p, q, r, the sub-diagonal and the inverse diagonal of the
+        # bidiagonal block factors read, x, r and z written
+        avg_bj_s = (bj_ms / max(bj_n, 1)) * 1e-3
+        bytes_bj = 72.0 * n
+        bj_gbs = bytes_bj / avg_bj_s / 1e9 if avg_bj_s > 0 else 0.0
+        rbd, rbp = recs["bj_deflated"], recs["bj_plain"]
+        bj = {
+            "block_rows": args.N,
+            "deflated_s_per_system": per["bj_deflated"],
+            "plain_s_per_system": per["bj_plain"],
+            "iters_sampling_solve": rbd[0]["iters"],
+            "iters_deflated_mean": float(np.mean([r["iters"] for r in rbd[1:]])) if args.systems > 1 else None,
+            "iters_plain_mean": float(np.mean([r["iters"] for r in rbp])),
+            "m_tilde": rbd[0].get("m_tilde_built", 0),
+            "ritz_smallest": rbd[0]["ritz"][:8],
+            "true_relres_max": max(r["true_relres"] for r in rbd + rbp),
+            "kappa_cg_plain": round(rbp[-1]["kappa"], 3),
+            "prec": {"kernel": "k_update_bj (vector update + forward and backward block sweeps, one launch)",
+                     "unit": "GB/s",
+                     "achieved": bj_gbs, "peak": HBM_PEAK_GBS, "frac": bj_gbs / HBM_PEAK_GBS,
+                     "bytes_per_launch": bytes_bj, "avg_launch_us": avg_bj_s * 1e6, "launches": bj_n},
+        }
     out = {
         "metric": "time-to-solution/system at relres 1e-8, deflated vs plain ICCG; SpMV GB/s",
         "value": per_sys,
@@ -265,6 +307,7 @@ def main():
         "mixed_true_relres_max": max(r["true_relres"] for r in recs["mixed_deflated"]),
         "kappa_cg_per_system": [round(r["kappa"], 3) for r in rd],
         "kappa_es_per_system": [round(r["kappa_es"], 3) for r in rd],
+        "block_jacobi": bj,
         "sweeps": {"unit": "GB/s", "achieved": sweeps_gbs, "peak": HBM_PEAK_GBS, "frac": sweeps_gbs / HBM_PEAK_GBS,
                    "bytes_per_pair": bytes_sweeps, "avg_pair_us": avg_sweep_s * 1e6},
         "roofline": {
@@ -287,6 +330,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(p, args, mt, float(np.mean(its_defl)) if its_defl else its_plain[0])
     print(json.dumps(out), flush=True)
     s.close()
+    if sbj is not None:
+        sbj.close()
 
 
 if __name__ == "__main__":

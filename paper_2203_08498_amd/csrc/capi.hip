@@ -425,6 +425,12 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     const int gu = esd::grid_red(n, 1);
     const int nl = (int)c->lvl.size() - 1;
     const bool fuse_l0 = !o.noprec && nl >= 2;
+    // block Jacobi without subspace correction: the update kernel also applies
+    // the preconditioner to the new residual
+    const bool bj_fused = c->bj_rows > 0 && !o.noprec && !sc;
+    esd::UpdBj<T> ub{};
+    ub.n = n; ub.s = (int)c->bj_rows; ub.nb = c->bj_nb; ub.S = c->S; ub.part = c->part_upd;
+    ub.q = V.q; ub.x = V.x; ub.r = V.r; ub.lsub = V.lsub; ub.dinv = V.dinv; ub.z = V.z;
     esd::SpmvIt<T> sa{};
     sa.n = n; sa.S = c->S; sa.part = c->part_spmv; sa.A = V.A; sa.tmap = c->tmap;
     sa.z = defl ? nullptr : (sc ? V.zsc : V.z); // deflation: p_new given by the projection
@@ -444,6 +450,11 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     esd::FinRho fr{};
     fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = 2;
     fr.rho_upd = (fuse_l0 && !sc) ? 1 : 0;
+    if (bj_fused) {
+        fr.nblk_upd = esd::bj_grid(c->bj_nb);
+        fr.rho_upd = 1;
+        fr.nsweep = 0;
+    }
     fr.part_sweep = c->part_sweep; fr.hist_beta = c->hb; fr.init = 0;
     fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
     if (o.sampling && o.method_b) {
@@ -466,14 +477,22 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             esd::launch_spmv_it(sa, o.power, gs, c->stream);
             if (timing && (e = hipEventRecord(c->ev[4 * j + 1], c->stream)) != hipSuccess) return e;
             esd::launch_fin_alpha(fa, c->stream);
-            esd::launch_update_it(ua, 0, gu, c->stream);
-            if (sc) {
-                esd::launch_tsdot_rm(ta, gt, c->stream);
-                esd::launch_fin_u(c->S, c->part_ts, gt, st_t, m, c->Cinv, c->stream);
+            if (bj_fused) {
+                // the "sweep" time of this variant is the fused update + preconditioner launch
+                ub.p = ua.p;
+                if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 2], c->stream)) != hipSuccess) return e;
+                esd::launch_update_bj(ub, c->stream);
+                if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 3], c->stream)) != hipSuccess) return e;
+            } else {
+                esd::launch_update_it(ua, 0, gu, c->stream);
+                if (sc) {
+                    esd::launch_tsdot_rm(ta, gt, c->stream);
+                    esd::launch_fin_u(c->S, c->part_ts, gt, st_t, m, c->Cinv, c->stream);
+                }
+                if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 2], c->stream)) != hipSuccess) return e;
+                fr.nsweep = launch_prec<T>(c, V, o.noprec, sc, fuse_l0);
+                if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 3], c->stream)) != hipSuccess) return e;
             }
-            if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 2], c->stream)) != hipSuccess) return e;
-            fr.nsweep = launch_prec<T>(c, V, o.noprec, sc, fuse_l0);
-            if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 3], c->stream)) != hipSuccess) return e;
             if (defl) esd::launch_tsdot_rm(ta, gt, c->stream);
             esd::launch_fin_rho(fr, c->stream);
             if (defl) {
@@ -1168,7 +1187,7 @@ esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, const int64_t 
         int64_t tot = 0;
         for (size_t l = 0; l + 1 < c->lvl.size(); ++l) tot += esd::grid_red(c->lvl[l + 1] - c->lvl[l], 1);
         c->sweep_cap = std::max(cap, tot);
-        if (c->bj_nb > 0) c->sweep_cap = std::max<int64_t>(c->sweep_cap, (c->bj_nb + esd::kBlock / 64 - 1) / (esd::kBlock / 64));
+        if (c->bj_nb > 0) c->sweep_cap = std::max<int64_t>(c->sweep_cap, esd::bj_grid(c->bj_nb));
         SETUP_HIP(dalloc(&c->part_sweep, c->sweep_cap));
     }
     SETUP_HIP(dalloc(&c->S, 1));

@@ -150,6 +150,19 @@ template <typename T> struct BjSweep {
     int m; // > 0: subspace correction adds W u to zsc
 };
 
+// x += alpha p, r -= alpha q and the block-Jacobi z = M^{-1} r of the new r in
+// one launch (no subspace correction); partials ||r||^2 and ||y||^2 per block
+// of kBlock threads (stride 2)
+template <typename T> struct UpdBj {
+    int n, s, nb;
+    Scal *S;
+    double *part;
+    const T *p, *q;
+    T *x, *r;
+    const T *lsub, *dinv;
+    T *z;
+};
+
 // finalize after the SpMV: alpha = rho / ((p,q) - s^T C^{-1} s), mu = C^{-1} s
 // with s = W^T q from a TsDot partial table
 struct FinAlpha {
@@ -229,9 +242,13 @@ void launch_fwd(const Sweep<double> &a, bool last, bool sc, int grid, hipStream_
 void launch_fwd(const Sweep<float> &a, bool last, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
-// block-Jacobi z = M^{-1} r; returns the number of rho partials written
+// block-Jacobi z = M^{-1} r; returns the number of rho partials written (the
+// grid: at most kMaxGrid blocks, wavefronts loop over the Jacobi blocks)
+int bj_grid(int nb);
 int launch_bj(const BjSweep<double> &a, bool sc, hipStream_t s);
 int launch_bj(const BjSweep<float> &a, bool sc, hipStream_t s);
+int launch_update_bj(const UpdBj<double> &a, hipStream_t s);
+int launch_update_bj(const UpdBj<float> &a, hipStream_t s);
 void launch_copyz(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_copyz(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
 void launch_fin_alpha(const FinAlpha &f, hipStream_t s);

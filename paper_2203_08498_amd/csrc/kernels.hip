@@ -14,6 +14,7 @@
 // them visible to every XCD, and a one-block finalize kernel sums the rows in
 // a fixed order and runs the scalar step (alpha, beta, the coarse solve, the
 // stop test) on the device.
+#include <algorithm>
 #include <cfloat>
 
 #include "kernels.h"
@@ -442,82 +443,123 @@ __global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
 // over its rows from that value, so every row is computed by the sequential
 // sweep's own formula.  y stays in registers between the two sweeps.  Rows
 // past the block's end carry d = l = r = 0 and hence y = z = 0.
+template <typename T, int R> struct alignas(sizeof(T) * R) BjPack {
+    T v[R];
+};
+
+// the lane's R rows of a vector (zero past the block end).  Blocks of a
+// multiple of R rows start every lane's rows on an R-row boundary: one aligned
+// R-wide load (the vectors hold 64 entries past n, so the last block's
+// partial group stays in bounds and its rows past the end are zeroed).
+template <typename T, int R>
+__device__ __forceinline__ void bj_load(const T *src, int r0, int k0, int len, bool vec, T (&v)[R]) {
+    if (vec && k0 < len) {
+        const BjPack<T, R> q = *reinterpret_cast<const BjPack<T, R> *>(src + r0 + k0);
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = (k0 + j < len) ? q.v[j] : T(0);
+    } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = (k0 + j < len) ? src[r0 + k0 + j] : T(0);
+    }
+}
+// entry n of a vector must stay zero (gathers of padding slots read it): only
+// whole groups are written as one R-wide store
+template <typename T, int R>
+__device__ __forceinline__ void bj_store(T *dst, int r0, int k0, int len, bool vec, const T (&v)[R]) {
+    if (vec && k0 + R <= len) {
+        BjPack<T, R> q;
+#pragma unroll
+        for (int j = 0; j < R; ++j) q.v[j] = v[j];
+        *reinterpret_cast<BjPack<T, R> *>(dst + r0 + k0) = q;
+    } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (k0 + j < len) dst[r0 + k0 + j] = v[j];
+    }
+}
+
+// one block's z = M^{-1} r on registers; adds ||y||^2 of the lane's rows to ysq
+template <typename T, int R>
+__device__ __forceinline__ void bj_block(int lane, const T (&l)[R], const T (&di)[R], const T (&rr)[R], T (&zr)[R],
+                                         double &ysq) {
+    // forward: y leaving the lane's rows = A * (y entering) + C
+    T A = T(1), C = T(0);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const T aj = -l[j] * di[j];
+        C = aj * C + rr[j] * di[j];
+        A = aj * A;
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const T Ap = __shfl_up(A, d, 64), Cp = __shfl_up(C, d, 64);
+        if (lane >= d) {
+            C = A * Cp + C;
+            A = A * Ap;
+        }
+    }
+    T yv = __shfl_up(C, 1, 64);
+    if (lane == 0) yv = T(0); // l = 0 at the block start: nothing enters
+    T y[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        yv = (rr[j] - l[j] * yv) * di[j];
+        y[j] = yv;
+        ysq += (double)yv * (double)yv;
+    }
+    // backward: l_{k+1} of the lane's last row is the next lane's first l
+    T lnext = __shfl_down(l[0], 1, 64);
+    if (lane == 63) lnext = T(0);
+    T E = T(1), G = T(0);
+#pragma unroll
+    for (int j = R - 1; j >= 0; --j) {
+        const T ej = -((j + 1 < R) ? l[j + 1] : lnext) * di[j];
+        G = ej * G + y[j] * di[j];
+        E = ej * E;
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const T Ep = __shfl_down(E, d, 64), Gp = __shfl_down(G, d, 64);
+        if (lane + d < 64) {
+            G = E * Gp + G;
+            E = E * Ep;
+        }
+    }
+    T zv = __shfl_down(G, 1, 64);
+    if (lane == 63) zv = T(0);
+#pragma unroll
+    for (int j = R - 1; j >= 0; --j) {
+        zv = (y[j] - ((j + 1 < R) ? l[j + 1] : lnext) * zv) * di[j];
+        zr[j] = zv;
+    }
+}
+
+// wavefront w of the grid takes blocks w, w + (waves in the grid), ...
 template <typename T, int R, bool SC>
 __global__ __launch_bounds__(kBlock) void k_bj(BjSweep<T> a) {
     if (a.S->done) return;
     const int lane = threadIdx.x & 63;
-    const int blk = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int stride = gridDim.x * (kBlock / 64);
+    const bool vec = R > 1 && a.s % R == 0;
     double acc[1] = {0.0};
-    if (blk < a.nb) { // uniform over the wavefront
+    for (int blk = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6); blk < a.nb; blk += stride) {
         const int r0 = blk * a.s;
         const int len = min(a.s, a.n - r0);
         const int k0 = lane * R;
-        T l[R], di[R], rr[R], y[R];
+        T l[R], di[R], rr[R], zr[R];
+        bj_load<T, R>(a.lsub, r0, k0, len, vec, l);
+        bj_load<T, R>(a.dinv, r0, k0, len, vec, di);
+        bj_load<T, R>(a.r, r0, k0, len, vec, rr);
+        double ysq = 0.0;
+        bj_block<T, R>(lane, l, di, rr, zr, ysq);
+        if constexpr (!SC) acc[0] += ysq;
+        bj_store<T, R>(a.z, r0, k0, len, vec, zr);
+        if constexpr (SC) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            if (k0 + j < len) {
-                const int p = r0 + k0 + j;
-                l[j] = a.lsub[p];
-                di[j] = a.dinv[p];
-                rr[j] = a.r[p];
-            } else {
-                l[j] = T(0);
-                di[j] = T(0);
-                rr[j] = T(0);
-            }
-        }
-        // forward: y leaving the lane's rows = A * (y entering) + C
-        T A = T(1), C = T(0);
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const T aj = -l[j] * di[j];
-            C = aj * C + rr[j] * di[j];
-            A = aj * A;
-        }
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const T Ap = __shfl_up(A, d, 64), Cp = __shfl_up(C, d, 64);
-            if (lane >= d) {
-                C = A * Cp + C;
-                A = A * Ap;
-            }
-        }
-        T yv = __shfl_up(C, 1, 64);
-        if (lane == 0) yv = T(0); // l = 0 at the block start: nothing enters
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            yv = (rr[j] - l[j] * yv) * di[j];
-            y[j] = yv;
-            if constexpr (!SC) acc[0] += (double)yv * (double)yv;
-        }
-        // backward: l_{k+1} of the lane's last row is the next lane's first l
-        T lnext = __shfl_down(l[0], 1, 64);
-        if (lane == 63) lnext = T(0);
-        T E = T(1), G = T(0);
-#pragma unroll
-        for (int j = R - 1; j >= 0; --j) {
-            const T ej = -((j + 1 < R) ? l[j + 1] : lnext) * di[j];
-            G = ej * G + y[j] * di[j];
-            E = ej * E;
-        }
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const T Ep = __shfl_down(E, d, 64), Gp = __shfl_down(G, d, 64);
-            if (lane + d < 64) {
-                G = E * Gp + G;
-                E = E * Ep;
-            }
-        }
-        T zv = __shfl_down(G, 1, 64);
-        if (lane == 63) zv = T(0);
-#pragma unroll
-        for (int j = R - 1; j >= 0; --j) {
-            zv = (y[j] - ((j + 1 < R) ? l[j + 1] : lnext) * zv) * di[j];
-            if (k0 + j < len) {
-                const int p = r0 + k0 + j;
-                a.z[p] = zv;
-                if constexpr (SC) {
-                    double sc = (double)zv;
+            for (int j = 0; j < R; ++j) {
+                if (k0 + j < len) {
+                    const int p = r0 + k0 + j;
+                    double sc = (double)zr[j];
                     for (int q = 0; q < a.m; ++q) sc += (double)a.W[(size_t)q * a.n + p] * a.S->u[q];
                     const T zs = (T)sc;
                     a.zsc[p] = zs;
@@ -527,6 +569,43 @@ __global__ __launch_bounds__(kBlock) void k_bj(BjSweep<T> a) {
         }
     }
     block_partials<1>(acc, a.part, 1);
+}
+
+// x += alpha p, r -= alpha q, then z = M^{-1} r (block Jacobi) on the updated r
+// held in registers: one pass over the block's rows instead of the update
+// kernel followed by k_bj.  Partials: column 0 ||r||^2, column 1 ||y||^2.
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_update_bj(UpdBj<T> a) {
+    Scal *S = a.S;
+    if (S->done) return;
+    const T ta = (T)S->alpha;
+    const int lane = threadIdx.x & 63;
+    const int stride = gridDim.x * (kBlock / 64);
+    const bool vec = R > 1 && a.s % R == 0;
+    double acc[2] = {0.0, 0.0};
+    for (int blk = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6); blk < a.nb; blk += stride) {
+        const int r0 = blk * a.s;
+        const int len = min(a.s, a.n - r0);
+        const int k0 = lane * R;
+        T pv[R], qv[R], xv[R], rv[R], l[R], di[R], zr[R];
+        bj_load<T, R>(a.p, r0, k0, len, vec, pv);
+        bj_load<T, R>(a.q, r0, k0, len, vec, qv);
+        bj_load<T, R>(a.x, r0, k0, len, vec, xv);
+        bj_load<T, R>(a.r, r0, k0, len, vec, rv);
+        bj_load<T, R>(a.lsub, r0, k0, len, vec, l);
+        bj_load<T, R>(a.dinv, r0, k0, len, vec, di);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            xv[j] += ta * pv[j];
+            rv[j] = rv[j] - ta * qv[j];
+            acc[0] += (double)rv[j] * (double)rv[j];
+        }
+        bj_store<T, R>(a.x, r0, k0, len, vec, xv);
+        bj_store<T, R>(a.r, r0, k0, len, vec, rv);
+        bj_block<T, R>(lane, l, di, rv, zr, acc[1]);
+        bj_store<T, R>(a.z, r0, k0, len, vec, zr);
+    }
+    block_partials<2>(acc, a.part, 2);
 }
 
 // M = I: z = r (+ W u for subspace correction)
@@ -1250,8 +1329,10 @@ template <typename T> static void bwd_impl(const Sweep<T> &a, bool sc, int grid,
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
 
+int bj_grid(int nb) { return std::min(kMaxGrid, (nb + kBlock / 64 - 1) / (kBlock / 64)); }
+
 template <typename T> static int bj_impl(const BjSweep<T> &a, bool sc, hipStream_t s) {
-    const int grid = (a.nb + kBlock / 64 - 1) / (kBlock / 64);
+    const int grid = bj_grid(a.nb);
     if (a.s <= 64) {
         if (sc) k_bj<T, 1, true><<<grid, kBlock, 0, s>>>(a);
         else k_bj<T, 1, false><<<grid, kBlock, 0, s>>>(a);
@@ -1269,6 +1350,17 @@ template <typename T> static int bj_impl(const BjSweep<T> &a, bool sc, hipStream
 }
 int launch_bj(const BjSweep<double> &a, bool sc, hipStream_t s) { return bj_impl(a, sc, s); }
 int launch_bj(const BjSweep<float> &a, bool sc, hipStream_t s) { return bj_impl(a, sc, s); }
+
+template <typename T> static int update_bj_impl(const UpdBj<T> &a, hipStream_t s) {
+    const int grid = bj_grid(a.nb);
+    if (a.s <= 64) k_update_bj<T, 1><<<grid, kBlock, 0, s>>>(a);
+    else if (a.s <= 128) k_update_bj<T, 2><<<grid, kBlock, 0, s>>>(a);
+    else if (a.s <= 256) k_update_bj<T, 4><<<grid, kBlock, 0, s>>>(a);
+    else k_update_bj<T, 8><<<grid, kBlock, 0, s>>>(a);
+    return grid;
+}
+int launch_update_bj(const UpdBj<double> &a, hipStream_t s) { return update_bj_impl(a, s); }
+int launch_update_bj(const UpdBj<float> &a, hipStream_t s) { return update_bj_impl(a, s); }
 
 template <typename T> static void copyz_impl(const Sweep<T> &a, bool sc, int grid, hipStream_t s) {
     if (sc) k_copyz<T, true><<<grid, kBlock, 0, s>>>(a);

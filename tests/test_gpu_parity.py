@@ -59,8 +59,9 @@ def _cases():
         "fv3d_bj": _block_jacobi(P.config2(N=18, nsph=2, radius=3.0), 18),
         # 27-point, blocks of 7 rows straddling grid lines, ragged last block
         "q1_bj": _block_jacobi(P.config4(Ne=11, nblk=2, blk=3), 7),
-        # 130 rows per block: four rows per lane
-        "fv2d_bj": _block_jacobi(P.config1(N=130, nbox=2, box=6), 130),
+        # 128 rows per block (two rows per lane, R-wide loads), blocks
+        # straddling grid lines, a last block of 4 rows
+        "fv2d_bj": _block_jacobi(P.config1(N=130, nbox=2, box=6), 128),
     }
 
 
@@ -420,12 +421,16 @@ def test_gradient_values(case):
 
 # ---------------------------------------------------------------- block Jacobi
 
-@pytest.mark.parametrize("s_rows", [70, 100, 130, 290, 300])
-def test_block_jacobi_preconditioner_lane_widths(s_rows):
-    """Block-Jacobi M^{-1} r and its factor against the oracle for blocks of
-    1, 2, 4 and 8 rows per lane (ragged last block for 70, 130 and 290 rows)
-    on a 300 x 300 grid, and a solve at tolerance."""
-    p = _block_jacobi(P.config1(N=300, nbox=4, box=10), s_rows)
+@pytest.mark.parametrize("N,s_rows", [(300, 70), (300, 100), (300, 130), (300, 290), (300, 300), (299, 64),
+                                      (299, 128), (299, 296)])
+def test_block_jacobi_preconditioner_lane_widths(N, s_rows):
+    """Block-Jacobi M^{-1} r and its factor against the oracle for 1, 2, 4 and
+    8 rows per lane on N x N grids: R-wide loads where the block size is a
+    multiple of R (70, 100, 128, 296 rows), element loads otherwise; ragged
+    last blocks (70, 130, 290 rows on 300^2; every case on 299^2), with a
+    partial last group of rows for 128 and 296 rows on 299^2; and a solve at
+    tolerance."""
+    p = _block_jacobi(P.config1(N=N, nbox=4, box=10), s_rows)
     print("block jacobi lane widths: n", p.n, "block rows", s_rows, flush=True)
     s = _solver(p, m_max=1)
     s.factor_ic0()
