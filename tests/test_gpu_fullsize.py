@@ -148,3 +148,40 @@ def test_large_configs_kernels_and_mixed_deflated(which):
         print(which, "||W^T r||", float((W.t() @ r).norm()), "||r||", float(r.norm()), "floor", floor, flush=True)
         assert float((W.t() @ r).norm()) <= 1e-6 * float(r.norm()) + floor
     s.close()
+
+
+@pytest.mark.parametrize("which", ["cfg2_128", "cfg3_256"])
+def test_block_jacobi_full_size(which):
+    """Block-Jacobi IC(0) with one grid line per block, as bench.py runs it
+    (128^3, FP64) and at 256^3 (four rows per lane): factor and M^{-1} r
+    against the oracle in full, 40 iterations of the fused update +
+    preconditioner loop element-wise against the oracle (matched iterations),
+    and a solve to tolerance (mixed precision at 256^3)."""
+    from paper_2203_08498_amd import esd
+
+    p = P.config2() if which == "cfg2_128" else P.config3()
+    N = p.shape[0]
+    print(which, "block Jacobi, n", p.n, "block rows", N, flush=True)
+    s = esd.Solver.from_problem(p, m_max=p.params["m"], block_rows=N)
+    s.factor_ic0()
+    o = O.Oracle.from_problem(p, block_rows=N)
+    assert o.factor_ic0() == 0
+    rp, c, v = o.factor_csr()
+    assert np.abs(s.factor_diag() - v[rp[1:] - 1]).max() <= 1e-13
+    r = np.random.default_rng(31).standard_normal(p.n)
+    assert _relerr(s.prec(r), o.prec(r)) <= 1e-12
+    x, info = s.solve(p.f, tol=0.0, maxit=40)
+    y, oi = o.solve(p.f, tol=0.0, maxit=40)
+    a, b = s.history()
+    oa, ob = o.history()
+    print(which, "matched 40 iterations: err", _relerr(x, y), flush=True)
+    assert info["iters"] == oi.iters == 40 and _relerr(x, y) <= 1e-10
+    assert np.max(np.abs(a[:10] - oa[:10]) / np.abs(oa[:10])) <= 1e-10
+    assert np.max(np.abs(b[:10] - ob[:10]) / np.abs(ob[:10])) <= 1e-10
+    del o
+    flags = 0 if which == "cfg2_128" else esd.FLAG_MIXED
+    x, info = s.solve(p.f, tol=1e-8, maxit=50000, flags=flags)
+    print(which, "block Jacobi solve its", info["iters"], "fp64 its", info.get("fp64_iters"), "relres",
+          info["true_relres"], flush=True)
+    assert info["converged"] and info["true_relres"] <= max(1e-8, _fp64_floor(p, x, p.f))
+    s.close()
