@@ -26,6 +26,12 @@ with stream launches; all other solves replay the captured iteration graphs.
 The same events bracket the IC(0) sweep launches of each iteration (sweeps
 GB/s).  `traffic` comes from the committed rocprofv3 counter summary.
 cpu_baseline: the FP64 C oracle, one thread.
+
+`large_kernels` (after the timed steps, not part of `value`): the FP32 SpMV
+and IC(0) sweep launches of the mixed solver's inner iterations at 256^3
+(config-3 recipe) and on the Q1 27-point matrix with 160^3 nodes (config-4
+recipe), timed the same way; at 128^3 the FP64 working set is about the size
+of the 256 MB last-level cache, these two are well beyond it.
 """
 import argparse
 import json
@@ -51,6 +57,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bj", action="store_true", help="skip the block-Jacobi sequences")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 and Q1 160^3 kernel timings")
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
@@ -94,6 +101,44 @@ def run_sequence(s, p, args, mode, esd, P, timing, prec_flags=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return recs, wall, tm
+
+
+def large_kernels(esd, P):
+    """FP32 SpMV and sweep-pair rates inside the mixed solver's inner
+    iterations on the config-3 and config-4 matrices (plain form, no W)."""
+    import torch
+
+    out = {}
+    for name, make, maxit in (("cfg3_fv3d_256", P.config3, 50000), ("cfg4_q1_160", P.config4, 300)):
+        p = make()
+        print("# large kernels: %s n=%d nnz=%d" % (name, p.n, p.nnz), file=sys.stderr, flush=True)
+        s = esd.Solver.from_problem(p, m_max=1)
+        s.factor_ic0()
+        f = torch.as_tensor(p.f, device=s.device)
+        # config 4: the first 300 FP32 inner iterations only (its mixed solve
+        # later finishes in FP64, whose iterations would enter the averages)
+        x, info = s.solve(f, tol=1e-8, maxit=maxit, flags=esd.FLAG_MIXED | esd.FLAG_TIMING)
+        tm = s.timing()
+        n, nnz = p.n, p.nnz
+        # FP32 (w = 4): plain-form SpMV gathers z and p_old, writes p and q;
+        # sweep pair reads both triangles with their diagonals, r, y, writes y, z
+        b_spmv = 8.0 * nnz + 16.0 * n
+        b_sw = 8.0 * (nnz + n) + 16.0 * n
+        ok = info["fp64_iters"] == 0 and tm["iters"] > 0
+        sp_s, sw_s = tm["spmv_ms"] * 1e-3, tm["sweep_ms"] * 1e-3
+        out[name] = {
+            "n": n, "nnz": nnz, "fp32_iterations_timed": tm["iters"],
+            "spmv": {"bytes_per_launch": b_spmv, "avg_launch_us": sp_s * 1e6,
+                     "achieved": b_spmv / sp_s / 1e9 if ok else None,
+                     "frac": b_spmv / sp_s / 1e9 / HBM_PEAK_GBS if ok else None},
+            "sweeps": {"bytes_per_pair": b_sw, "avg_pair_us": sw_s * 1e6,
+                       "achieved": b_sw / sw_s / 1e9 if ok else None,
+                       "frac": b_sw / sw_s / 1e9 / HBM_PEAK_GBS if ok else None},
+            "unit": "GB/s", "peak": HBM_PEAK_GBS,
+        }
+        s.close()
+        del p
+    return out
 
 
 def counter_traffic(kernel):
@@ -325,6 +370,8 @@ def main():
             "launches": spmv_n,
         },
     }
+    if not args.no_large and args.N == 128:
+        out["large_kernels"] = large_kernels(esd, P)
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p, args, mt, float(np.mean(its_defl)) if its_defl else its_plain[0])
