@@ -16,7 +16,7 @@ Timed beside it on the same sequence (extra fields, not `value`): plain ICCG
 throughout, the subspace-correction preconditioner, the FP32/FP64 mixed
 solver, deflated and plain, and the block-Jacobi IC(0) preconditioner of the
 paper's parallel solver (natural order, one grid line of N rows per block),
-plain and deflated, with the duration of its one launch per iteration that
+plain, deflated and mixed-precision plain, with the duration of its one launch per iteration that
 updates x and r and applies the preconditioner to the new r.
 
 Roofline: the dominant kernel is the per-iteration SpMV launch; its duration
@@ -228,7 +228,8 @@ def main():
     seqs = (("deflated", esd.DEFLATED, 0), ("plain", esd.PLAIN, 0), ("subspace", esd.SUBSPACE, 0),
             ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED), ("mixed_plain", esd.PLAIN, esd.FLAG_MIXED))
     if sbj is not None:
-        seqs = seqs + (("bj_deflated", esd.DEFLATED, 0), ("bj_plain", esd.PLAIN, 0))
+        seqs = seqs + (("bj_deflated", esd.DEFLATED, 0), ("bj_plain", esd.PLAIN, 0),
+                       ("bj_mixed_plain", esd.PLAIN, esd.FLAG_MIXED))
     solver_of = lambda name: sbj if name.startswith("bj_") else s
     for _ in range(args.warmup):
         for name, mode, pf in seqs:
@@ -298,6 +299,8 @@ def main():
             "block_rows": args.N,
             "deflated_s_per_system": per["bj_deflated"],
             "plain_s_per_system": per["bj_plain"],
+            "mixed_plain_s_per_system": per["bj_mixed_plain"],
+            "iters_mixed_plain_mean": float(np.mean([r["iters"] for r in recs["bj_mixed_plain"]])),
             "iters_sampling_solve": rbd[0]["iters"],
             "iters_deflated_mean": float(np.mean([r["iters"] for r in rbd[1:]])) if args.systems > 1 else None,
             "iters_plain_mean": float(np.mean([r["iters"] for r in rbp])),
