@@ -32,12 +32,13 @@ struct Tiles {
     int t0, t1;
 };
 
+// Tiles [t0, t1) of the order for this block: the nt tiles split as evenly
+// as possible over the grid's positions (xcd_block), so that every XCD gets
+// an eighth of them whatever nt / gridDim is.
 __device__ __forceinline__ Tiles my_tiles(int rows) {
     const int nt = (rows + kBlock - 1) / kBlock;
-    const int G = gridDim.x;
-    const int per = (nt + G - 1) / G;
-    const int t0 = xcd_block() * per;
-    return {t0, min(nt, t0 + per)};
+    const int64_t G = gridDim.x, pos = xcd_block();
+    return {(int)(pos * nt / G), (int)((pos + 1) * nt / G)};
 }
 
 // Block reduction of NV doubles; thread k < NV stores the block total at
@@ -337,8 +338,8 @@ __global__ __launch_bounds__(kTsBlock) void k_tsdot_rm(TsDot<T> a) {
     const int m = a.m, n = a.n;
     const int G = gridDim.x;
     constexpr int STEP = WAVES * RPW;
-    const int per = ((n + G - 1) / G + STEP - 1) / STEP * STEP;
-    const int r0 = xcd_block() * per, r1 = min(n, r0 + per);
+    // rows split evenly over the grid's positions (every XCD an eighth)
+    const int r0 = (int)((int64_t)xcd_block() * n / G), r1 = (int)((int64_t)(xcd_block() + 1) * n / G);
     double acc = 0.0;
     if (k < m) {
 #pragma unroll 4
