@@ -446,6 +446,55 @@ def test_block_jacobi_preconditioner_lane_widths(N, s_rows):
     s.close()
 
 
+def _tridiagonal(n, seed=9):
+    """A diagonally dominant SPD tridiagonal matrix with a random sub-diagonal."""
+    rng = np.random.default_rng(seed)
+    off = -rng.uniform(0.2, 1.0, n - 1)
+    diag = np.zeros(n)
+    diag[1:] += -off
+    diag[:-1] += -off
+    diag += 0.05
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        if i > 0:
+            rows.append(i); cols.append(i - 1); vals.append(off[i - 1])
+        rows.append(i); cols.append(i); vals.append(diag[i])
+        if i < n - 1:
+            rows.append(i); cols.append(i + 1); vals.append(off[i])
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, np.array(rows) + 1, 1)
+    return np.cumsum(rp), np.array(cols, np.int32), np.array(vals)
+
+
+@pytest.mark.parametrize("n,s_rows", [(300, 512), (5, 2), (1, 1), (700, 1)])
+def test_block_jacobi_edge_cases(n, s_rows):
+    """One block holding the whole tridiagonal matrix (M = A: PCG stops after
+    one iteration at the dense solution), tiny and one-row matrices, and
+    one-row blocks (Jacobi: z = r / a_ii), against numpy and the oracle."""
+    from paper_2203_08498_amd import esd
+
+    rp, c, v = _tridiagonal(n)
+    A = P.csr_to_dense(rp, c, v, n)
+    s = esd.Solver(rp, c, v, None, m_max=1, block_rows=s_rows)
+    s.factor_ic0()
+    o = O.Oracle(rp, c, v, block_rows=s_rows)
+    assert o.factor_ic0() == 0
+    r = np.random.default_rng(3).standard_normal(n)
+    z = s.prec(r).cpu().numpy()
+    blk = np.arange(n) // s_rows
+    Abd = np.where(blk[:, None] == blk[None, :], A, 0.0)
+    want = np.linalg.solve(Abd, r)
+    assert np.abs(z - want).max() <= 1e-12 * np.abs(want).max()
+    assert _relerr(z, o.prec(r)) <= 1e-13
+    b = np.random.default_rng(4).standard_normal(n)
+    x, info = s.solve(b, tol=1e-10, maxit=5000)
+    y, oi = o.solve(b, tol=1e-10, maxit=5000)
+    assert info["converged"] and abs(info["iters"] - oi.iters) <= 2 and _relerr(x, y) <= 1e-10
+    if s_rows >= n:
+        assert info["iters"] == 1 and _relerr(x, np.linalg.solve(A, b)) <= 1e-12
+    s.close()
+
+
 def test_block_jacobi_setup_errors():
     from paper_2203_08498_amd import esd
 
