@@ -103,6 +103,27 @@ def run_sequence(s, p, args, mode, esd, P, timing, prec_flags=0):
     return recs, wall, tm
 
 
+def copy_ceiling():
+    """Device-to-device copy of 1 GiB (FP64), the practical HBM ceiling on this
+    GPU: read + written bytes over the mean of 10 copies (hipEvents)."""
+    import torch
+
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    us = a.elapsed_time(b) * 1e3 / 10
+    nbytes = 2.0 * src.numel() * 8
+    del src, dst
+    return {"bytes_per_copy": nbytes, "avg_us": us, "gbs": nbytes / us / 1e3, "frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
+
+
 def large_kernels(esd, P):
     """FP32 SpMV and sweep-pair rates inside the mixed solver's inner
     iterations on the config-3 and config-4 matrices (plain form, no W)."""
@@ -181,11 +202,21 @@ def cpu_baseline(p, args, mt, iters_per_system):
     t0 = time.perf_counter()
     o.solve(p.f, tol=0.0, maxit=args.cpu_iters, mode=O.DEFLATED if mt > 0 else O.PLAIN)
     t_it = (time.perf_counter() - t0) / args.cpu_iters
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": t_it * iters_per_system,
         "unit": "s/system",
         "cores": 1,
         "kind": "oracle",
+        "host": {"cpu_model": model, "nproc": os.cpu_count(),
+                 "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None},
         "sample": "FP64 C oracle, 1 thread: %d deflated PCG iterations (m_tilde=%d, seeded random W) on the "
                   "same %d-row matrix, %.3f s/iteration x %.1f iterations per system (mean of this run); "
                   "IC(0) factor %.2f s not included" % (args.cpu_iters, k, p.n, t_it, iters_per_system, t_fac),
@@ -373,6 +404,7 @@ def main():
             "launches": spmv_n,
         },
     }
+    out["hbm_copy"] = copy_ceiling()
     if not args.no_large and args.N == 128:
         out["large_kernels"] = large_kernels(esd, P)
     if not args.no_cpu:
