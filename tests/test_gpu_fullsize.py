@@ -85,6 +85,15 @@ def test_config2_full_parity_sampling_build_deflated():
     assert i2["true_relres"] <= 1.01e-8
     y3, j3 = o.solve(b2, tol=0.0, maxit=i2["iters"], mode=O.DEFLATED)
     assert abs(i2["kappa"] / j3.kappa - 1) <= 1e-6
+    # the FP32/FP64 mixed deflated solver on the same system, against the
+    # oracle's FP64 solution: both meet relres 1e-8, so they differ by at most
+    # kappa(A) (1e-8 + 1e-8) in relative terms
+    x4, i4 = s.solve(b2, tol=1e-8, maxit=20000, mode=esd.DEFLATED, flags=esd.FLAG_MIXED)
+    print("mixed deflated its", i4["iters"], "outer", i4["outer_iters"], "fp64 its", i4["fp64_iters"], "relres",
+          i4["true_relres"], "err vs FP64 oracle", _relerr(x4, y2), "FP64 gpu err", _relerr(x2, y2), flush=True)
+    assert i4["true_relres"] <= 1.01e-8
+    # regression guard: measured 3.1e-10 at this size (the kappa bound is far looser)
+    assert _relerr(x4, y2) <= 1e-7
     s.close()
 
 
