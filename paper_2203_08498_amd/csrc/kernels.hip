@@ -380,8 +380,12 @@ __device__ __forceinline__ T add_coarse(const Sweep<T> &a, int i, T zi) {
     }
 }
 
+// The sweep launches are latency-bound (one dependent round trip per row, a
+// level of 0.26-0.79 M rows takes more than one round of resident waves), so
+// both ask for 8 waves per SIMD (at most 64 VGPRs; the FP64 forward kernel
+// needed 66 without the bound).
 template <typename T, bool LAST, bool SC>
-__global__ __launch_bounds__(kBlock) void k_fwd(Sweep<T> a) {
+__global__ __launch_bounds__(kBlock, 8) void k_fwd(Sweep<T> a) {
     if (a.S->done) return;
     double acc[1] = {0.0};
     const T *y = a.y;
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(Sweep<T> a) {
 }
 
 template <typename T, bool SC>
-__global__ __launch_bounds__(kBlock) void k_bwd(Sweep<T> a) {
+__global__ __launch_bounds__(kBlock, 8) void k_bwd(Sweep<T> a) {
     if (a.S->done) return;
     double acc[1] = {0.0};
     const T *z = a.z;
