@@ -139,7 +139,8 @@ esd_status esd_setup_block_jacobi(esd_ctx **ctx, void *hip_stream, int64_t n, co
 esd_status esd_update_values(esd_ctx *ctx, const double *val);
 
 /* esd_factor_ic0 - IC(0) on the stored lower pattern in the chosen order (the
- * paper's IC preconditioner, Sec. 4.4).  FP64 factor plus an FP32 copy.
+ * paper's IC preconditioner, Sec. 4.4); after esd_setup_block_jacobi, IC(0)
+ * of the block-diagonal part (Sec. 5.3).  FP64 factor plus an FP32 copy.
  * ESD_ENOTSPD on a non-positive pivot. */
 esd_status esd_factor_ic0(esd_ctx *ctx);
 
@@ -246,7 +247,7 @@ esd_status esd_get_samples(esd_ctx *ctx, int32_t *iters_by_slot);
  * (0 <= slot < m of the last esd_sample_errors / esd_load_samples; the
  * content of an empty slot is undefined) */
 esd_status esd_get_sample_vector(esd_ctx *ctx, int32_t slot, double *out);
-/* (h) int32[8]: n, nnz, number of sweep levels, number of colours,
+/* (h) int32[8]: n, nnz, number of sweep levels (1 with block Jacobi), number of colours,
  * 1/0 whether the iteration kernels read A, L and U in the class-aligned
  * layout (per 64-row slice one column offset per slot instead of one column
  * index per entry; used when no slice needs more than 64 slots), and the
@@ -254,8 +255,12 @@ esd_status esd_get_sample_vector(esd_ctx *ctx, int32_t slot, double *out);
  * iteration SpMV reads */
 esd_status esd_get_layout(esd_ctx *ctx, int32_t *out8);
 /* (h) double[4] from the last solve run with ESD_FLAG_TIMING: average ms per
- * executed iteration of out[0] the SpMV launch, out[1] all sweep launches,
- * out[2] the vector-update launch; out[3] the number of timed iterations. */
+ * executed iteration of out[0] the SpMV launch, out[1] the preconditioner
+ * (all sweep launches; with block Jacobi and no subspace correction the one
+ * launch that updates x, r and applies M^{-1}), out[2] what runs between the
+ * two (alpha finalize and, unless fused into out[1], the vector update; with
+ * subspace correction also W^T r and u); out[3] the number of timed
+ * iterations. */
 esd_status esd_get_timing(esd_ctx *ctx, double *out4);
 
 const char *esd_status_string(esd_status s);
