@@ -18,7 +18,9 @@
  *     tensors); the library never frees them and never keeps them after the
  *     call returns.  All device memory the library needs for its own state
  *     (permuted matrix, factor, auxiliary space, work vectors) is allocated by
- *     esd_setup / esd_build_aux and released by esd_destroy.
+ *     esd_setup, and lazily by esd_solve / esd_build_aux when a larger
+ *     history or sampling table, the preconditioned Rayleigh-Ritz buffer or a
+ *     captured iteration graph is first needed; esd_destroy releases it.
  *   - Vectors (b, x0, x, lambda, v0, W) are float64 in the caller's row order;
  *     the library permutes internally.
  *   - Work is enqueued on the stream given to esd_setup.  Calls that return
