@@ -31,7 +31,9 @@ cpu_baseline: the FP64 C oracle, one thread.
 and IC(0) sweep launches of the mixed solver's inner iterations at 256^3
 (config-3 recipe) and on the Q1 27-point matrix with 160^3 nodes (config-4
 recipe), timed the same way; at 128^3 the FP64 working set is about the size
-of the 256 MB last-level cache, these two are well beyond it.
+of the 256 MB last-level cache, these two are well beyond it.  On the Q1
+matrix also FP64 deflated against plain ICCG for one system after a sampling
+solve (its 64 floating blocks give isolated small eigenvalues).
 """
 import argparse
 import json
@@ -133,7 +135,7 @@ def large_kernels(esd, P):
     for name, make, maxit in (("cfg3_fv3d_256", P.config3, 50000), ("cfg4_q1_160", P.config4, 300)):
         p = make()
         print("# large kernels: %s n=%d nnz=%d" % (name, p.n, p.nnz), file=sys.stderr, flush=True)
-        s = esd.Solver.from_problem(p, m_max=1)
+        s = esd.Solver.from_problem(p, m_max=p.params["m"] if name == "cfg4_q1_160" else 1)
         s.factor_ic0()
         f = torch.as_tensor(p.f, device=s.device)
         # config 4: the first 300 FP32 inner iterations only (its mixed solve
@@ -157,6 +159,26 @@ def large_kernels(esd, P):
                        "frac": b_sw / sw_s / 1e9 / HBM_PEAK_GBS if ok else None},
             "unit": "GB/s", "peak": HBM_PEAK_GBS,
         }
+        if name == "cfg4_q1_160":
+            # FP64 deflated vs plain ICCG on this matrix's many isolated small
+            # eigenvalues: sampling solve (m = 64), build_aux, system 2 both ways
+            m, theta = p.params["m"], 1e-3
+            s.sample_errors(m)
+            x1, i1 = s.solve(f, tol=1e-8, maxit=50000)
+            st, ritz, mb, mt = s.build_aux(theta)
+            b2 = s.sequence_rhs(f, x1, 0.1)
+            res = {}
+            for label, mode in (("plain", esd.PLAIN), ("deflated", esd.DEFLATED)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x2, i2 = s.solve(b2, tol=1e-8, maxit=50000, mode=mode)
+                torch.cuda.synchronize()
+                res[label] = {"iters": i2["iters"], "s": time.perf_counter() - t0, "true_relres": i2["true_relres"]}
+            out[name]["fp64_deflation"] = {
+                "m": m, "theta": theta, "m_bar": mb, "m_tilde": mt, "sampling_iters": i1["iters"],
+                "plain": res["plain"], "deflated": res["deflated"],
+                "speedup_vs_plain": res["plain"]["s"] / res["deflated"]["s"],
+            }
         s.close()
         del p
     return out
