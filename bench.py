@@ -105,6 +105,32 @@ def run_sequence(s, p, args, mode, esd, P, timing, prec_flags=0):
     return recs, wall, tm
 
 
+def grad_rate(s, p):
+    """esd_grad_values on the benchmark matrix: g_k = -lam_row(k) x_col(k) for
+    every stored entry; algorithmic bytes: column index and g per entry, row
+    pointer, lam and x per row.  Mean of 20 launches between hipEvents."""
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    g0 = torch.Generator(device="cpu").manual_seed(5)
+    lam = torch.randn(p.n, generator=g0, dtype=torch.float64).to(s.device)
+    x = torch.randn(p.n, generator=g0, dtype=torch.float64).to(s.device)
+    g = torch.empty(p.nnz, dtype=torch.float64, device=s.device)
+    call = lambda: s.L.esd_grad_values(s.h, esd._dptr(lam), esd._dptr(x), esd._dptr(g))
+    for _ in range(3):
+        call()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s.stream)
+    for _ in range(20):
+        call()
+    b.record(s.stream)
+    b.synchronize()
+    us = a.elapsed_time(b) * 1e3 / 20
+    nbytes = 12.0 * p.nnz + 24.0 * p.n
+    return {"bytes_per_launch": nbytes, "avg_us": us, "gbs": nbytes / us / 1e3, "frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
+
+
 def copy_ceiling():
     """Device-to-device copy of 1 GiB (FP64), the practical HBM ceiling on this
     GPU: read + written bytes over the mean of 10 copies (hipEvents)."""
@@ -427,6 +453,7 @@ def main():
         },
     }
     out["hbm_copy"] = copy_ceiling()
+    out["gradient"] = grad_rate(s, p)
     if not args.no_large and args.N == 128:
         out["large_kernels"] = large_kernels(esd, P)
     if not args.no_cpu:

@@ -232,7 +232,8 @@ esd_status esd_sequence_rhs(esd_ctx *ctx, const double *f, const double *xprev, 
 /* esd_grad_values - gradient of a loss through x = A^{-1} b with respect to
  * every stored value: gval[k] = -lam[row k] * x[col k] in the caller's CSR
  * order, where lam = A^{-1} (dL/dx) is the adjoint solution.
- * lam(d), x(d) float64[n]; gval(d) float64[nnz] out. */
+ * lam(d), x(d) float64[n]; gval(d) float64[nnz] out.  Enqueued on the
+ * context's stream without synchronising (device output only). */
 esd_status esd_grad_values(esd_ctx *ctx, const double *lam, const double *x, double *gval);
 
 /* Inspection entry points (used by tests and the benchmark). */

@@ -1385,8 +1385,7 @@ esd_status esd_sequence_rhs(esd_ctx *c, const double *f, const double *xprev, do
 esd_status esd_grad_values(esd_ctx *c, const double *lam, const double *x, double *gval) {
     if (!c || !lam || !x || !gval) return ESD_EINVAL;
     esd::launch_grad((int)c->n, c->urp, c->ucol, lam, x, gval, c->stream);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError()); // device output only: ordered on the stream, no synchronisation
     return ESD_OK;
 }
 

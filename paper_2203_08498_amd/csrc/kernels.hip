@@ -1210,12 +1210,32 @@ __global__ __launch_bounds__(kBlock) void k_tsgemm(int n, const double *X, int m
     }
 }
 
-__global__ void k_grad(int n, const int64_t *rowptr, const int32_t *col, const double *lam, const double *x,
-                       double *g) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double li = lam[i];
-    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) g[k] = -li * x[col[k]];
+// g_k = -lam_row(k) x_col(k) for every stored entry, CSR order.  One wavefront
+// per 64 rows: their entries are one contiguous range, which the lanes stream
+// in order (coalesced col and g); lane j holds the start of row j, and each
+// entry finds its row by a binary search over those starts (shuffles), the
+// last row whose start is <= k, so empty rows are passed over.
+__global__ __launch_bounds__(kBlock) void k_grad(int n, const int64_t *rowptr, const int32_t *col, const double *lam,
+                                                 const double *x, double *g) {
+    const int lane = threadIdx.x & 63;
+    const int r0 = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64;
+    if (r0 >= n) return; // uniform over the wavefront
+    const int rl = min(64, n - r0);
+    // entry offsets fit in int32 (setup rejects nnz >= 2^31); lanes >= rl hold the end
+    const int st = (int)rowptr[r0 + min(lane, rl)];
+    const int e0 = __shfl(st, 0, 64), e1 = (int)rowptr[r0 + rl];
+    const double li = lane < rl ? lam[r0 + lane] : 0.0;
+    for (int base = e0; base < e1; base += 64) {
+        const int k = base + lane;
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int s = __shfl(st, lo + step, 64); // lo + step <= 63
+            if (s <= k) lo += step;
+        }
+        const double lr = __shfl(li, lo, 64);
+        if (k < e1) g[k] = -lr * x[col[k]];
+    }
 }
 
 inline int blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
