@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bj", action="store_true", help="skip the block-Jacobi sequences")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 and Q1 160^3 kernel timings")
-    ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--cpu-iters", type=int, default=300)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
