@@ -244,9 +244,12 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
     return V;
 }
 
-// One application of the preconditioner (all sweep launches).  With sc the
-// coarse term W u is added into zsc.  Every launch that finishes rows of z
-// writes one (r, z) partial per block; returns the number of partial slots.
+// One application of the preconditioner (all sweep launches, or the one
+// block-Jacobi launch).  With sc the coarse term W u is added into zsc.
+// rho partials, one per block: without subspace correction rho = (r, z) =
+// ||L^{-1} r||^2, so the forward launches write ||y||^2; with it, the
+// launches that finish rows of z write (r, z + W u).  Returns the number of
+// partial slots.
 template <typename T>
 int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_l0 = false) {
     esd::Sweep<T> s{};
