@@ -122,11 +122,14 @@ esd_status esd_setup(esd_ctx **ctx, void *hip_stream, int64_t n, const int64_t *
  * esd_factor_ic0 then computes IC(0) of the block-diagonal part of A, i.e.
  * every coupling between two blocks is left out of the preconditioner (A,
  * the SpMV and everything else keep them).
- *   block_rows: 1 .. 512.  Every coupling inside a block must join two
+ *   block_rows >= 1.  When every coupling inside a block joins two
  *     consecutive rows (tridiagonal blocks; on a natural-order grid, blocks of
- *     at most one grid line), so that each block's factor is its exact
- *     Cholesky factor and M^{-1} r is two recurrences per block; otherwise
- *     ESD_EINVAL.
+ *     at most one grid line) and block_rows <= 512, each block's factor is
+ *     its exact Cholesky factor and M^{-1} r runs as one launch (two
+ *     recurrences per block, one wavefront each).  Other blocks (the paper's
+ *     few large blocks, for instance) run the level-scheduled sweeps of the
+ *     in-block couplings: correct for any block shape, one launch per level,
+ *     so slow when the chains inside a block are long.
  * Sampling, auxiliary space, all solver modes, mixed precision and the
  * gradient work as after esd_setup.
  */

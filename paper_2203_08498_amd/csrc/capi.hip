@@ -1109,8 +1109,10 @@ esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, const int64_t 
     c->n = n;
     c->nnz = H.nnz;
     c->ncolors = H.ncolors;
-    c->bj_rows = H.block_rows;
-    c->bj_nb = H.block_rows > 0 ? (int)((n + H.block_rows - 1) / H.block_rows) : 0;
+    // the block kernels serve tridiagonal blocks; other block-Jacobi blocks
+    // run through the level-scheduled sweeps of their in-block factor
+    c->bj_rows = H.bj_scan ? H.block_rows : 0;
+    c->bj_nb = c->bj_rows > 0 ? (int)((n + c->bj_rows - 1) / c->bj_rows) : 0;
     c->lvl = H.lvl_ptr;
     c->p2u_h = H.p2u;
     c->lperm_h = H.lperm;
@@ -1232,7 +1234,7 @@ esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *
 
 esd_status esd_setup_block_jacobi(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr,
                                   const int32_t *col, const double *val, int32_t block_rows, int32_t m_max) {
-    if (block_rows < 1 || block_rows > esd::kMaxBlockRows) return ESD_EINVAL;
+    if (block_rows < 1) return ESD_EINVAL;
     return setup_impl(out, hip_stream, n, rowptr, col, val, nullptr, block_rows, m_max);
 }
 

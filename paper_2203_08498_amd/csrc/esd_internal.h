@@ -8,7 +8,7 @@ namespace esd {
 
 constexpr int kSlice = 64;   // sliced-ELL slice height = wavefront size
 constexpr int kMaxCols = 64; // largest auxiliary-space dimension
-constexpr int kMaxBlockRows = 512; // largest block-Jacobi block (one wavefront, 8 rows per lane)
+constexpr int kMaxBlockRows = 512; // largest block of the block-scan sweeps (one wavefront, 8 rows per lane)
 
 // Sliced-ELL matrix on the host while it is being built: slice s holds rows
 // [64 s, 64 s + 64); entry k of lane t sits at sptr[s] + 64 k + t.  Padding
@@ -24,6 +24,7 @@ struct HostLayout {
     int64_t n = 0, nnz = 0;
     int ncolors = 0;
     int64_t block_rows = 0;        // > 0: block-Jacobi IC(0) with blocks of that many consecutive rows
+    bool bj_scan = false;          // block Jacobi with tridiagonal blocks: one level, block-scan sweeps
     std::vector<int32_t> lperm;    // logical position -> user row
     std::vector<int32_t> p2u;      // physical row -> user row
     std::vector<int32_t> u2p;      // user row -> physical row
@@ -40,9 +41,12 @@ struct HostLayout {
 };
 
 // Builds the layout; returns an empty string on success, else the reason.
-// block_rows > 0 (block-Jacobi IC(0)): natural order, one level, and L / U
-// hold only couplings inside a block of block_rows consecutive rows, which
-// must join consecutive rows (tridiagonal blocks); A keeps every entry.
+// block_rows > 0 (block-Jacobi IC(0)): natural order, and L / U hold only
+// couplings inside a block of block_rows consecutive rows (A keeps every
+// entry).  When every such coupling joins consecutive rows (tridiagonal
+// blocks) there is one level and bj_scan is set; otherwise the levels are
+// the chains of in-block couplings and the ordinary level-scheduled sweeps
+// apply the block-diagonal factor.
 std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                          const int32_t *colors, int64_t block_rows, HostLayout &out);
 

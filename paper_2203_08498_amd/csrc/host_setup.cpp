@@ -51,11 +51,10 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
     H.n = n;
     H.nnz = nnz;
     H.block_rows = block_rows;
-    if (block_rows < 0 || block_rows > kMaxBlockRows) return "block size out of range";
+    if (block_rows < 0) return "block size out of range";
     if (block_rows > 0 && colors) return "block Jacobi keeps the natural order (no colours)";
     // block Jacobi: the factor keeps only couplings inside a block of
-    // block_rows consecutive rows; every such coupling must join consecutive
-    // rows (tridiagonal blocks)
+    // block_rows consecutive rows
     const auto in_blk = [block_rows](int64_t u, int64_t c) { return block_rows == 0 || u / block_rows == c / block_rows; };
     // validate rows: columns in range, strictly increasing, diagonal present
     for (int64_t i = 0; i < n; ++i) {
@@ -67,11 +66,17 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
         }
         if (!diag) return "missing diagonal entry";
     }
+    // tridiagonal blocks (every coupling inside a block joins consecutive rows)
+    // take the one-launch block sweeps; other blocks the level schedule of
+    // their in-block couplings
+    H.bj_scan = block_rows > 0 && block_rows <= kMaxBlockRows;
     if (block_rows > 0)
-        for (int64_t i = 0; i < n; ++i)
+        for (int64_t i = 0; i < n && H.bj_scan; ++i)
             for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
-                if (col[k] != i && in_blk(i, col[k]) && col[k] != i - 1 && col[k] != i + 1)
-                    return "block Jacobi needs tridiagonal blocks (couplings inside a block only between consecutive rows)";
+                if (col[k] != i && in_blk(i, col[k]) && col[k] != i - 1 && col[k] != i + 1) {
+                    H.bj_scan = false;
+                    break;
+                }
     // logical order: stable counting sort by colour
     H.lperm.resize(n);
     std::vector<int32_t> lpos(n);
@@ -97,12 +102,13 @@ std::string build_layout(int64_t n, const int64_t *rowptr, const int32_t *col, c
     // level of every logical row: longest chain of logically-lower couplings
     std::vector<int32_t> lev(n, 0);
     int32_t nlev = 1;
-    // block Jacobi: one level (the block sweeps do not use the level schedule)
-    for (int64_t l = 0; l < (block_rows > 0 ? 0 : n); ++l) {
+    // (tridiagonal block Jacobi: one level, the block sweeps do not use the
+    // level schedule; other block Jacobi: chains of in-block couplings only)
+    for (int64_t l = 0; l < (H.bj_scan ? 0 : n); ++l) {
         int32_t u = H.lperm[l], lv = 0;
         for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
             int32_t lc = lpos[col[k]];
-            if (lc < l) lv = std::max(lv, lev[lc] + 1);
+            if (lc < l && in_blk(u, col[k])) lv = std::max(lv, lev[lc] + 1);
         }
         lev[l] = lv;
         nlev = std::max(nlev, lv + 1);

@@ -62,6 +62,9 @@ def _cases():
         # 128 rows per block (two rows per lane, R-wide loads), blocks
         # straddling grid lines, a last block of 4 rows
         "fv2d_bj": _block_jacobi(P.config1(N=130, nbox=2, box=6), 128),
+        # blocks of two planes and 5 rows (not tridiagonal): level-scheduled
+        # sweeps of the in-block factor, ragged last block
+        "fv3d_bjg": _block_jacobi(P.config2(N=13, nsph=2, radius=2.5), 2 * 169 + 5),
     }
 
 
@@ -495,14 +498,42 @@ def test_block_jacobi_edge_cases(n, s_rows):
     s.close()
 
 
+@pytest.mark.parametrize("case", ["4_blocks_3d", "3_lines_2d", "tridiagonal_600"])
+def test_block_jacobi_general_blocks(case):
+    """Blocks that the block-scan kernel does not take: a few large blocks as
+    in the paper's parallel solver (4 blocks of a 16^3 matrix, ragged), blocks
+    of three grid lines, and tridiagonal blocks above 512 rows; M^{-1} r and
+    solves against the oracle."""
+    from paper_2203_08498_amd import esd
+
+    if case == "4_blocks_3d":
+        p = _block_jacobi(P.config2(N=16, nsph=1, radius=2.0), 16 ** 3 // 4 + 7)
+    elif case == "3_lines_2d":
+        p = _block_jacobi(P.config1(N=40, nbox=2, box=6), 3 * 40)
+    else:
+        rp, c, v = _tridiagonal(1500)
+        p = P.Problem(name="tri", n=1500, rowptr=rp, col=c, val=v, colors=None,
+                      f=np.random.default_rng(2).standard_normal(1500), shape=(1500,), params={"block_rows": 600})
+    print("general block jacobi", case, "n", p.n, "block rows", _bj(p), flush=True)
+    s = _solver(p, m_max=1)
+    s.factor_ic0()
+    assert s.layout()["levels"] > 1
+    o = _oracle(p)
+    r = np.random.default_rng(8).standard_normal(p.n)
+    assert _relerr(s.prec(r), o.prec(r)) <= 1e-12
+    x, info = s.solve(p.f, tol=1e-8, maxit=5000)
+    y, oi = o.solve(p.f, tol=1e-8, maxit=5000)
+    print("  its gpu/oracle", info["iters"], oi.iters, flush=True)
+    assert info["converged"] and abs(info["iters"] - oi.iters) <= 2 and _relerr(x, y) <= 1e-10
+    s.close()
+
+
 def test_block_jacobi_setup_errors():
     from paper_2203_08498_amd import esd
 
     p = CASES["fv3d_colors"]
-    with pytest.raises(esd.EsdError):  # a block of 14 rows reaches a y-neighbour: not tridiagonal
-        esd.Solver(p.rowptr, p.col, p.val, None, m_max=1, block_rows=14)
     with pytest.raises(esd.EsdError):
-        esd.Solver(p.rowptr, p.col, p.val, None, m_max=1, block_rows=513)
+        esd.Solver(p.rowptr, p.col, p.val, None, m_max=1, block_rows=0)
     with pytest.raises(ValueError):
         esd.Solver(p.rowptr, p.col, p.val, p.colors, m_max=1, block_rows=13)
 

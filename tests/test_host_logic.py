@@ -201,15 +201,45 @@ def test_block_jacobi_layout(driver, tmp_path, name, s):
     assert set(as_set(out["U"])) == {(j, i) for (i, j) in low}
 
 
-def test_block_jacobi_layout_rejects_non_tridiagonal_blocks_and_colours(driver, tmp_path):
+@pytest.mark.parametrize("name,s", [("fv3d_12", 2 * 144 + 5), ("fv2d_natural", 3 * 24), ("q1_7", 700)])
+def test_block_jacobi_layout_general_blocks(driver, tmp_path, name, s):
+    """Blocks that are not tridiagonal (several grid lines or planes, or one
+    block for the whole Q1 matrix): natural logical order, levels = longest
+    chains of in-block couplings (brute force), L / U = the in-block couplings."""
+    base = CASES[name]
+    p = P.Problem(name=name, n=base.n, rowptr=base.rowptr, col=base.col, val=base.val, colors=None, f=base.f,
+                  shape=base.shape, params={})
+    out = _run_layout(driver, str(tmp_path), p, block_rows=s)
+    assert out["ok"] == 1, out.get("why")
+    n = p.n
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(n, n))
+    lev = np.zeros(n, np.int64)
+    for u in range(n):
+        nb = A.indices[A.indptr[u]:A.indptr[u + 1]]
+        nb = nb[(nb < u) & (nb // s == u // s)]
+        lev[u] = 1 + lev[nb].max() if nb.size else 0
+    assert len(out["lvl"]) - 1 == lev.max() + 1 > 2
+    assert np.array_equal(np.diff(out["lvl"]), np.bincount(lev))
+    assert np.array_equal(out["p2u"], np.lexsort((np.arange(n), lev)))
+    p2u = out["p2u"]
+    coo = A.tocoo()
+    ref = {(int(i), int(j)): v for i, j, v in zip(coo.row, coo.col, coo.data)}
+
+    def user_set(t):
+        r, c, v = t
+        return {(int(p2u[a]), int(p2u[b])): x for a, b, x in zip(r, c, v)}
+
+    assert user_set(out["A"]) == ref
+    low = {k: v for k, v in ref.items() if k[1] < k[0] and k[0] // s == k[1] // s}
+    assert user_set(out["L"]) == low
+    assert set(user_set(out["U"])) == {(j, i) for (i, j) in low}
+
+
+def test_block_jacobi_layout_rejects_colours_and_bad_sizes(driver, tmp_path):
     p = CASES["fv3d_12"]
+    assert _run_layout(driver, str(tmp_path), p, block_rows=12)["ok"] == 0  # colours given
     q = P.Problem(name="x", n=p.n, rowptr=p.rowptr, col=p.col, val=p.val, colors=None, f=p.f, shape=p.shape, params={})
-    out = _run_layout(driver, str(tmp_path), q, block_rows=13)  # a block reaches the y-neighbour
-    assert out["ok"] == 0 and "tridiagonal" in out["why"]
-    out = _run_layout(driver, str(tmp_path), p, block_rows=12)  # colours given
-    assert out["ok"] == 0
-    out = _run_layout(driver, str(tmp_path), q, block_rows=513)
-    assert out["ok"] == 0
+    assert _run_layout(driver, str(tmp_path), q, block_rows=-3)["ok"] == 0
 
 
 def test_sampling_table_matches_worked_examples_and_oracle(driver, tmp_path):
