@@ -14,10 +14,13 @@ Gram-Schmidt, Rayleigh-Ritz, W, C = W^T A W), then systems 2..10 deflated.
 `value` = mean seconds per system of that step (sampling and build included).
 Timed beside it on the same sequence (extra fields, not `value`): plain ICCG
 throughout, the subspace-correction preconditioner, the FP32/FP64 mixed
-solver, deflated and plain, and the block-Jacobi IC(0) preconditioner of the
-paper's parallel solver (natural order, one grid line of N rows per block),
-plain, deflated and mixed-precision plain, with the duration of its one launch per iteration that
-updates x and r and applies the preconditioner to the new r.
+solver, deflated and plain, with restarted refinement steps and with
+residual replacement (ESD_FLAG_MIXED_KEEP, one continued FP32 CG run), and the
+block-Jacobi IC(0) preconditioner of the paper's parallel solver (natural
+order, one grid line of N rows per block), plain, deflated and
+mixed-precision plain (both refinement forms), with the duration of its one
+launch per iteration that updates x and r and applies the preconditioner to
+the new r.
 
 Roofline: the dominant kernel is the per-iteration SpMV launch; its duration
 is measured with hipEvents on the solver's stream around every executed
@@ -61,6 +64,8 @@ def parse():
     ap.add_argument("--no-bj", action="store_true", help="skip the block-Jacobi sequences")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 and Q1 160^3 kernel timings")
     ap.add_argument("--cpu-iters", type=int, default=300)
+    ap.add_argument("--keep-eta", type=float, default=1e-2,
+                    help="reduction between residual replacements of the mixed solver with ESD_FLAG_MIXED_KEEP")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -304,15 +309,28 @@ def main():
     if not args.no_bj:
         sbj = esd.Solver.from_problem(p, m_max=args.m, block_rows=args.N)
         sbj.set_power_start(P.power_start(2, p.n))
+    keep = esd.FLAG_MIXED | esd.FLAG_MIXED_KEEP
     seqs = (("deflated", esd.DEFLATED, 0), ("plain", esd.PLAIN, 0), ("subspace", esd.SUBSPACE, 0),
-            ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED), ("mixed_plain", esd.PLAIN, esd.FLAG_MIXED))
+            ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED), ("mixed_plain", esd.PLAIN, esd.FLAG_MIXED),
+            ("mixed_keep_deflated", esd.DEFLATED, keep), ("mixed_keep_plain", esd.PLAIN, keep))
     if sbj is not None:
         seqs = seqs + (("bj_deflated", esd.DEFLATED, 0), ("bj_plain", esd.PLAIN, 0),
-                       ("bj_mixed_plain", esd.PLAIN, esd.FLAG_MIXED))
+                       ("bj_mixed_plain", esd.PLAIN, esd.FLAG_MIXED), ("bj_mixed_keep_plain", esd.PLAIN, keep))
     solver_of = lambda name: sbj if name.startswith("bj_") else s
+
+    def run(name, mode, pf, timing):
+        sv = solver_of(name)
+        if pf & esd.FLAG_MIXED_KEEP:
+            sv.set_mixed_params(args.keep_eta, 60)
+        try:
+            return run_sequence(sv, p, args, mode, esd, P, timing, pf)
+        finally:
+            if pf & esd.FLAG_MIXED_KEEP:
+                sv.set_mixed_params()
+
     for _ in range(args.warmup):
         for name, mode, pf in seqs:
-            run_sequence(solver_of(name), p, args, mode, esd, P, False, pf)
+            run(name, mode, pf, False)
         print("# warmup step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     walls = {name: [] for name, _, _ in seqs}
@@ -323,7 +341,7 @@ def main():
     bj_n = 0
     for k in range(args.steps):
         for name, mode, pf in seqs:
-            r, wall, tm = run_sequence(solver_of(name), p, args, mode, esd, P, name in ("deflated", "bj_deflated"), pf)
+            r, wall, tm = run(name, mode, pf, name in ("deflated", "bj_deflated"))
             walls[name].append(wall)
             recs[name] = r
             if tm and name == "deflated":
@@ -380,6 +398,8 @@ def main():
             "plain_s_per_system": per["bj_plain"],
             "mixed_plain_s_per_system": per["bj_mixed_plain"],
             "iters_mixed_plain_mean": float(np.mean([r["iters"] for r in recs["bj_mixed_plain"]])),
+            "mixed_keep_plain_s_per_system": per["bj_mixed_keep_plain"],
+            "iters_mixed_keep_plain_mean": float(np.mean([r["iters"] for r in recs["bj_mixed_keep_plain"]])),
             "iters_sampling_solve": rbd[0]["iters"],
             "iters_deflated_mean": float(np.mean([r["iters"] for r in rbd[1:]])) if args.systems > 1 else None,
             "iters_plain_mean": float(np.mean([r["iters"] for r in rbp])),
@@ -416,6 +436,16 @@ def main():
         "subspace_s_per_system": per["subspace"],
         "mixed_deflated_s_per_system": per["mixed_deflated"],
         "mixed_plain_s_per_system": per["mixed_plain"],
+        # the same mixed solver with ESD_FLAG_MIXED_KEEP: each refinement step
+        # replaces the residual of the running FP32 CG instead of restarting it
+        "mixed_keep_eta": args.keep_eta,
+        "mixed_keep_deflated_s_per_system": per["mixed_keep_deflated"],
+        "mixed_keep_plain_s_per_system": per["mixed_keep_plain"],
+        "iters_mixed_keep_deflated_mean": float(np.mean([r["iters"] for r in recs["mixed_keep_deflated"][1:]])) if args.systems > 1 else None,
+        "iters_mixed_keep_plain_mean": float(np.mean([r["iters"] for r in recs["mixed_keep_plain"]])),
+        "mixed_keep_m_tilde": recs["mixed_keep_deflated"][0].get("m_tilde_built", 0),
+        "mixed_keep_fp64_iters_total": int(sum(r["fp64_iters"] for r in recs["mixed_keep_deflated"] + recs["mixed_keep_plain"])),
+        "mixed_keep_true_relres_max": max(r["true_relres"] for r in recs["mixed_keep_deflated"] + recs["mixed_keep_plain"]),
         "deflated_s_systems_2_to_K": float(np.mean([r["seconds"] for r in rd[1:]])) if len(rd) > 1 else None,
         "plain_s_systems_2_to_K": float(np.mean([r["seconds"] for r in rp[1:]])) if len(rp) > 1 else None,
         "iters_sampling_solve": rd[0]["iters"],

@@ -76,6 +76,11 @@ typedef enum {
                                  replays of a captured 16-iteration HIP graph, cached in the context
                                  (solves with ESD_FLAG_TIMING, ESD_FLAG_TIMING_SPMV or
                                  ESD_FLAG_SYNC_EVERY always use stream launches) */
+#define ESD_FLAG_MIXED_KEEP 256 /* with ESD_FLAG_MIXED: a refinement step whose inner run reached its
+                                   target does not restart CG; the FP64 true residual replaces that
+                                   run's FP32 recurrence residual and the run continues with its
+                                   search direction (beta recomputed from the new residual's rho).
+                                   An inner run that stagnated is followed by a fresh one. */
 
 typedef struct {
     int32_t iters;        /* CG iterations (mixed: total inner iterations) */
@@ -209,7 +214,11 @@ esd_status esd_get_aux(esd_ctx *ctx, double *W, double *C);
 esd_status esd_set_power_start(esd_ctx *ctx, const double *v0);
 
 /* esd_set_mixed_params - inner relative tolerance of each FP32 inner solve
- * (default 1e-4) and the maximum number of FP64 refinement steps (default 30). */
+ * (default 1e-4) and the maximum number of FP64 refinement steps (default 30).
+ * With ESD_FLAG_MIXED_KEEP the inner tolerance is the reduction between two
+ * residual replacements; about 1e-2 suits it: after much larger reductions the
+ * FP32 recurrence has drifted far from the true residual, and replacing it
+ * disturbs the conjugacy of the run. */
 esd_status esd_set_mixed_params(esd_ctx *ctx, double inner_tol, int32_t max_outer);
 
 /*
@@ -244,7 +253,8 @@ esd_status esd_spmv(esd_ctx *ctx, const double *x, double *y);       /* y = A x,
 esd_status esd_prec_apply(esd_ctx *ctx, const double *r, double *z); /* z = (L L^T)^{-1} r, (d) */
 esd_status esd_get_perm(esd_ctx *ctx, int32_t *perm);  /* (h) int32[n]: logical position -> user row */
 esd_status esd_get_factor_diag(esd_ctx *ctx, double *ldiag); /* (h) float64[n] l_ii, user row order */
-/* (h) alpha[cap], beta[cap] of the last solve (mixed: the first inner solve);
+/* (h) alpha[cap], beta[cap] of the last solve (mixed: the first inner run, which with
+ * ESD_FLAG_MIXED_KEEP spans every refinement step it continued through);
  * returns the count of alphas through *count; beta has count-1 entries. */
 esd_status esd_get_history(esd_ctx *ctx, double *alpha, double *beta, int32_t cap, int32_t *count);
 /* (h) int32[m]: iteration stored in each sampling slot (0 = empty) */

@@ -384,11 +384,15 @@ struct KrylovOpts {
     const double *xbase = nullptr; // mixed inner solves sample xbase + S.xscale * iterate
     bool resid = false;    // sampling stores residuals (no xbase)
     bool method_b = false; // sampling method B: slots chosen on the device
+    // continue a run whose residual the caller replaced: S keeps iter, rho and
+    // beta of that run, its last direction is in p[0]
+    bool resume = false;
 };
 
 // Runs the CG loop from the state prepared by the caller (x, r, S with
 // tol2/maxit/done set; u = C^{-1} W^T r for subspace correction).  Returns the
-// number of completed iterations through *iters and the exit code in Sh->done.
+// number of iterations completed by this call through *iters and the exit
+// code in Sh->done.
 //
 // Deflation iterates with projected directions: after the preconditioner,
 // zhat = P z = z - W C^{-1} (AW)^T z and p = zhat + beta p in one pass, then
@@ -414,7 +418,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
         const int ns = launch_prec<T>(c, V, o.noprec, sc);
         if (defl) esd::launch_tsdot_rm(ta, gt, c->stream);
         esd::FinRho fr{};
-        fr.S = c->S; fr.part_sweep = c->part_sweep; fr.nsweep = ns; fr.init = 1;
+        fr.S = c->S; fr.part_sweep = c->part_sweep; fr.nsweep = ns; fr.init = o.resume ? 2 : 1;
+        fr.hist_beta = o.resume ? c->hb : nullptr;
         fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
         esd::launch_fin_rho(fr, c->stream);
         if (defl) {
@@ -507,9 +512,10 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
         }
         return hipGetLastError();
     };
+    const int iter0 = c->Sh->iter; // the caller's state, as put on the device
     auto harvest = [&](int launched, int chunk) {
         if (!timing) return;
-        const int executed = std::min(chunk, std::max(0, c->Sh->iter - launched));
+        const int executed = std::min(chunk, std::max(0, c->Sh->iter - iter0 - launched));
         for (int j = 0; j < executed; ++j) {
             float a = 0, b = 0, d = 0;
             (void)hipEventElapsedTime(&a, c->ev[4 * j + 0], c->ev[4 * j + 1]);
@@ -584,8 +590,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             if (!o.sync_every && chunk < 32) chunk *= 2;
         }
     }
-    *iters = c->Sh->iter;
-    *vbase = (*vbase + c->Sh->iter) & 1;
+    *iters = c->Sh->iter - iter0;
+    *vbase = (*vbase + *iters) & 1;
     return ESD_OK;
 }
 
@@ -869,6 +875,13 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     const bool method_b = sampling && c->samp_method == 1;
     if (method_b) arm_method_b(c, tol);
     double rn2 = 0.0, rn2_prev = -1.0;
+    // ESD_FLAG_MIXED_KEEP: a step that follows an inner run which reached its
+    // target replaces that run's residual by the new FP64 one and continues
+    // it (same search direction, same scale s_in of the inner quantities)
+    const bool keep = (flags & ESD_FLAG_MIXED_KEEP) != 0;
+    bool can_resume = false;
+    double s_in = 1.0;
+    int last_in = 0;
     c->segments.clear();
     for (outer = 0; outer <= c->max_outer; ++outer) {
         // FP64 true residual; deflation: coarse correction x += W C^{-1} W^T r
@@ -928,21 +941,38 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
             continue; // the next pass recomputes the FP64 residual and tests it
         }
         const double rn = std::sqrt(rn2);
-        esd::launch_cast_scale(n, c->r, c->r32, 1.0 / rn, c->stream);
+        const bool cont = keep && can_resume;
+        if (!cont) s_in = rn;
+        esd::launch_cast_scale(n, c->r, c->r32, 1.0 / s_in, c->stream);
         esd::launch_fill(n, c->d32, 0.0f, c->stream);
         // inner relative target: the refinement tolerance, or just what is still missing
         const double want = std::max(c->inner_tol, 0.3 * std::sqrt(tol2) / rn);
-        init_scal(c, maxit - total, c->vs32, c->stag_window);
-        c->Sh->tol2 = want * want;
-        c->Sh->bnorm2 = bn2;
-        c->Sh->hist_base = total;
-        c->Sh->sample_base = total;
-        c->Sh->xscale = rn;
-        if (method_b) put_method_b(c);
+        const double rel = rn / s_in; // ||r32||
+        if (cont) {
+            // the run's scalar block as the last synchronisation read it:
+            // iteration count, rho, beta, history and sampling offsets stay
+            Scal &S = *c->Sh;
+            S.done = 0;
+            S.tol2 = want * want * rel * rel;
+            S.maxit = S.iter + (maxit - total);
+            S.rr_ref = 1e300;
+            S.it_ref = S.iter;
+            // the run's last direction is in p[last_in & 1]; the next call reads it from p[0]
+            if (last_in & 1)
+                HIPCHK(hipMemcpyAsync(V.p[0], V.p[1], sizeof(float) * n, hipMemcpyDeviceToDevice, c->stream));
+        } else {
+            init_scal(c, maxit - total, c->vs32, c->stag_window);
+            c->Sh->tol2 = want * want;
+            c->Sh->bnorm2 = bn2;
+            c->Sh->hist_base = total;
+            c->Sh->sample_base = total;
+            c->Sh->xscale = rn;
+            if (method_b) put_method_b(c);
+        }
         st = put_scal(c);
         if (st) return st;
-        // u = C^{-1} W^T r / ||r|| for the first preconditioned inner residual
-        if (kind == 2) dev_tsdot(c, c->W, m, c->r, c->S->u, 1.0 / rn);
+        // u = C^{-1} W^T r / s_in for the first preconditioned inner residual
+        if (kind == 2) dev_tsdot(c, c->W, m, c->r, c->S->u, 1.0 / s_in);
         KrylovOpts o;
         o.kind = kind;
         o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
@@ -955,15 +985,19 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         o.timing = (flags & kFlagTiming) != 0;
         o.timing_all = (flags & ESD_FLAG_TIMING) != 0;
         o.xbase = c->x;
+        o.resume = cont;
         int it_in = 0;
         st = krylov<float>(c, V, o, &it_in, &c->vb32);
         if (st) return st;
         if (method_b) get_method_b(c);
         done_in = c->Sh->done;
-        c->segments.push_back({total, it_in});
+        if (cont) c->segments.back().second += it_in; // one Lanczos run
+        else c->segments.push_back({total, it_in});
         total += it_in;
         if (power) c->vs32 = c->Sh->vscale;
-        esd::launch_add_scaled(n, c->x, c->d32, rn, c->stream);
+        esd::launch_add_scaled(n, c->x, c->d32, s_in, c->stream);
+        can_resume = done_in == 1 && it_in >= 1;
+        last_in = it_in;
         if (done_in == 3) return fail(c, ESD_ENUMERIC, "non-finite value in the inner iteration");
     }
     dev_resid(c, c->b, c->x, c->t, nullptr, 0, nullptr, &c->S->out, 0);

@@ -184,7 +184,8 @@ struct FinRho {
     int nsweep;
     int rho_upd; // rho also takes column 1 of the update partials (level 0 fused there)
     double *hist_beta;
-    int init; // first preconditioner application of a solve: only rho
+    int init; // 1: first preconditioner application of a solve (only rho);
+              // 2: after a residual replacement (rho and beta of the new residual)
     const double *part_s; // (AW)^T z partials (deflated), nblk_s x stride_s
     int nblk_s, stride_s, m;
     const double *Cinv;

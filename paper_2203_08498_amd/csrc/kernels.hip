@@ -728,9 +728,21 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
     }
     if (t == 0) {
         const double rn = tot[2] + (f.rho_upd ? tot[1] : 0.0);
-        if (f.init) {
+        if (f.init == 1) {
             S->rho = rn;
             if (!isfinite(rn)) S->done = 3;
+            return;
+        }
+        if (f.init == 2) {
+            // residual replacement in a running iteration: the recurrence
+            // residual of iteration `iter` was replaced by the true one, so
+            // its rho and the beta that joins it to rho_{iter-1} follow the
+            // new residual (rho_{iter-1} = rho_old / beta_old)
+            const double b = rn * S->beta / rho_old;
+            S->beta = b;
+            S->rho = rn;
+            if (f.hist_beta && iter >= 1) f.hist_beta[hbase + iter - 1] = b;
+            if (!isfinite(b)) S->done = 3;
             return;
         }
         const double rr = tot[0];

@@ -418,6 +418,39 @@ def test_mixed_precision_meets_fp64_tolerance(case):
         assert _relerr(x, y) <= 1e-5
 
 
+def test_mixed_keep_continues_the_run(case):
+    """ESD_FLAG_MIXED_KEEP: every refinement step replaces the FP32 recurrence
+    residual by the FP64 true residual and continues the same CG run.  The
+    solve meets the FP64 tolerance, its alpha/beta history is one unbroken run
+    (as many coefficients as iterations, over several refinement steps), and
+    graph replays give the same result as stream launches."""
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    y, _ = o.solve(p.f, tol=1e-12, maxit=20000)
+    s.set_mixed_params(1e-2, 60)
+    try:
+        modes = [esd.PLAIN] + ([esd.DEFLATED, esd.SUBSPACE] if getattr(s, "m_tilde", 0) else [])
+        for mode in modes:
+            flags = esd.FLAG_MIXED | esd.FLAG_MIXED_KEEP
+            x, info = s.solve(p.f, tol=1e-8, maxit=20000, mode=mode, flags=flags)
+            a, b = s.history()
+            print(name, "keep mode", mode, "its", info["iters"], "outer", info["outer_iters"], "fp64",
+                  info["fp64_iters"], "relres", info["true_relres"], "err", _relerr(x, y), "kappa", info["kappa"],
+                  flush=True)
+            assert info["converged"] and info["true_relres"] <= 1e-8
+            assert _relerr(x, y) <= 1e-5
+            if info["fp64_iters"] == 0:
+                assert info["outer_iters"] >= 3
+                assert len(a) == info["iters"] and len(b) == info["iters"] - 1
+            xs, i_s = s.solve(p.f, tol=1e-8, maxit=20000, mode=mode, flags=flags | esd.FLAG_STREAM)
+            assert i_s["iters"] == info["iters"] and torch.equal(xs, x)
+    finally:
+        s.set_mixed_params(1e-4, 30)
+
+
 def test_graph_replays_match_stream_launches(case):
     """The captured 16-iteration chunks replay the same kernels with the same
     arguments as direct stream launches: results are bit-identical, also on a

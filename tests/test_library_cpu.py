@@ -42,6 +42,19 @@ def test_binding_covers_header(lib):
     assert L.esd_status_string(-2).decode().startswith("IC(0)")
 
 
+def test_binding_constants_match_header():
+    """Every mode, flag and status value of include/esd.h has the same value
+    in the binding (ESD_X -> esd.X)."""
+    from paper_2203_08498_amd import esd
+
+    src = open(HDR).read()
+    consts = dict(re.findall(r"#define ESD_([A-Z_0-9]+) (-?\d+)", src))
+    consts.update(re.findall(r"\bESD_([A-Z_0-9]+) = (-?\d+)", src))
+    assert len(consts) >= 25
+    for name, val in consts.items():
+        assert getattr(esd, name) == int(val), name
+
+
 def test_binding_argument_counts_match_header():
     """Every ctypes signature in the binding has as many parameters as the C
     declaration in include/esd.h."""
