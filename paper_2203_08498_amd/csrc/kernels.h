@@ -243,6 +243,13 @@ void launch_fwd(const Sweep<double> &a, bool last, bool sc, int grid, hipStream_
 void launch_fwd(const Sweep<float> &a, bool last, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
+// the same sweeps (forward: not the last level; both: no subspace correction)
+// with two rows per thread, for levels of more than kPairTiles tiles; the
+// grid covers half of the level's tiles
+void launch_fwd2(const Sweep<double> &a, int grid, hipStream_t s);
+void launch_fwd2(const Sweep<float> &a, int grid, hipStream_t s);
+void launch_bwd2(const Sweep<double> &a, int grid, hipStream_t s);
+void launch_bwd2(const Sweep<float> &a, int grid, hipStream_t s);
 // block-Jacobi z = M^{-1} r; returns the number of rho partials written (the
 // grid: at most kMaxGrid blocks, wavefronts loop over the Jacobi blocks)
 int bj_grid(int nb);
@@ -322,6 +329,11 @@ void launch_tsgemm(int n, const double *X, int ma, const double *T, int mb, doub
 // gradient with respect to stored values: g[k] = -lam[row k] x[col k] (user CSR)
 void launch_grad(int n, const int64_t *rowptr, const int32_t *col, const double *lam,
                  const double *x, double *g, hipStream_t s);
+
+// a level of more tiles than one round of resident wavefronts (8 per SIMD
+// on 256 CUs: 2048 blocks of kBlock threads) runs two rows per thread
+constexpr int kPairTiles = 2048;
+inline bool sweep_pairs(int64_t rows) { return (rows + kBlock - 1) / kBlock > kPairTiles; }
 
 inline int grid_for(int64_t rows) {
     int64_t g = (rows + kBlock - 1) / kBlock;

@@ -144,14 +144,14 @@ __device__ __forceinline__ void fin_colsum(const double *part, int nblk, int str
 // aligned layout: column = row + offset of the slot, clamped into [0, n]; a
 // row without an entry in a slot holds the value 0 there, so whatever finite
 // value the clamped column gathers is multiplied by zero.
-template <typename T>
-__device__ __forceinline__ void ell_chunk(const Ell<T> &M, int64_t base, int w, int k0, int i, int n, int (&c)[8],
-                                          T (&a)[8]) {
+template <typename T, int K = 8>
+__device__ __forceinline__ void ell_chunk(const Ell<T> &M, int64_t base, int w, int k0, int i, int n, int (&c)[K],
+                                          T (&a)[K]) {
     const int lane = i & 63;
     if (M.soff) {
-        int off[8];
+        int off[K];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < K; ++k) {
             if (k0 + k < w) {
                 a[k] = M.val[base + (int64_t)(k0 + k) * 64 + lane];
                 off[k] = M.soff[(base >> 6) + k0 + k];
@@ -161,10 +161,10 @@ __device__ __forceinline__ void ell_chunk(const Ell<T> &M, int64_t base, int w, 
             }
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) c[k] = min(max(i + off[k], 0), n);
+        for (int k = 0; k < K; ++k) c[k] = min(max(i + off[k], 0), n);
     } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < K; ++k) {
             if (k0 + k < w) {
                 const int64_t pos = base + (int64_t)(k0 + k) * 64 + lane;
                 a[k] = M.val[pos];
@@ -436,6 +436,109 @@ __global__ __launch_bounds__(kBlock, 8) void k_bwd(Sweep<T> a) {
         }
     }
     if constexpr (SC) block_partials<1>(acc, a.part, 1);
+}
+
+// Two rows per thread, from tiles t and t + 1 of the block's range: the slot
+// loads of both rows, then both gathers, then the products.  A wavefront has
+// twice the loads in flight, so a level with more tiles than one round of
+// resident wavefronts finishes in about one round of dependent round trips.
+// Each row's sum is formed as ell_dot forms it.  h0 / h1: the row exists.
+template <bool U, typename T, typename G>
+__device__ __forceinline__ void ell_dot_pair(const Ell<T> &M, int i0, bool h0, int i1, bool h1, int n, G g, T &s0,
+                                             T &s1) {
+    int64_t b0 = 0, b1 = 0;
+    int w0 = 0, w1 = 0;
+    if (h0) ell_slice<U>(M, i0, b0, w0);
+    if (h1) ell_slice<U>(M, i1, b1, w1);
+    s0 = T(0);
+    s1 = T(0);
+    // chunks of 4 slots (the sweeps' triangles are narrow) keep both rows
+    // within the 64 registers of 8 wavefronts per SIMD
+    constexpr int K = 4;
+    const int w = max(w0, w1);
+    for (int k0 = 0; k0 < w; k0 += K) {
+        int c0[K], c1[K];
+        T a0[K], a1[K];
+        ell_chunk<T, K>(M, b0, w0, k0, i0, n, c0, a0); // w0 = 0: value 0, column n
+        ell_chunk<T, K>(M, b1, w1, k0, i1, n, c1, a1);
+        T v0[K], v1[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v0[k] = g(c0[k]);
+            v1[k] = g(c1[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            s0 += a0[k] * v0[k];
+            s1 += a1[k] * v1[k];
+        }
+    }
+}
+
+// rows i0 (tile t) and i1 (tile t + 1, if the range has it) of the thread
+struct RowPair {
+    int i0, i1;
+    bool h0, h1;
+};
+template <typename T> __device__ __forceinline__ RowPair row_pair(const Sweep<T> &a, int t, int t1) {
+    RowPair q;
+    q.i0 = a.r0 + (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
+    q.i1 = (t + 1 < t1) ? a.r0 + (a.tmap ? a.tmap[t + 1] : t + 1) * kBlock + threadIdx.x : a.r1;
+    q.h0 = q.i0 < a.r1;
+    q.h1 = q.i1 < a.r1;
+    return q;
+}
+
+// forward sweep of a level that is neither the last one nor under subspace
+// correction, two rows per thread (same arithmetic per row as k_fwd); 6
+// wavefronts per SIMD (at most 80 registers) hold 12 rows' loads in flight
+template <typename T>
+__global__ __launch_bounds__(kBlock, 6) void k_fwd2(Sweep<T> a) {
+    if (a.S->done) return;
+    double acc[1] = {0.0};
+    const T *y = a.y;
+    const bool aligned = (a.r0 & 63) == 0;
+    const Tiles tl = my_tiles(a.r1 - a.r0);
+    const auto gy = [&](int c) { return y[c]; };
+    for (int t = tl.t0; t < tl.t1; t += 2) {
+        const RowPair q = row_pair(a, t, tl.t1);
+        const T ri0 = q.h0 ? a.r[q.i0] : T(0), ri1 = q.h1 ? a.r[q.i1] : T(0);
+        const T d0 = q.h0 ? a.dinv[q.i0] : T(0), d1 = q.h1 ? a.dinv[q.i1] : T(0);
+        T s0, s1;
+        if (aligned) ell_dot_pair<true>(a.M, q.i0, q.h0, q.i1, q.h1, a.n, gy, s0, s1);
+        else ell_dot_pair<false>(a.M, q.i0, q.h0, q.i1, q.h1, a.n, gy, s0, s1);
+        if (q.h0) {
+            const T yi = (ri0 - s0) * d0;
+            a.y[q.i0] = yi;
+            acc[0] += (double)yi * (double)yi;
+        }
+        if (q.h1) {
+            const T yi = (ri1 - s1) * d1;
+            a.y[q.i1] = yi;
+            acc[0] += (double)yi * (double)yi;
+        }
+    }
+    block_partials<1>(acc, a.part, 1);
+}
+
+// backward sweep of a level without subspace correction, two rows per thread
+template <typename T>
+__global__ __launch_bounds__(kBlock, 6) void k_bwd2(Sweep<T> a) {
+    if (a.S->done) return;
+    const T *z = a.z;
+    const bool aligned = (a.r0 & 63) == 0;
+    const Tiles tl = my_tiles(a.r1 - a.r0);
+    const auto gz = [&](int c) { return z[c]; };
+    for (int t = tl.t0; t < tl.t1; t += 2) {
+        const RowPair q = row_pair(a, t, tl.t1);
+        const T y0 = q.h0 ? a.y[q.i0] : T(0), y1 = q.h1 ? a.y[q.i1] : T(0);
+        const T d0 = q.h0 ? a.dinv[q.i0] : T(0), d1 = q.h1 ? a.dinv[q.i1] : T(0);
+        T s0, s1;
+        if (aligned) ell_dot_pair<true>(a.M, q.i0, q.h0, q.i1, q.h1, a.n, gz, s0, s1);
+        else ell_dot_pair<false>(a.M, q.i0, q.h0, q.i1, q.h1, a.n, gz, s0, s1);
+        if (q.h0) a.z[q.i0] = (y0 - s0) * d0;
+        if (q.h1) a.z[q.i1] = (y1 - s1) * d1;
+    }
 }
 
 // Block-Jacobi z = M^{-1} r with tridiagonal blocks, one wavefront per block,
@@ -1365,6 +1468,10 @@ template <typename T> static void bwd_impl(const Sweep<T> &a, bool sc, int grid,
 }
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
+void launch_fwd2(const Sweep<double> &a, int grid, hipStream_t s) { k_fwd2<double><<<grid, kBlock, 0, s>>>(a); }
+void launch_fwd2(const Sweep<float> &a, int grid, hipStream_t s) { k_fwd2<float><<<grid, kBlock, 0, s>>>(a); }
+void launch_bwd2(const Sweep<double> &a, int grid, hipStream_t s) { k_bwd2<double><<<grid, kBlock, 0, s>>>(a); }
+void launch_bwd2(const Sweep<float> &a, int grid, hipStream_t s) { k_bwd2<float><<<grid, kBlock, 0, s>>>(a); }
 
 int bj_grid(int nb) { return std::min(kMaxGrid, (nb + kBlock / 64 - 1) / (kBlock / 64)); }
 
