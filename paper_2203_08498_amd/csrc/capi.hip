@@ -530,57 +530,82 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             c->t_spmv += a; c->t_upd += b; c->t_sweep += d; c->t_count++;
         }
     };
-    constexpr int kChunk = 16;
-    hipGraphExec_t ex = nullptr;
-    bool known = false;
-    // kernel timing reads hipEvents recorded between stream launches (events
-    // recorded as graph nodes give no elapsed time): timing solves stay off graphs
-    if (c->use_graphs && !o.sync_every && !o.stream_only && !timing) {
-        const uint32_t key = (sizeof(T) == 4 ? 1u : 0u) | ((uint32_t)o.kind << 1) | ((uint32_t)o.noprec << 3) |
-                             ((uint32_t)o.power << 4) | ((uint32_t)o.sampling << 5) | ((uint32_t)(*vbase & 1) << 6) |
-                             ((uint32_t)fuse_l0 << 7) | ((uint32_t)o.resid << 8) | ((uint32_t)o.method_b << 9);
+    // 16-iteration chunks; once the residual's recent rate predicts the end
+    // within 12 iterations, 4-iteration chunks, so that fewer launches of a
+    // chunk run (and return at once) after the stop
+    constexpr int kChunk = 16, kTail = 4;
+    const uint32_t key0 = (sizeof(T) == 4 ? 1u : 0u) | ((uint32_t)o.kind << 1) | ((uint32_t)o.noprec << 3) |
+                          ((uint32_t)o.power << 4) | ((uint32_t)o.sampling << 5) | ((uint32_t)(*vbase & 1) << 6) |
+                          ((uint32_t)fuse_l0 << 7) | ((uint32_t)o.resid << 8) | ((uint32_t)o.method_b << 9);
+    // the cached graph of `count` iterations of this variant (nullptr: the
+    // variant does not capture, stream launches for it)
+    auto graph_for = [&](int count) -> hipGraphExec_t {
+        const uint32_t key = key0 | ((uint32_t)(count == kTail) << 10);
         for (auto &g : c->graphs)
-            if (g.key == key && g.epoch == c->epoch) { ex = g.exec; known = true; }
-        if (!known && !c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+            if (g.key == key && g.epoch == c->epoch) return g.exec;
+        if (!c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
             c->cap = nullptr;
             c->use_graphs = false;
+            return nullptr;
         }
-        if (!known && c->cap) {
-            // capture on the private stream (the caller's may be the null
-            // stream, which cannot be captured); replays go to the caller's
-            hipGraph_t graph = nullptr;
-            hipStream_t user = c->stream;
-            c->stream = c->cap;
-            bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
-            if (ok) {
-                const hipError_t eb = body(0, kChunk);
-                const hipError_t ee = hipStreamEndCapture(c->stream, &graph);
-                ok = eb == hipSuccess && ee == hipSuccess && graph;
+        // capture on the private stream (the caller's may be the null
+        // stream, which cannot be captured); replays go to the caller's
+        hipGraphExec_t ex = nullptr;
+        hipGraph_t graph = nullptr;
+        hipStream_t user = c->stream;
+        c->stream = c->cap;
+        bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+        if (ok) {
+            const hipError_t eb = body(0, count);
+            const hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+            ok = eb == hipSuccess && ee == hipSuccess && graph;
+        }
+        c->stream = user;
+        if (ok) ok = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        if (!ok) ex = nullptr;
+        for (auto it = c->graphs.begin(); it != c->graphs.end();)
+            if (it->key == key) {
+                if (it->exec) (void)hipGraphExecDestroy(it->exec);
+                it = c->graphs.erase(it);
+            } else {
+                ++it;
             }
-            c->stream = user;
-            if (ok) ok = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) == hipSuccess;
-            if (graph) (void)hipGraphDestroy(graph);
-            (void)hipGetLastError();
-            if (!ok) ex = nullptr; // this variant does not capture: stream launches for it
-            for (auto it = c->graphs.begin(); it != c->graphs.end();)
-                if (it->key == key) {
-                    if (it->exec) (void)hipGraphExecDestroy(it->exec);
-                    it = c->graphs.erase(it);
-                } else {
-                    ++it;
-                }
-            c->graphs.push_back({key, c->epoch, ex});
-        }
-    }
+        c->graphs.push_back({key, c->epoch, ex});
+        return ex;
+    };
+    // kernel timing reads hipEvents recorded between stream launches (events
+    // recorded as graph nodes give no elapsed time): timing solves stay off graphs
+    hipGraphExec_t ex = nullptr;
+    if (c->use_graphs && !o.sync_every && !o.stream_only && !timing) ex = graph_for(kChunk);
     int launched = 0;
     if (ex) {
+        hipGraphExec_t tail = nullptr;
+        bool tail_tried = false;
+        int chunk = kChunk;
+        double rr_prev = -1.0;
         for (;;) {
-            HIPCHK(hipGraphLaunch(ex, c->stream));
+            HIPCHK(hipGraphLaunch(chunk == kChunk ? ex : tail, c->stream));
             esd_status st = sync_read(c);
             if (st != ESD_OK) return st;
-            harvest(launched, kChunk);
-            launched += kChunk;
+            harvest(launched, chunk);
+            launched += chunk;
             if (c->Sh->done) break;
+            if (chunk == kChunk) {
+                const double rr = c->Sh->rr, t2 = c->Sh->tol2;
+                if (rr_prev > 0.0 && rr > t2 && rr < rr_prev) {
+                    const double need = std::log(t2 / rr) / (std::log(rr / rr_prev) / kChunk);
+                    if (need < 12.0) {
+                        if (!tail_tried) {
+                            tail = graph_for(kTail);
+                            tail_tried = true;
+                        }
+                        if (tail) chunk = kTail;
+                    }
+                }
+                rr_prev = rr;
+            }
         }
     } else {
         int chunk = o.sync_every ? 1 : 8;
