@@ -73,7 +73,8 @@ typedef enum {
 #define ESD_FLAG_TRUE_RES 64  /* FP64: after the recurrence test, restart from x while the recomputed
                                  residual misses tol (at most 4 restarts) */
 #define ESD_FLAG_STREAM 128   /* launch every kernel on the stream; by default the iterations run as
-                                 replays of a captured 16-iteration HIP graph, cached in the context
+                                 replays of captured 16- and 4-iteration HIP graphs (the short one
+                                 near the stop the residual's rate predicts), cached in the context
                                  (solves with ESD_FLAG_TIMING, ESD_FLAG_TIMING_SPMV or
                                  ESD_FLAG_SYNC_EVERY always use stream launches) */
 #define ESD_FLAG_MIXED_KEEP 256 /* with ESD_FLAG_MIXED: a refinement step whose inner run reached its
