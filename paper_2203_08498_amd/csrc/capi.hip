@@ -411,7 +411,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     const bool sc = (o.kind == 2), defl = (o.kind == 1);
     const int gt = m > 0 ? esd::tsdot_grid(n, m) : 1;
     const int st_t = m > 0 ? esd::tsdot_stride(m) : 1;
-    const int gn = esd::grid_red(n, 1);
+    const int gn = esd::stream_grid<T>(n);
     // tall-skinny (AW)^T z (deflation) or W^T r (subspace correction)
     esd::TsDot<T> ta{};
     ta.n = n; ta.m = m; ta.Wrm = defl ? V.AWrm : V.Wrm; ta.v = defl ? V.z : V.r; ta.part = c->part_ts; ta.S = c->S;
@@ -434,7 +434,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     }
     const int sstride = esd::spmv_stride(o.power);
     const int gs = esd::grid_red(n, sstride);
-    const int gu = esd::grid_red(n, 1);
+    const int gu = esd::stream_grid<T>(n); // update launches and their partial rows
     const int nl = (int)c->lvl.size() - 1;
     const bool fuse_l0 = !o.noprec && nl >= 2;
     // block Jacobi without subspace correction: the update kernel also applies

@@ -335,6 +335,16 @@ void launch_grad(int n, const int64_t *rowptr, const int32_t *col, const double 
 constexpr int kPairTiles = 2048;
 inline bool sweep_pairs(int64_t rows) { return (rows + kBlock - 1) / kBlock > kPairTiles; }
 
+// FP32 update (plain / projected form) and projection launches (m <= 16)
+// over more than kPairTiles tiles run two rows per thread; stream_grid is
+// the grid (and partial count) of such a launch
+template <typename T> inline bool stream_pairs(int64_t rows) {
+    return sizeof(T) == 4 && (rows + kBlock - 1) / kBlock > kPairTiles;
+}
+template <typename T> inline int stream_grid(int64_t rows) {
+    return grid_red(stream_pairs<T>(rows) ? (rows + 1) / 2 : rows, 1);
+}
+
 inline int grid_for(int64_t rows) {
     int64_t g = (rows + kBlock - 1) / kBlock;
     if (g > kMaxGrid) g = kMaxGrid;

@@ -325,6 +325,51 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
     block_partials<2>(acc, a.part, 2);
 }
 
+// FP32 vector update (plain / projected form) with two rows per thread, tiles
+// t and t + 1 of the block's range: all loads of both rows first.  A 4-byte
+// row moves half the bytes of an FP64 one per load instruction, so one row
+// per thread leaves the FP32 streams short of loads in flight.  Same
+// arithmetic per row as k_update_it<T, MT, 0>.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_it2(UpdIt<T> a) {
+    Scal *S = a.S;
+    if (S->done) return;
+    const T ta = (T)S->alpha;
+    double acc[2] = {0.0, 0.0};
+    const int n = a.n;
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; t += 2) {
+        int i[2];
+        bool h[2];
+        T qv[2], pv[2], xv[2], rv[2], dv[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int tt = t + u;
+            i[u] = tt < tl.t1 ? (a.tmap ? a.tmap[tt] : tt) * kBlock + threadIdx.x : n;
+            h[u] = i[u] < n;
+            qv[u] = h[u] ? a.q[i[u]] : T(0);
+            pv[u] = h[u] ? a.p[i[u]] : T(0);
+            xv[u] = h[u] ? a.x[i[u]] : T(0);
+            rv[u] = h[u] ? a.r[i[u]] : T(0);
+            dv[u] = (h[u] && i[u] < a.l0) ? a.dinv[i[u]] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!h[u]) continue;
+            a.x[i[u]] = xv[u] + ta * pv[u];
+            const T ri = rv[u] - ta * qv[u];
+            a.r[i[u]] = ri;
+            acc[0] += (double)ri * (double)ri;
+            if (i[u] < a.l0) {
+                const T yi = ri * dv[u];
+                a.y[i[u]] = yi;
+                acc[1] += (double)yi * (double)yi;
+            }
+        }
+    }
+    block_partials<2>(acc, a.part, 2);
+}
+
 // s = W^T v, W row-major n x m; P = next power of two >= m.  Lane l of a
 // wavefront takes column l % P of rows l / P, l / P + 64 / P, ...; blocks of
 // kTsBlock threads keep the partial table (one row of P per block) short.
@@ -915,6 +960,46 @@ __global__ __launch_bounds__(kBlock) void k_proj(Proj<T> a) {
     }
 }
 
+// FP32 projection with two rows per thread (tiles t and t + 1), all loads of
+// both rows first; same arithmetic per row as k_proj
+template <typename T, int MT>
+__global__ __launch_bounds__(kBlock) void k_proj2(Proj<T> a) {
+    const Scal *S = a.S;
+    if (S->done) return;
+    const bool first = (S->iter == 0);
+    const T beta = first ? T(0) : (T)S->beta;
+    double mu[MT];
+#pragma unroll
+    for (int k = 0; k < MT; ++k) mu[k] = (k < a.m) ? S->mu[k] : 0.0;
+    const int n = a.n;
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; t += 2) {
+        int i[2];
+        bool h[2];
+        T zv[2], pv[2], wv[2][MT];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int tt = t + u;
+            i[u] = tt < tl.t1 ? (a.tmap ? a.tmap[tt] : tt) * kBlock + threadIdx.x : n;
+            h[u] = i[u] < n;
+            zv[u] = h[u] ? a.z[i[u]] : T(0);
+            pv[u] = (h[u] && !first) ? a.pold[i[u]] : T(0);
+#pragma unroll
+            for (int k = 0; k < MT; ++k) wv[u][k] = (h[u] && k < a.m) ? a.W[(size_t)k * n + i[u]] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!h[u]) continue;
+            double s = (double)zv[u];
+#pragma unroll
+            for (int k = 0; k < MT; ++k)
+                if (k < a.m) s -= (double)wv[u][k] * mu[k];
+            const T zh = (T)s;
+            a.pnew[i[u]] = first ? zh : zh + beta * pv[u];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kFinThreads) void k_fin_gen(FinGen f) {
     Scal *S = f.S;
     __shared__ double tot[kMaxNV];
@@ -1422,7 +1507,9 @@ void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s
 void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 
 template <typename T> static void update_it_impl(const UpdIt<T> &a, int kind, int grid, hipStream_t s) {
-    if (kind == 1) {
+    if (kind == 0 && stream_pairs<T>(a.n)) {
+        k_update_it2<T><<<grid, kBlock, 0, s>>>(a);
+    } else if (kind == 1) {
         ESD_MT_SWITCH(a.m, (k_update_it<T, (MTV > 0 ? MTV : 8), 1><<<grid, kBlock, 0, s>>>(a)));
     } else {
         k_update_it<T, 0, 0><<<grid, kBlock, 0, s>>>(a);
@@ -1432,6 +1519,11 @@ void launch_update_it(const UpdIt<double> &a, int kind, int grid, hipStream_t s)
 void launch_update_it(const UpdIt<float> &a, int kind, int grid, hipStream_t s) { update_it_impl(a, kind, grid, s); }
 
 template <typename T> static void proj_impl(const Proj<T> &a, int grid, hipStream_t s) {
+    if (stream_pairs<T>(a.n) && a.m <= 16) {
+        if (a.m <= 8) k_proj2<T, 8><<<grid, kBlock, 0, s>>>(a);
+        else k_proj2<T, 16><<<grid, kBlock, 0, s>>>(a);
+        return;
+    }
     ESD_MT_SWITCH(a.m, (k_proj<T, (MTV > 0 ? MTV : 8)><<<grid, kBlock, 0, s>>>(a)));
 }
 void launch_proj(const Proj<double> &a, int grid, hipStream_t s) { proj_impl(a, grid, s); }
