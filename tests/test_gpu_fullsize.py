@@ -94,6 +94,22 @@ def test_config2_full_parity_sampling_build_deflated():
     assert i4["true_relres"] <= 1.01e-8
     # regression guard: measured 3.1e-10 at this size (the kappa bound is far looser)
     assert _relerr(x4, y2) <= 1e-7
+    # residual replacement (one continued FP32 run) on the same system, both forms
+    _, i6 = s.solve(b2, tol=1e-8, maxit=20000, mode=esd.PLAIN)
+    fp64_its = {esd.DEFLATED: i2["iters"], esd.PLAIN: i6["iters"]}
+    s.set_mixed_params(1e-2, 60)
+    for mode in (esd.DEFLATED, esd.PLAIN):
+        x5, i5 = s.solve(b2, tol=1e-8, maxit=20000, mode=mode, flags=esd.FLAG_MIXED | esd.FLAG_MIXED_KEEP)
+        a5, _ = s.history()
+        print("mixed keep mode", mode, "its", i5["iters"], "outer", i5["outer_iters"], "fp64 its", i5["fp64_iters"],
+              "relres", i5["true_relres"], "err vs FP64 oracle", _relerr(x5, y2), flush=True)
+        assert i5["true_relres"] <= 1.01e-8 and i5["fp64_iters"] == 0
+        assert _relerr(x5, y2) <= 1e-7
+        # one CG run across the refinement steps, within 20% of the FP64 iteration count
+        # (measured 1.11x deflated, 1.10x plain; restarted refinement takes 1.31x)
+        assert len(a5) == i5["iters"] and i5["outer_iters"] >= 3
+        assert i5["iters"] <= 1.2 * fp64_its[mode] + 10
+    s.set_mixed_params()
     s.close()
 
 
