@@ -113,6 +113,67 @@ def test_config2_full_parity_sampling_build_deflated():
     s.close()
 
 
+def test_config1_sequence_as_specified():
+    """Config 1 as specified: 64 x 64 FV cells with four 8 x 8 squares of
+    coefficient 1e-4, natural order, IC(0); system 1 samples m = 8 error
+    vectors with the power iteration, build_aux at theta = 1e-2 and 1e-3, then
+    systems 2-4 (b_k = f + 0.1 x_{k-1}) deflated.  Per system against the
+    oracle given the same b: iterations within 2, solution to 1e-10, kappa_es
+    to 1e-6; m_tilde equal (none selected at 1e-3, where the smallest Ritz
+    value lies above theta).  Each side builds W from its own samples, which
+    differ by the rounding of the two sampling solves amplified through
+    e = x_N - x_i, so kappa_cg of the deflated iteration is compared at
+    matched iterations with an oracle given the GPU's W (same operator): 1e-6."""
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    p = P.config1()
+    v0 = P.power_start(1, p.n)
+    for theta in p.params["theta"]:
+        s = esd.Solver.from_problem(p, m_max=8)
+        s.factor_ic0()
+        s.set_power_start(v0)
+        o = O.Oracle.from_problem(p)
+        assert o.factor_ic0() == 0
+        o.set_power_start(v0)
+        s.sample_errors(8)
+        o.arm_sampling(8)
+        x, i1 = s.solve(torch.as_tensor(p.f, device="cuda"), tol=1e-8, maxit=5000, flags=esd.FLAG_POWER)
+        y, j1 = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE | O.POWER)
+        samples = o.samples(8)
+        assert i1["iters"] == j1.iters and np.array_equal(s.samples(8), samples)
+        assert _relerr(x, y) <= 1e-10
+        st, ritz, mb, mt = s.build_aux(theta)
+        ost, oritz, omb, omt = o.build_aux(theta)
+        print("theta", theta, "system 1 its", i1["iters"], "m_bar", mb, "m_tilde", mt, omt, "ritz", ritz[:4],
+              "max rel ritz diff", np.max(np.abs(ritz - oritz) / oritz), flush=True)
+        assert (mb, mt) == (omb, omt)
+        # the oracle with the GPU's W: the same deflated operator
+        ow = O.Oracle.from_problem(p)
+        assert ow.factor_ic0() == 0
+        if mt:
+            ow.set_aux(s.get_aux()[0].cpu().numpy())
+        if theta == 1e-3:
+            assert mt == 0 and ritz.min() > 1e-3
+        else:
+            assert mt > 0
+        for k in range(2, 5):
+            b = P.sequence_rhs(p.f, y)
+            x, info = s.solve(torch.as_tensor(b, device="cuda"), tol=1e-8, maxit=5000, mode=esd.DEFLATED)
+            y, oi = o.solve(b, tol=1e-8, maxit=5000, mode=O.DEFLATED)
+            _, om = ow.solve(b, tol=0.0, maxit=info["iters"], mode=O.DEFLATED if mt else O.PLAIN)
+            print("theta", theta, "system", k, "its", info["iters"], oi.iters, "kappa_cg", info["kappa"],
+                  "kappa_es", info["kappa_es"], j1.lambda_max / oritz.min(), "mode used", info["mode_used"], flush=True)
+            assert abs(info["iters"] - oi.iters) <= 2 and _relerr(x, y) <= 1e-10
+            assert info["true_relres"] <= 1.01e-8
+            assert info["mode_used"] == (esd.DEFLATED if mt else esd.PLAIN)
+            assert abs(info["kappa"] / om.kappa - 1) <= 1e-6
+            # K2: lambda_max of system 1's power iteration over the smallest Ritz value
+            assert abs(info["kappa_es"] / (j1.lambda_max / oritz.min()) - 1) <= 1e-6
+        s.close()
+
+
 def _fp64_floor(p, x, b):
     """Attainable relative residual of any FP64 solve: b - A x itself is only
     known to about gamma_k ||(|A| |x|)|| with k = the longest row (rounding
