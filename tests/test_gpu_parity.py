@@ -646,6 +646,41 @@ def test_errors_and_fallbacks():
     s2.close()
 
 
+@pytest.mark.parametrize("k", [12, 24, 48])
+def test_wide_aux_space_against_oracle(k):
+    """W of 12, 24 and 48 columns (the 16-, 32- and 64-wide kernel variants of
+    the projection, the tall-skinny products and the finalize): the k lowest
+    eigenvectors of A given to both sides; deflated and subspace-corrected
+    ICCG against the oracle (iterations within 2, solutions 1e-10, kappa at
+    matched iterations 1e-6), and the mixed deflated solve to relres 1e-8."""
+    from paper_2203_08498_amd import esd
+
+    p = P.config1(N=40, nbox=2, box=6)
+    A = np.zeros((p.n, p.n))
+    for i in range(p.n):
+        A[i, p.col[p.rowptr[i]:p.rowptr[i + 1]]] = p.val[p.rowptr[i]:p.rowptr[i + 1]]
+    lam, V = np.linalg.eigh(A)
+    W = np.ascontiguousarray(V[:, :k])
+    s = _solver(p, m_max=64)
+    s.factor_ic0()
+    o = _oracle(p)
+    s.set_aux(W)
+    o.set_aux(W)
+    for mode, omode in ((esd.DEFLATED, O.DEFLATED), (esd.SUBSPACE, O.SUBSPACE)):
+        x, info = s.solve(p.f, tol=1e-8, maxit=5000, mode=mode)
+        y, oi = o.solve(p.f, tol=1e-8, maxit=5000, mode=omode)
+        _, om = o.solve(p.f, tol=0.0, maxit=info["iters"], mode=omode)
+        print("k", k, "mode", mode, "its", info["iters"], oi.iters, "m_tilde", info["m_tilde"], "kappa", info["kappa"],
+              om.kappa, flush=True)
+        assert info["m_tilde"] == k and info["mode_used"] == mode
+        assert abs(info["iters"] - oi.iters) <= 2 and _relerr(x, y) <= 1e-10
+        assert info["true_relres"] <= 1.01e-8
+        assert abs(info["kappa"] / om.kappa - 1) <= 1e-6
+    x, info = s.solve(p.f, tol=1e-8, maxit=20000, mode=esd.DEFLATED, flags=esd.FLAG_MIXED)
+    assert info["converged"] and info["true_relres"] <= 1e-8 and _relerr(x, y) <= 1e-5
+    s.close()
+
+
 def test_exact_eigenvectors_closed_form_on_gpu():
     """Deflating exact Poisson eigenvectors (M = I) leaves kappa = lambda_max / lambda_{k+1}."""
     from paper_2203_08498_amd import esd
