@@ -200,6 +200,39 @@ def _full_kernel_parity(p, s, o):
     assert _relerr(s.prec(x), o.prec(x)) <= 1e-11
 
 
+def test_two_row_kernels_on_ragged_levels():
+    """131^3 (odd): the colour levels (about 843 K rows, 3294 tiles) take the
+    two-rows-per-thread sweeps and FP32 streams and end in partial tiles.
+    SpMV, factor and M^{-1} r against the oracle; 40 matched FP64 deflated
+    iterations with a seeded orthonormal W; the FP32/FP64 mixed deflated solve
+    (two-row FP32 update and projection) to relres 1e-8 against the oracle's
+    FP64 deflated solution."""
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    p = P.config2(N=131, nsph=4, systems=2)
+    s = esd.Solver.from_problem(p, m_max=8)
+    s.factor_ic0()
+    o = O.Oracle.from_problem(p)
+    _full_kernel_parity(p, s, o)
+    W, _ = np.linalg.qr(np.random.default_rng(8).standard_normal((p.n, 6)))
+    s.set_aux(W)
+    o.set_aux(W)
+    x, info = s.solve(torch.as_tensor(p.f, device="cuda"), tol=0.0, maxit=40, mode=esd.DEFLATED)
+    y, oi = o.solve(p.f, tol=0.0, maxit=40, mode=O.DEFLATED)
+    print("131^3 deflated 40 its: err", _relerr(x, y), "kappa", info["kappa"], oi.kappa, flush=True)
+    assert info["iters"] == oi.iters == 40 and _relerr(x, y) <= 1e-10
+    assert abs(info["kappa"] / oi.kappa - 1) <= 1e-6
+    y8, oi8 = o.solve(p.f, tol=1e-8, maxit=20000, mode=O.DEFLATED)
+    x8, i8 = s.solve(torch.as_tensor(p.f, device="cuda"), tol=1e-8, maxit=20000, mode=esd.DEFLATED,
+                     flags=esd.FLAG_MIXED)
+    print("131^3 mixed deflated its", i8["iters"], "relres", i8["true_relres"], "err vs oracle", _relerr(x8, y8),
+          "oracle its", oi8.iters, flush=True)
+    assert i8["converged"] and i8["true_relres"] <= 1e-8 and _relerr(x8, y8) <= 1e-7
+    s.close()
+
+
 @pytest.mark.parametrize("which", ["cfg3_256", "cfg4_q1_160"])
 def test_large_configs_kernels_and_mixed_deflated(which):
     import torch
