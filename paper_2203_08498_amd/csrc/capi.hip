@@ -287,10 +287,10 @@ int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_
         s.r0 = (int)c->lvl[l]; s.r1 = (int)c->lvl[l + 1];
         s.tmap = c->tmap_lvl + c->tmap_off[l];
         const bool last = (l == nl - 1);
-        const bool pair = !last && !sc && esd::sweep_pairs(s.r1 - s.r0);
+        const bool pair = !last && esd::sweep_pairs(s.r1 - s.r0);
         const int g = esd::grid_red(pair ? (s.r1 - s.r0 + 1) / 2 : s.r1 - s.r0, 1);
         s.part = c->part_sweep + off;
-        if (pair) esd::launch_fwd2(s, g, c->stream);
+        if (pair) esd::launch_fwd2(s, sc, g, c->stream);
         else esd::launch_fwd(s, last, sc, g, c->stream);
         if (last || !sc) off += g;
     }
@@ -298,10 +298,10 @@ int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_
     for (int l = nl - 2; l >= 0; --l) {
         s.r0 = (int)c->lvl[l]; s.r1 = (int)c->lvl[l + 1];
         s.tmap = c->tmap_lvl + c->tmap_off[l];
-        const bool pair = !sc && esd::sweep_pairs(s.r1 - s.r0);
+        const bool pair = esd::sweep_pairs(s.r1 - s.r0);
         const int g = esd::grid_red(pair ? (s.r1 - s.r0 + 1) / 2 : s.r1 - s.r0, 1);
         s.part = c->part_sweep + off;
-        if (pair) esd::launch_bwd2(s, g, c->stream);
+        if (pair) esd::launch_bwd2(s, sc, g, c->stream);
         else esd::launch_bwd(s, sc, g, c->stream);
         if (sc) off += g;
     }

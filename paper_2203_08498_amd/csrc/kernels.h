@@ -243,13 +243,13 @@ void launch_fwd(const Sweep<double> &a, bool last, bool sc, int grid, hipStream_
 void launch_fwd(const Sweep<float> &a, bool last, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
-// the same sweeps (forward: not the last level; both: no subspace correction)
-// with two rows per thread, for levels of more than kPairTiles tiles; the
-// grid covers half of the level's tiles
-void launch_fwd2(const Sweep<double> &a, int grid, hipStream_t s);
-void launch_fwd2(const Sweep<float> &a, int grid, hipStream_t s);
-void launch_bwd2(const Sweep<double> &a, int grid, hipStream_t s);
-void launch_bwd2(const Sweep<float> &a, int grid, hipStream_t s);
+// the same sweeps (forward: not the last level) with two rows per thread,
+// for levels of more than kPairTiles tiles; the grid covers half of the
+// level's tiles
+void launch_fwd2(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
+void launch_fwd2(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
+void launch_bwd2(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
+void launch_bwd2(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
 // block-Jacobi z = M^{-1} r; returns the number of rho partials written (the
 // grid: at most kMaxGrid blocks, wavefronts loop over the Jacobi blocks)
 int bj_grid(int nb);

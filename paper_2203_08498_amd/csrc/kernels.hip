@@ -534,10 +534,11 @@ template <typename T> __device__ __forceinline__ RowPair row_pair(const Sweep<T>
     return q;
 }
 
-// forward sweep of a level that is neither the last one nor under subspace
-// correction, two rows per thread (same arithmetic per row as k_fwd); 6
-// wavefronts per SIMD (at most 80 registers) hold 12 rows' loads in flight
-template <typename T>
+// forward sweep of a level that is not the last one, two rows per thread
+// (same arithmetic per row as k_fwd); RHO: reduce ||y||^2 (rho without
+// subspace correction).  6 wavefronts per SIMD (at most 80 registers) hold
+// 12 rows' loads in flight
+template <typename T, bool RHO>
 __global__ __launch_bounds__(kBlock, 6) void k_fwd2(Sweep<T> a) {
     if (a.S->done) return;
     double acc[1] = {0.0};
@@ -555,21 +556,23 @@ __global__ __launch_bounds__(kBlock, 6) void k_fwd2(Sweep<T> a) {
         if (q.h0) {
             const T yi = (ri0 - s0) * d0;
             a.y[q.i0] = yi;
-            acc[0] += (double)yi * (double)yi;
+            if constexpr (RHO) acc[0] += (double)yi * (double)yi;
         }
         if (q.h1) {
             const T yi = (ri1 - s1) * d1;
             a.y[q.i1] = yi;
-            acc[0] += (double)yi * (double)yi;
+            if constexpr (RHO) acc[0] += (double)yi * (double)yi;
         }
     }
-    block_partials<1>(acc, a.part, 1);
+    if constexpr (RHO) block_partials<1>(acc, a.part, 1);
 }
 
-// backward sweep of a level without subspace correction, two rows per thread
-template <typename T>
+// backward sweep of a level, two rows per thread (same arithmetic per row as
+// k_bwd); SC: subspace correction, z + W u and rho = (r, z + W u) as in k_bwd
+template <typename T, bool SC>
 __global__ __launch_bounds__(kBlock, 6) void k_bwd2(Sweep<T> a) {
     if (a.S->done) return;
+    double acc[1] = {0.0};
     const T *z = a.z;
     const bool aligned = (a.r0 & 63) == 0;
     const Tiles tl = my_tiles(a.r1 - a.r0);
@@ -581,9 +584,26 @@ __global__ __launch_bounds__(kBlock, 6) void k_bwd2(Sweep<T> a) {
         T s0, s1;
         if (aligned) ell_dot_pair<true>(a.M, q.i0, q.h0, q.i1, q.h1, a.n, gz, s0, s1);
         else ell_dot_pair<false>(a.M, q.i0, q.h0, q.i1, q.h1, a.n, gz, s0, s1);
-        if (q.h0) a.z[q.i0] = (y0 - s0) * d0;
-        if (q.h1) a.z[q.i1] = (y1 - s1) * d1;
+        if (q.h0) {
+            const T zi = (y0 - s0) * d0;
+            a.z[q.i0] = zi;
+            if constexpr (SC) {
+                const T zs = add_coarse<T, SC>(a, q.i0, zi);
+                a.zsc[q.i0] = zs;
+                acc[0] += (double)a.r[q.i0] * (double)zs;
+            }
+        }
+        if (q.h1) {
+            const T zi = (y1 - s1) * d1;
+            a.z[q.i1] = zi;
+            if constexpr (SC) {
+                const T zs = add_coarse<T, SC>(a, q.i1, zi);
+                a.zsc[q.i1] = zs;
+                acc[0] += (double)a.r[q.i1] * (double)zs;
+            }
+        }
     }
+    if constexpr (SC) block_partials<1>(acc, a.part, 1);
 }
 
 // Block-Jacobi z = M^{-1} r with tridiagonal blocks, one wavefront per block,
@@ -1560,10 +1580,18 @@ template <typename T> static void bwd_impl(const Sweep<T> &a, bool sc, int grid,
 }
 void launch_bwd(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
 void launch_bwd(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { bwd_impl(a, sc, grid, s); }
-void launch_fwd2(const Sweep<double> &a, int grid, hipStream_t s) { k_fwd2<double><<<grid, kBlock, 0, s>>>(a); }
-void launch_fwd2(const Sweep<float> &a, int grid, hipStream_t s) { k_fwd2<float><<<grid, kBlock, 0, s>>>(a); }
-void launch_bwd2(const Sweep<double> &a, int grid, hipStream_t s) { k_bwd2<double><<<grid, kBlock, 0, s>>>(a); }
-void launch_bwd2(const Sweep<float> &a, int grid, hipStream_t s) { k_bwd2<float><<<grid, kBlock, 0, s>>>(a); }
+template <typename T> static void fwd2_impl(const Sweep<T> &a, bool sc, int grid, hipStream_t s) {
+    if (sc) k_fwd2<T, false><<<grid, kBlock, 0, s>>>(a);
+    else k_fwd2<T, true><<<grid, kBlock, 0, s>>>(a);
+}
+template <typename T> static void bwd2_impl(const Sweep<T> &a, bool sc, int grid, hipStream_t s) {
+    if (sc) k_bwd2<T, true><<<grid, kBlock, 0, s>>>(a);
+    else k_bwd2<T, false><<<grid, kBlock, 0, s>>>(a);
+}
+void launch_fwd2(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { fwd2_impl(a, sc, grid, s); }
+void launch_fwd2(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { fwd2_impl(a, sc, grid, s); }
+void launch_bwd2(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { bwd2_impl(a, sc, grid, s); }
+void launch_bwd2(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { bwd2_impl(a, sc, grid, s); }
 
 int bj_grid(int nb) { return std::min(kMaxGrid, (nb + kBlock / 64 - 1) / (kBlock / 64)); }
 

@@ -203,8 +203,9 @@ def _full_kernel_parity(p, s, o):
 def test_two_row_kernels_on_ragged_levels():
     """131^3 (odd): the colour levels (about 843 K rows, 3294 tiles) take the
     two-rows-per-thread sweeps and FP32 streams and end in partial tiles.
-    SpMV, factor and M^{-1} r against the oracle; 40 matched FP64 deflated
-    iterations with a seeded orthonormal W; the FP32/FP64 mixed deflated solve
+    SpMV, factor and M^{-1} r against the oracle; 40 matched FP64 deflated and
+    subspace-corrected iterations with a seeded orthonormal W (the latter
+    through the two-row sweeps that add W u); the FP32/FP64 mixed deflated solve
     (two-row FP32 update and projection) to relres 1e-8 against the oracle's
     FP64 deflated solution."""
     import torch
@@ -219,11 +220,12 @@ def test_two_row_kernels_on_ragged_levels():
     W, _ = np.linalg.qr(np.random.default_rng(8).standard_normal((p.n, 6)))
     s.set_aux(W)
     o.set_aux(W)
-    x, info = s.solve(torch.as_tensor(p.f, device="cuda"), tol=0.0, maxit=40, mode=esd.DEFLATED)
-    y, oi = o.solve(p.f, tol=0.0, maxit=40, mode=O.DEFLATED)
-    print("131^3 deflated 40 its: err", _relerr(x, y), "kappa", info["kappa"], oi.kappa, flush=True)
-    assert info["iters"] == oi.iters == 40 and _relerr(x, y) <= 1e-10
-    assert abs(info["kappa"] / oi.kappa - 1) <= 1e-6
+    for mode, omode in ((esd.DEFLATED, O.DEFLATED), (esd.SUBSPACE, O.SUBSPACE)):
+        x, info = s.solve(torch.as_tensor(p.f, device="cuda"), tol=0.0, maxit=40, mode=mode)
+        y, oi = o.solve(p.f, tol=0.0, maxit=40, mode=omode)
+        print("131^3 mode", mode, "40 its: err", _relerr(x, y), "kappa", info["kappa"], oi.kappa, flush=True)
+        assert info["iters"] == oi.iters == 40 and _relerr(x, y) <= 1e-10
+        assert abs(info["kappa"] / oi.kappa - 1) <= 1e-6
     y8, oi8 = o.solve(p.f, tol=1e-8, maxit=20000, mode=O.DEFLATED)
     x8, i8 = s.solve(torch.as_tensor(p.f, device="cuda"), tol=1e-8, maxit=20000, mode=esd.DEFLATED,
                      flags=esd.FLAG_MIXED)
