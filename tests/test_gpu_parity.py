@@ -614,6 +614,15 @@ def test_zero_rhs_and_maxit():
     assert _relerr(x, y) <= 1e-12
     x, info = s.solve(p.f, tol=1e-8, maxit=0)
     assert info["iters"] == 0 and info["status"] == esd.NOT_CONVERGED
+    # mixed solves stopped by maxit, in both refinement forms: the cap counts
+    # FP32 inner iterations across refinement steps (a continued run included)
+    s.set_mixed_params(1e-2, 60)
+    for flags in (esd.FLAG_MIXED, esd.FLAG_MIXED | esd.FLAG_MIXED_KEEP):
+        x, info = s.solve(p.f, tol=1e-12, maxit=9, flags=flags)
+        print("mixed maxit 9, flags", flags, "its", info["iters"], "outer", info["outer_iters"], flush=True)
+        assert info["status"] == esd.NOT_CONVERGED and info["iters"] == 9 and info["outer_iters"] >= 2
+        assert np.isfinite(x.cpu().numpy()).all()
+    s.set_mixed_params()
     s.close()
 
 
