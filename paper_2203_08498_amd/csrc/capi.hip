@@ -457,7 +457,6 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     fa.Cinv = c->Cinv; fa.hist_alpha = c->ha;
     esd::UpdIt<T> ua{};
     ua.n = n; ua.S = c->S; ua.part = c->part_upd; ua.q = V.q; ua.x = V.x; ua.r = V.r; ua.tmap = c->tmap;
-    ua.AW = V.AW; ua.m = 0;
     ua.l0 = fuse_l0 ? (int)c->lvl[1] : 0; ua.dinv = V.dinv; ua.y = V.y;
     esd::FinRho fr{};
     fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = 2;
@@ -496,7 +495,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
                 esd::launch_update_bj(ub, c->stream);
                 if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 3], c->stream)) != hipSuccess) return e;
             } else {
-                esd::launch_update_it(ua, 0, gu, c->stream);
+                esd::launch_update_it(ua, gu, c->stream);
                 if (sc) {
                     esd::launch_tsdot_rm(ta, gt, c->stream);
                     esd::launch_fin_u(c->S, c->part_ts, gt, st_t, m, c->Cinv, c->stream);

@@ -82,17 +82,15 @@ template <typename T> struct SpmvIt {
     const int32_t *tmap; // tile order (nullptr: natural)
 };
 
-// x += alpha p; r -= alpha w with w = q (plain, SC) or q - AW mu (deflated);
-// partials ||r||^2; rows [0, l0) also do their forward-sweep step y = r / l_ii
-// (they have no logically-earlier neighbour).
+// x += alpha p; r -= alpha q (q = A p of the plain, subspace-corrected or
+// projected deflated direction); partials ||r||^2; rows [0, l0) also do their
+// forward-sweep step y = r / l_ii (they have no logically-earlier neighbour).
 template <typename T> struct UpdIt {
     int n;
     Scal *S;
     double *part;
     const T *p, *q;
     T *x, *r;
-    const T *AW; // deflated, column-major
-    int m;
     int l0;      // rows of the first sweep level fused here (0 = none)
     const T *dinv;
     T *y;
@@ -229,8 +227,8 @@ void launch_repack(int64_t size, const int64_t *src, const double *from, double 
 void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s);
 void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s);
 // kind 0 plain / subspace correction, 1 deflated
-void launch_update_it(const UpdIt<double> &a, int kind, int grid, hipStream_t s);
-void launch_update_it(const UpdIt<float> &a, int kind, int grid, hipStream_t s);
+void launch_update_it(const UpdIt<double> &a, int grid, hipStream_t s);
+void launch_update_it(const UpdIt<float> &a, int grid, hipStream_t s);
 void launch_proj(const Proj<double> &a, int grid, hipStream_t s);
 void launch_proj(const Proj<float> &a, int grid, hipStream_t s);
 void launch_tsdot_rm(const TsDot<double> &a, int grid, hipStream_t s);

@@ -287,33 +287,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
     block_partials<NV>(acc, a.part, NV);
 }
 
-// KIND: 0 plain / subspace correction, 1 deflated (w = q - AW mu)
-template <typename T, int MT, int KIND>
+// x += alpha p, r -= alpha q, ||r||^2; rows of the first sweep level (i < l0)
+// also take y = r / l_ii and ||y||^2 (the level-0 forward sweep fused here)
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
     const T ta = (T)S->alpha;
     double acc[2] = {0.0, 0.0};
-    const int n = a.n, m = a.m;
-    double mu[KIND == 1 ? MT : 1];
-    if constexpr (KIND == 1) {
-#pragma unroll
-        for (int k = 0; k < MT; ++k) mu[k] = (k < m) ? S->mu[k] : 0.0;
-    }
+    const int n = a.n;
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= n) continue;
-        T wi = a.q[i];
-        if constexpr (KIND == 1) {
-            double s = (double)wi;
-#pragma unroll
-            for (int k = 0; k < MT; ++k)
-                if (k < m) s -= (double)a.AW[(size_t)k * n + i] * mu[k];
-            wi = (T)s;
-        }
         a.x[i] += ta * a.p[i];
-        const T ri = a.r[i] - ta * wi;
+        const T ri = a.r[i] - ta * a.q[i];
         a.r[i] = ri;
         acc[0] += (double)ri * (double)ri;
         if (i < a.l0) {
@@ -329,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
 // t and t + 1 of the block's range: all loads of both rows first.  A 4-byte
 // row moves half the bytes of an FP64 one per load instruction, so one row
 // per thread leaves the FP32 streams short of loads in flight.  Same
-// arithmetic per row as k_update_it<T, MT, 0>.
+// arithmetic per row as k_update_it.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_it2(UpdIt<T> a) {
     Scal *S = a.S;
@@ -1526,17 +1514,12 @@ template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, bool power, i
 void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 
-template <typename T> static void update_it_impl(const UpdIt<T> &a, int kind, int grid, hipStream_t s) {
-    if (kind == 0 && stream_pairs<T>(a.n)) {
-        k_update_it2<T><<<grid, kBlock, 0, s>>>(a);
-    } else if (kind == 1) {
-        ESD_MT_SWITCH(a.m, (k_update_it<T, (MTV > 0 ? MTV : 8), 1><<<grid, kBlock, 0, s>>>(a)));
-    } else {
-        k_update_it<T, 0, 0><<<grid, kBlock, 0, s>>>(a);
-    }
+template <typename T> static void update_it_impl(const UpdIt<T> &a, int grid, hipStream_t s) {
+    if (stream_pairs<T>(a.n)) k_update_it2<T><<<grid, kBlock, 0, s>>>(a);
+    else k_update_it<T><<<grid, kBlock, 0, s>>>(a);
 }
-void launch_update_it(const UpdIt<double> &a, int kind, int grid, hipStream_t s) { update_it_impl(a, kind, grid, s); }
-void launch_update_it(const UpdIt<float> &a, int kind, int grid, hipStream_t s) { update_it_impl(a, kind, grid, s); }
+void launch_update_it(const UpdIt<double> &a, int grid, hipStream_t s) { update_it_impl(a, grid, s); }
+void launch_update_it(const UpdIt<float> &a, int grid, hipStream_t s) { update_it_impl(a, grid, s); }
 
 template <typename T> static void proj_impl(const Proj<T> &a, int grid, hipStream_t s) {
     if (stream_pairs<T>(a.n) && a.m <= 16) {
