@@ -97,7 +97,11 @@ typedef struct {
     double kappa;         /* K1: extreme Lanczos values from the CG alpha/beta */
     double kappa_es;      /* K2: power-method lambda_max / smallest Ritz value (Sec. 5.4) */
     double lambda_max;    /* (v, A v) of the power iteration of this solve, or of the last solve on
-                             the current values that ran it (ESD_FLAG_POWER); 0 if none did */
+                             the current values that ran it (ESD_FLAG_POWER); 0 if none did.
+                             With ESD_FLAG_MIXED the power iterate rides on the FP32 inner SpMV,
+                             so A here is the FP32 copy of the values (the quotient itself is
+                             accumulated in FP64); it differs from the FP64 lambda_max by about
+                             the FP32 rounding of A, relative 1e-7 */
     double lambda_min_ritz; /* smallest Ritz value of the last build_aux (0 if none) */
     double lanczos_min, lanczos_max; /* extreme eigenvalues of the Lanczos matrix */
     double seconds;       /* wall time of the solve on the stream (hipEvent) */

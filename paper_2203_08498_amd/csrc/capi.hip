@@ -453,8 +453,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     sa.q = V.q;
     esd::FinAlpha fa{};
     fa.S = c->S; fa.part = c->part_spmv; fa.nblk = gs; fa.stride = sstride; fa.power = o.power;
-    fa.part_s = c->part_ts; fa.nblk_s = gt; fa.stride_s = st_t; fa.m = 0;
-    fa.Cinv = c->Cinv; fa.hist_alpha = c->ha;
+    fa.hist_alpha = c->ha;
     esd::UpdIt<T> ua{};
     ua.n = n; ua.S = c->S; ua.part = c->part_upd; ua.q = V.q; ua.x = V.x; ua.r = V.r; ua.tmap = c->tmap;
     ua.l0 = fuse_l0 ? (int)c->lvl[1] : 0; ua.dinv = V.dinv; ua.y = V.y;
@@ -535,7 +534,9 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     constexpr int kChunk = 16, kTail = 4;
     const uint32_t key0 = (sizeof(T) == 4 ? 1u : 0u) | ((uint32_t)o.kind << 1) | ((uint32_t)o.noprec << 3) |
                           ((uint32_t)o.power << 4) | ((uint32_t)o.sampling << 5) | ((uint32_t)(*vbase & 1) << 6) |
-                          ((uint32_t)fuse_l0 << 7) | ((uint32_t)o.resid << 8) | ((uint32_t)o.method_b << 9);
+                          ((uint32_t)fuse_l0 << 7) | ((uint32_t)o.resid << 8) | ((uint32_t)o.method_b << 9) |
+                          // method B's finalize takes the slot count as an argument
+                          ((uint32_t)((o.sampling && o.method_b) ? c->m_req : 0) << 11);
     // the cached graph of `count` iterations of this variant (nullptr: the
     // variant does not capture, stream launches for it)
     auto graph_for = [&](int count) -> hipGraphExec_t {
@@ -946,18 +947,24 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
             c->Sh->rr = rn2;
             c->Sh->hist_base = total;
             c->Sh->sample_base = total;
+            // a sampling solve keeps sampling here: the FP64 iterate is the
+            // solution itself (no base, scale 1), stored like the inner ones
+            if (method_b) put_method_b(c);
             if ((st = put_scal(c))) return st;
             if (kind == 2) dev_tsdot(c, c->W, m, c->r, c->S->u, 1.0);
             KrylovOpts o;
             o.kind = kind;
             o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
             o.power = false;
-            o.sampling = false;
+            o.sampling = sampling;
+            o.resid = c->samp_resid;
+            o.method_b = method_b;
             o.sync_every = (flags & ESD_FLAG_SYNC_EVERY) != 0;
             o.stream_only = (flags & ESD_FLAG_STREAM) != 0;
             int it64 = 0;
             st = krylov<double>(c, V64, o, &it64, &c->vb64);
             if (st) return st;
+            if (method_b) get_method_b(c);
             c->segments.push_back({total, it64});
             total += it64;
             fp64_iters += it64;
@@ -1040,7 +1047,8 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     esd::launch_scatter(n, c->p2u, c->x, xout, c->stream);
     if (sampling) {
         HIPCHK(hipMemcpyAsync(c->xN, c->x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-        // inner iterates followed by another inner iteration were sampled
+        // iterates followed by another iteration of the same run (FP32 inner
+        // run or FP64 finish) were sampled: a store rides on the next SpMV
         c->slot_iter.assign(c->m_req, 0);
         c->nsamples = 0;
         for (auto &sg : c->segments)

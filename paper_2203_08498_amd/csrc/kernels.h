@@ -161,15 +161,12 @@ template <typename T> struct UpdBj {
     T *z;
 };
 
-// finalize after the SpMV: alpha = rho / ((p,q) - s^T C^{-1} s), mu = C^{-1} s
-// with s = W^T q from a TsDot partial table
+// finalize after the SpMV: alpha = rho / (p, q); with the power iterate also
+// its scale 1 / ||v_new||
 struct FinAlpha {
     Scal *S;
     const double *part;
     int nblk, stride, power;
-    const double *part_s; // W^T q partials (deflated), nblk_s x stride_s
-    int nblk_s, stride_s, m;
-    const double *Cinv;
     double *hist_alpha;
 };
 // finalize after the preconditioner: stop test on ||r||^2, rho, beta; with

@@ -794,34 +794,17 @@ __global__ __launch_bounds__(kBlock) void k_copyz(Sweep<T> a) {
 __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(FinAlpha f) {
     Scal *S = f.S;
     __shared__ double tot[2];
-    __shared__ double sv[64];
-    __shared__ double mus[64];
-    __shared__ double cinv[64 * 64];
     const int done0 = S->done;
     const int t = threadIdx.x;
     double rho = 0.0;
     int iter = 0, hbase = 0;
     if (t == 0) { rho = S->rho; iter = S->iter; hbase = S->hist_base; }
-    const int mm = f.m * f.m;
-    for (int k = t; k < mm; k += kFinThreads) cinv[k] = f.Cinv[k];
-    if (f.m > 0) {
-        const ColTab tab[2] = {{f.part, f.nblk, f.stride, 0, f.stride, tot}, {f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv}};
-        fin_colsums<2>(tab);
-    } else {
-        fin_colsum(f.part, f.nblk, f.stride, 0, f.stride, tot);
-    }
+    fin_colsum(f.part, f.nblk, f.stride, 0, f.stride, tot);
     if (done0) return;
-    if (t < f.m) {
-        double acc = 0.0;
-        for (int j = 0; j < f.m; ++j) acc += cinv[t * f.m + j] * sv[j];
-        mus[t] = acc;
-        S->mu[t] = acc;
-    }
-    __syncthreads();
     if (t == 0) {
-        double denom = tot[0];
-        for (int k = 0; k < f.m; ++k) denom -= sv[k] * mus[k];
-        const double alpha = rho / denom;
+        // (p, q) of the direction the SpMV multiplied: for deflation the
+        // projected p, so (p, q) = (p, P^T A p) needs no correction term
+        const double alpha = rho / tot[0];
         S->alpha = alpha;
         if (f.hist_alpha) f.hist_alpha[hbase + iter] = alpha;
         if (!isfinite(alpha)) S->done = 3;

@@ -186,6 +186,25 @@ def _theta(o):
     return float(np.sqrt(r0[g] * r0[g + 1]))
 
 
+def _own_aux(p, s, o, seed=13):
+    """Give the solver (and the oracle) a W of its own, independent of what an
+    earlier test left: seeded samples whose errors are rich in the low
+    spectrum, build_aux at a threshold inside the widest Ritz gap, so
+    m_tilde >= 1 on both sides.  Returns m_tilde."""
+    rng = np.random.default_rng(seed)
+    xN = rng.standard_normal(p.n)
+    E0 = rng.standard_normal((p.n, 6))
+    for _ in range(3):
+        E0 = E0 - 0.5 * np.column_stack([o.spmv(E0[:, j]) for j in range(E0.shape[1])])
+    s.load_samples(xN[:, None] - E0, xN)
+    o.load_samples(xN[:, None] - E0, xN)
+    theta = _theta(o)
+    st, ritz, mb, mt = s.build_aux(theta)
+    ost, oritz, omb, omt = o.build_aux(theta)
+    assert mt == omt and mt > 0
+    return mt
+
+
 def test_rayleigh_ritz_on_identical_samples(case):
     """build_aux on the same seeded samples: Ritz values, W and C to 1e-10."""
     from paper_2203_08498_amd import esd
@@ -381,6 +400,97 @@ def test_sampling_method_b_and_residual_vectors(case, method, residuals):
     assert np.abs(ritz - oritz).max() <= 10 * max(delta, 1e-13) * 2.0 + 1e-12
 
 
+def test_method_b_slot_count_change_on_one_context():
+    """Sampling method B at m = 4 and then at m = 8 on the same context (the
+    second solve must not replay the first one's captured iteration chunks,
+    whose finalize was built for 4 thresholds): both times the oracle's
+    sampled iterations and stored vectors."""
+    p = P.config2(N=18, nsph=2, radius=3.0)
+    s = _solver(p, m_max=8)
+    s.factor_ic0()
+    for m in (4, 8, 4):
+        o = _oracle(p)
+        s.sample_errors(m, method=1)
+        x, info = s.solve(p.f, tol=1e-8, maxit=5000)
+        o.arm_sampling(m, method=1)
+        y, oi = o.solve(p.f, tol=1e-8, maxit=5000, flags=O.SAMPLE)
+        its = o.samples(m)
+        print("method B m", m, "sampled", its.tolist(), s.samples(m).tolist(), flush=True)
+        assert info["iters"] == oi.iters and np.array_equal(s.samples(m), its)
+        assert (its > 0).sum() >= m - 1
+        X = o.slot_vectors(m)
+        for sl in range(m):
+            if its[sl]:
+                assert _relerr(s.sample_vector(sl), X[:, sl]) <= 1e-10
+    s.close()
+
+
+def _schedule_skipping(m, total, skip):
+    """Iteration kept in each slot by sampling method A over iterations
+    1 .. total-1 when the iterate of iteration `skip` is never stored (the
+    last iterate of a run that a new run follows): the oracle's schedule
+    decides the slot of every iteration."""
+    cur = np.zeros(m, np.int64)
+    for i in range(1, total):
+        hit = np.flatnonzero(O.sample_schedule(m, i + 1) == i)
+        if len(hit) and i != skip:
+            cur[hit[0]] = i
+    return cur
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_mixed_sampling_continues_in_the_fp64_finish(method):
+    """A mixed-precision sampling solve whose refinement stalls on purpose
+    (inner tolerance 0.9: a refinement step cuts the residual by 10% only, so
+    the second step hands the rest of the solve to FP64 CG).  The FP64 finish
+    keeps sampling: every slot a stale earlier solve (another right-hand side)
+    filled is overwritten by an iterate of this solve.  Method A: the recorded
+    iterations are the schedule's, minus the last iterate of the FP32 run; the
+    stored iterates' A-norm errors fall strictly with the iteration.  Method
+    B: each stored iterate meets its threshold tol^{(s+1)/(m+1)} with its FP64
+    true residual.  build_aux keeps every stored vector (m_bar = filled)."""
+    from paper_2203_08498_amd import esd
+
+    p = P.config2(N=18, nsph=2, radius=3.0)
+    s = _solver(p, m_max=8)
+    s.factor_ic0()
+    o = _oracle(p)
+    m, tol = 8, 1e-8
+    s.sample_errors(m, method=method)
+    s.solve(2.0 * p.f + 1.0, tol=tol, maxit=5000)  # stale slot contents
+    s.set_mixed_params(0.9, 30)
+    try:
+        s.sample_errors(m, method=method)
+        x, info = s.solve(p.f, tol=tol, maxit=5000, flags=esd.FLAG_MIXED)
+    finally:
+        s.set_mixed_params()
+    k32 = info["iters"] - info["fp64_iters"]
+    its = s.samples(m)
+    print("mixed sampling method", method, "iters", info["iters"], "fp64", info["fp64_iters"], "sampled",
+          its.tolist(), flush=True)
+    assert info["converged"] and info["fp64_iters"] >= 0.8 * info["iters"] and k32 >= 1
+    xn = x.cpu().numpy()
+    filled = [sl for sl in range(m) if its[sl] > 0]
+    if method == 0:
+        assert np.array_equal(its, _schedule_skipping(m, info["iters"], k32))
+        assert len(filled) == m
+        errs = []
+        for sl in sorted(filled, key=lambda q: its[q]):
+            e = xn - s.sample_vector(sl).cpu().numpy()
+            errs.append(np.sqrt(e @ o.spmv(e)))
+        assert np.all(np.diff(errs) < 0), errs
+    else:
+        assert len(filled) >= m - 1
+        nb = np.linalg.norm(p.f)
+        for sl in filled:
+            xs = s.sample_vector(sl).cpu().numpy()
+            rel = np.linalg.norm(p.f - o.spmv(xs)) / nb
+            assert rel <= tol ** ((sl + 1) / (m + 1)) * (1 + 1e-6), (sl, rel)
+    st, ritz, mb, mt = s.build_aux(1.0)
+    assert mb == len(filled)
+    s.close()
+
+
 def test_power_iteration_kappa_es(case):
     from paper_2203_08498_amd import esd
 
@@ -407,9 +517,8 @@ def test_mixed_precision_meets_fp64_tolerance(case):
     from paper_2203_08498_amd import esd
 
     name, p, s, o = case
+    _own_aux(p, s, o)
     for mode in (esd.PLAIN, esd.DEFLATED, esd.SUBSPACE):
-        if mode != esd.PLAIN and getattr(s, "m_tilde", 0) == 0:
-            continue
         x, info = s.solve(p.f, tol=1e-8, maxit=20000, mode=mode, flags=esd.FLAG_MIXED)
         y, _ = o.solve(p.f, tol=1e-12, maxit=20000)
         print(name, "mixed mode", mode, "its", info["iters"], "outer", info["outer_iters"],
@@ -430,10 +539,10 @@ def test_mixed_keep_continues_the_run(case):
 
     name, p, s, o = case
     y, _ = o.solve(p.f, tol=1e-12, maxit=20000)
+    _own_aux(p, s, o)
     s.set_mixed_params(1e-2, 60)
     try:
-        modes = [esd.PLAIN] + ([esd.DEFLATED, esd.SUBSPACE] if getattr(s, "m_tilde", 0) else [])
-        for mode in modes:
+        for mode in (esd.PLAIN, esd.DEFLATED, esd.SUBSPACE):
             flags = esd.FLAG_MIXED | esd.FLAG_MIXED_KEEP
             x, info = s.solve(p.f, tol=1e-8, maxit=20000, mode=mode, flags=flags)
             a, b = s.history()
@@ -460,9 +569,9 @@ def test_graph_replays_match_stream_launches(case):
     from paper_2203_08498_amd import esd
 
     name, p, s, o = case
-    modes = [esd.PLAIN] + ([esd.DEFLATED, esd.SUBSPACE] if getattr(s, "m_tilde", 0) else [])
+    _own_aux(p, s, o)
     for flags in (0, esd.FLAG_MIXED):
-        for mode in modes:
+        for mode in (esd.PLAIN, esd.DEFLATED, esd.SUBSPACE):
             xs, i_s = s.solve(p.f, tol=1e-8, maxit=5000, mode=mode, flags=flags | esd.FLAG_STREAM)
             for rep in range(2):
                 xg, i_g = s.solve(p.f, tol=1e-8, maxit=5000, mode=mode, flags=flags)

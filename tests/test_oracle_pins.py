@@ -449,8 +449,6 @@ def test_gram_schmidt_and_rayleigh_ritz():
     A = dense(p)
     assert mb == E.shape[1] and mb <= 8
     assert np.abs(E.T @ E - np.eye(mb)).max() < 1e-14
-    # every error vector lies in span(E)
-    o2 = O.Oracle.from_problem(p); o2.factor_ic0(); o2.arm_sampling(8)
     assert np.abs(np.sort(ritz) - ritz).max() == 0
     G = E.T @ A @ E
     assert np.abs(ritz - np.linalg.eigvalsh(0.5 * (G + G.T))).max() < 1e-12
@@ -537,6 +535,48 @@ def test_error_vectors_span_contains_errors():
     for xk in xs:
         e = x - xk
         assert np.linalg.norm(e - E @ (E.T @ e)) <= 1e-9 * np.linalg.norm(e)
+
+
+def test_dependent_samples_are_dropped_mbar_is_rank():
+    """Sec. 4.2 (eq. (ekd)): the orthonormalised error vectors drop samples
+    that add nothing to the span, so m_bar = rank of the error set.  Samples:
+    four independent errors, an exact repeat of the second, a linear
+    combination of the first and third, and the final solution itself (error
+    zero); the basis E spans exactly the error set, and the first sample of
+    every dependent group (in sampled-iteration order) is the one kept."""
+    p = P.config1(N=24, nbox=1, box=4)
+    o = O.Oracle.from_problem(p)
+    assert o.factor_ic0() == 0
+    rng = np.random.default_rng(31)
+    xN = rng.standard_normal(p.n)
+    E0 = rng.standard_normal((p.n, 4))
+    errs = [E0[:, 0], E0[:, 1], E0[:, 1].copy(), E0[:, 2], 0.3 * E0[:, 0] - 2.0 * E0[:, 2],
+            np.zeros(p.n), E0[:, 3]]
+    Eset = np.column_stack(errs)
+    X = xN[:, None] - Eset
+    o.load_samples(X, xN)
+    st, ritz, mb, mt = o.build_aux(1.0)
+    rank = np.linalg.matrix_rank(Eset)
+    assert rank == 4 and mb == rank
+    E = o.aux()[0]
+    assert E.shape[1] == mb and np.abs(E.T @ E - np.eye(mb)).max() < 1e-13
+    # same span: every error lies in span(E) and E lies in span of the errors
+    Q, _ = np.linalg.qr(E0)
+    assert np.abs(E @ E.T - Q @ Q.T).max() < 1e-12
+    for e in errs:
+        assert np.linalg.norm(e - E @ (E.T @ e)) <= 1e-12 * max(np.linalg.norm(e), 1.0)
+    # kept in order: E's first column is e_1 normalised, its second spans
+    # {e_1, e_2}, the third {e_1, e_2, e_4} (e_3 repeats e_2)
+    assert abs(abs(E[:, 0] @ errs[0]) / np.linalg.norm(errs[0]) - 1.0) < 1e-13
+    for k, upto in ((2, (0, 1)), (3, (0, 1, 3))):
+        Qk, _ = np.linalg.qr(np.column_stack([errs[j] for j in upto]))
+        assert np.abs(E[:, :k] @ E[:, :k].T - Qk @ Qk.T).max() < 1e-12
+    # a set of one repeated sample only: m_bar = 1
+    o1 = O.Oracle.from_problem(p)
+    o1.factor_ic0()
+    o1.load_samples(np.column_stack([X[:, 0], X[:, 0], X[:, 0]]), xN)
+    _, r1, mb1, _ = o1.build_aux(1.0)
+    assert mb1 == 1 and len(r1) == 1
 
 
 def test_ritz_values_approach_isolated_small_eigenvalues():
