@@ -14,13 +14,16 @@
  *
  * Conventions for every entry point
  *   - (h) marks a host pointer, (d) a device pointer on the context's device.
- *     Device buffers passed in or out are owned by the caller (e.g. torch
- *     tensors); the library never frees them and never keeps them after the
- *     call returns.  All device memory the library needs for its own state
- *     (permuted matrix, factor, auxiliary space, work vectors) is allocated by
- *     esd_setup, and lazily by esd_solve / esd_build_aux when a larger
- *     history or sampling table, the preconditioned Rayleigh-Ritz buffer or a
- *     captured iteration graph is first needed; esd_destroy releases it.
+ *     Every device buffer is owned by the caller (e.g. torch tensors): the
+ *     inputs and outputs of each call, and the one workspace given to
+ *     esd_setup, which holds all of the context's device state (permuted
+ *     matrix and factor, auxiliary space, work vectors, block partials, the
+ *     alpha/beta history and sampling table).  The library never allocates
+ *     or frees device memory; it keeps only the workspace (until
+ *     esd_destroy) and never keeps a call's other buffers after it returns.
+ *     The context itself holds host-side state (Ritz values, C, the history
+ *     read back, pinned 1 KB scalar mirror), HIP events and, once a solve
+ *     variant first runs, its captured iteration graphs.
  *   - Vectors (b, x0, x, lambda, v0, W) are float64 in the caller's row order;
  *     the library permutes internally.
  *   - Work is enqueued on the stream given to esd_setup.  Calls that return
@@ -53,8 +56,30 @@ typedef enum {
     ESD_EHIP = -3,         /* HIP runtime error */
     ESD_ENUMERIC = -4,     /* NaN/Inf in the iteration */
     ESD_ENOAUX = -5,       /* accelerated mode requested before build_aux/set_aux */
-    ESD_ENOSAMPLES = -6    /* build_aux without a sampling solve */
+    ESD_ENOSAMPLES = -6,   /* build_aux without a sampling solve */
+    ESD_EWORKSPACE = -7    /* workspace missing, too small or not 256-byte aligned */
 } esd_status;
+
+/* ordering of the rows (esd_options.order) */
+#define ESD_ORDER_NATURAL 0       /* the caller's row order; IC(0) of A */
+#define ESD_ORDER_COLORS 1        /* stable sort of the rows by colour (multicolour order); IC(0) of A */
+#define ESD_ORDER_BLOCK_JACOBI 2  /* natural order; block-Jacobi IC(0) of the paper's parallel solver
+                                     (Sec. 5.3): IC(0) of the block-diagonal part of A, blocks of
+                                     block_rows consecutive rows */
+/* arithmetic of the context (esd_options.prec) */
+#define ESD_PREC_FP64 0   /* FP64 only: no FP32 copies are kept, ESD_FLAG_MIXED is rejected */
+#define ESD_PREC_MIXED 1  /* FP64 plus FP32 copies of A, L, W, AW and FP32 work vectors */
+
+typedef struct {
+    int32_t order;      /* ESD_ORDER_* */
+    int32_t block_rows; /* ESD_ORDER_BLOCK_JACOBI: rows per block (>= 1); ignored otherwise */
+    int32_t prec;       /* ESD_PREC_* */
+    int32_t m_max;      /* largest sample count (esd_sample_errors, esd_load_samples) and width of
+                           W (esd_set_aux), 1..64 */
+    int32_t max_iters;  /* largest maxit a solve may ask for (sizes the alpha/beta history and the
+                           sampling table); 0 = 100000 */
+    int32_t reserved[3];
+} esd_options;
 
 /* solver modes (Sec. 5.2: ICCG, ES-D-ICCG, ES-SC-ICCG) */
 #define ESD_PLAIN 0    /* IC(0)-preconditioned CG */
@@ -64,7 +89,7 @@ typedef enum {
 /* solve flags */
 #define ESD_FLAG_NOPREC 1 /* M = I (unpreconditioned CG), used for closed-form checks */
 #define ESD_FLAG_POWER 2  /* power iteration fused into the SpMV, (q v) = A (p v) (Alg. PCG-con) */
-#define ESD_FLAG_MIXED 4  /* FP32 inner solves inside an FP64 iterative-refinement loop; if a
+#define ESD_FLAG_MIXED 4  /* (ESD_PREC_MIXED contexts) FP32 inner solves inside an FP64 iterative-refinement loop; if a
                              refinement step fails to halve the FP64 residual the solve is
                              finished by FP64 CG (reported in esd_info.fp64_iters) */
 #define ESD_FLAG_SYNC_EVERY 8 /* check convergence after every iteration (no speculative chunk) */
@@ -108,43 +133,64 @@ typedef struct {
 } esd_info;
 
 /*
- * esd_setup - take one SPD matrix and an ordering; build the device formats.
- *   n, rowptr(h) int64[n+1], col(h) int32[nnz], val(h) float64[nnz]: the full
- *     symmetric CSR of A (both triangles, diagonal stored, columns sorted).
- *     The paper's test matrices are diagonally scaled beforehand (Sec. 5.1);
- *     the library solves the matrix it is given.
- *   colors(h) int32[n] or NULL: NULL keeps the natural order; otherwise rows
- *     are ordered by a stable sort on colour, which fixes the IC(0) factor.
- *     Rows of one colour must not be coupled (checked: ESD_EINVAL).
- *   hip_stream: a hipStream_t (NULL = default stream) all work is queued on.
- *   m_max: largest number of sample vectors a later esd_sample_errors may ask
- *     for (<= 64).
- * The caller may free its CSR arrays after the call.
+ * esd_workspace_bytes - device workspace, in bytes, that esd_setup needs at
+ * most for a matrix of n rows and nnz stored entries none of whose rows holds
+ * more than max_row entries (diagonal included), with the options opt(h).
+ * Pure host arithmetic (no GPU call).  The bound follows from the layouts'
+ * construction: a 64-row slice of the sliced-ELL layout is as wide as its
+ * longest row, the class-aligned copy is at most 5/4 of it, a level schedule
+ * has at most n levels.  For stencil matrices it exceeds the exact need by a
+ * few bytes per row.  Returns 0 for invalid arguments.
  */
-esd_status esd_setup(esd_ctx **ctx, void *hip_stream, int64_t n, const int64_t *rowptr,
-                     const int32_t *col, const double *val, const int32_t *colors, int32_t m_max);
+size_t esd_workspace_bytes(int64_t n, int64_t nnz, int32_t max_row, const esd_options *opt);
 
 /*
- * esd_setup_block_jacobi - as esd_setup, with the block-Jacobi IC(0)
- * preconditioner of the paper's parallel solver (Sec. 5.3) instead of IC(0)
- * of the whole matrix.  Rows stay in the natural order and are split into
- * blocks of block_rows consecutive rows (the last block may be shorter);
- * esd_factor_ic0 then computes IC(0) of the block-diagonal part of A, i.e.
- * every coupling between two blocks is left out of the preconditioner (A,
- * the SpMV and everything else keep them).
- *   block_rows >= 1.  When every coupling inside a block joins two
- *     consecutive rows (tridiagonal blocks; on a natural-order grid, blocks of
- *     at most one grid line) and block_rows <= 512, each block's factor is
- *     its exact Cholesky factor and M^{-1} r runs as one launch (two
- *     recurrences per block, one wavefront each).  Other blocks (the paper's
- *     few large blocks, for instance) run the level-scheduled sweeps of the
- *     in-block couplings: correct for any block shape, one launch per level,
- *     so slow when the chains inside a block are long.
- * Sampling, auxiliary space, all solver modes, mixed precision and the
- * gradient work as after esd_setup.
+ * esd_setup - take one SPD matrix and an ordering; build the device formats
+ * in the caller's workspace.
+ *   n, nnz, rowptr(d) int64[n+1], col(d) int32[nnz], val(d) float64[nnz]: the
+ *     full symmetric CSR of A (both triangles, diagonal stored, columns
+ *     sorted).  The paper's test matrices are diagonally scaled beforehand
+ *     (Sec. 5.1); the library solves the matrix it is given.  The CSR is read
+ *     (copied to the host for the ordering and layout analysis, and into the
+ *     workspace); the caller may free it after the call.
+ *   colors(d) int32[n]: with ESD_ORDER_COLORS, rows are ordered by a stable
+ *     sort on colour, which fixes the IC(0) factor; rows of one colour must
+ *     not be coupled (checked: ESD_EINVAL).  Ignored (may be NULL) otherwise.
+ *   opt(h): ordering, block size, precision, m_max, max_iters.
+ *   hip_stream: a hipStream_t (NULL = default stream) all work is queued on.
+ *   workspace(d), ws_bytes: device memory of at least the exact need, 256-byte
+ *     aligned (torch's allocator returns such blocks); esd_workspace_bytes
+ *     gives an upper bound without the analysis.  The context uses it until
+ *     esd_destroy; the caller must not touch it meanwhile.
+ *   ws_needed(h) out (may be NULL): the exact bytes this matrix needs, set
+ *     whenever the analysis succeeded -- also on ESD_EWORKSPACE, so that a
+ *     call with workspace = NULL is a size query.
+ * ESD_EWORKSPACE: workspace NULL, smaller than the need or misaligned (no
+ * context is created).  ESD_EINVAL: bad CSR, colours or options.
  */
-esd_status esd_setup_block_jacobi(esd_ctx **ctx, void *hip_stream, int64_t n, const int64_t *rowptr,
-                                  const int32_t *col, const double *val, int32_t block_rows, int32_t m_max);
+esd_status esd_setup(esd_ctx **ctx, void *hip_stream, int64_t n, int64_t nnz, const int64_t *rowptr,
+                     const int32_t *col, const double *val, const int32_t *colors, const esd_options *opt,
+                     void *workspace, size_t ws_bytes, size_t *ws_needed);
+
+/* esd_workspace_used - bytes(h) of the workspace the context occupies (its
+ * exact need, as returned through ws_needed). */
+esd_status esd_workspace_used(const esd_ctx *ctx, size_t *bytes);
+
+/* Block-Jacobi IC(0) (ESD_ORDER_BLOCK_JACOBI): the preconditioner of the
+ * paper's parallel solver (Sec. 5.3) instead of IC(0) of the whole matrix.
+ * Rows stay in the natural order and are split into blocks of block_rows
+ * consecutive rows (the last block may be shorter); esd_factor_ic0 then
+ * computes IC(0) of the block-diagonal part of A, i.e. every coupling between
+ * two blocks is left out of the preconditioner (A, the SpMV and everything
+ * else keep them).  When every coupling inside a block joins two consecutive
+ * rows (tridiagonal blocks; on a natural-order grid, blocks of at most one
+ * grid line) and block_rows <= 512, each block's factor is its exact Cholesky
+ * factor and M^{-1} r runs as one launch (two recurrences per block, one
+ * wavefront each).  Other blocks (the paper's few large blocks, for
+ * instance) run the level-scheduled sweeps of the in-block couplings: correct
+ * for any block shape, one launch per level, so slow when the chains inside a
+ * block are long.  Sampling, auxiliary space, all solver modes, mixed
+ * precision and the gradient work as with IC(0) of A. */
 
 /* esd_update_values - new values val(d) float64[nnz] for the same pattern, in
  * the caller's CSR order (a slowly varying matrix A_k, Sec. 2; finite-
@@ -206,7 +252,7 @@ esd_status esd_build_aux(esd_ctx *ctx, double theta, double *ritz, int32_t *m_ba
 esd_status esd_set_rayleigh_ritz(esd_ctx *ctx, int32_t op);
 
 /* esd_set_aux - use a caller-given auxiliary matrix W(d): n x k, column-major,
- * float64, user row order, full column rank, 1 <= k <= 64.  Replaces any W. */
+ * float64, user row order, full column rank, 1 <= k <= m_max.  Replaces any W. */
 esd_status esd_set_aux(esd_ctx *ctx, const double *W, int32_t k);
 
 /* esd_get_aux - copy out W(d) (n x m_tilde, column-major, user order; NULL to
@@ -231,7 +277,8 @@ esd_status esd_set_mixed_params(esd_ctx *ctx, double inner_tol, int32_t max_oute
  *   b(d) float64[n]; x0(d) float64[n] or NULL (zero start); x(d) out.
  *   tol: stop when ||r_i||_2 <= tol ||b||_2 (Alg. "Deflated PCG method" loop
  *     test; for ESD_FLAG_MIXED the FP64 true residual is tested).
- *   maxit: iteration cap (mixed: total inner iterations).
+ *   maxit: iteration cap (mixed: total inner iterations), <= the context's
+ *     max_iters (ESD_EINVAL above it).
  *   mode: ESD_PLAIN / ESD_DEFLATED / ESD_SUBSPACE; flags: ESD_FLAG_*.
  *   info(h) out (may be NULL).
  * A sampling solve is the first solve after esd_sample_errors.
@@ -252,6 +299,17 @@ esd_status esd_sequence_rhs(esd_ctx *ctx, const double *f, const double *xprev, 
  * lam(d), x(d) float64[n]; gval(d) float64[nnz] out.  Enqueued on the
  * context's stream without synchronising (device output only). */
 esd_status esd_grad_values(esd_ctx *ctx, const double *lam, const double *x, double *gval);
+
+/* esd_hbm_probe - streaming probe of the achievable HBM bandwidth on the
+ * device of hip_stream (not part of the method; the benchmark's ceiling):
+ * ESD_PROBE_COPY copies n float64 from src(d) to dst(d); ESD_PROBE_READ reads
+ * src(d) and writes one partial sum per block to dst(d)[0 .. grid).  grid
+ * blocks of 256 threads (0 = 4096), 16-byte accesses, grid-stride.  n even,
+ * both pointers 16-byte aligned (ESD_EINVAL otherwise).  Enqueued on
+ * hip_stream without synchronising; needs no context. */
+#define ESD_PROBE_COPY 0
+#define ESD_PROBE_READ 1
+esd_status esd_hbm_probe(void *hip_stream, int32_t kind, const double *src, double *dst, int64_t n, int32_t grid);
 
 /* Inspection entry points (used by tests and the benchmark). */
 esd_status esd_spmv(esd_ctx *ctx, const double *x, double *y);       /* y = A x, FP64, (d) */

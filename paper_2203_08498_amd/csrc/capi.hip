@@ -48,6 +48,7 @@ struct DevEll {
 template <typename T> struct VecSet {
     T *x, *r, *z, *zsc, *y, *q, *p[2], *v[2];
     const T *W, *AW, *Wrm, *AWrm, *dinv, *lsub;
+    const T *Y; // M^{-1} A W (column-major), valid when the context's y_ok is set
     Ell<T> A, L, U;
 };
 
@@ -61,6 +62,9 @@ struct esd_ctx {
     int64_t n = 0, nnz = 0;
     int ncolors = 1;
     int m_max = 0;
+    bool mixed = true;      // FP32 copies kept (ESD_PREC_MIXED)
+    int64_t max_iters = 0;  // capacity of the alpha/beta history and sampling table
+    size_t ws_used = 0;     // bytes of the caller's workspace this context occupies
     std::vector<int64_t> lvl;
     std::vector<int32_t> p2u_h, lperm_h;
     DevEll A, L, U;
@@ -102,7 +106,6 @@ struct esd_ctx {
     std::vector<double> b_thr2;
     double *slots = nullptr;
     int32_t *slot_table = nullptr;
-    int64_t slot_table_cap = 0;
     std::vector<int32_t> table_h;
     std::vector<int32_t> slot_iter;
     int nsamples = 0;
@@ -113,6 +116,9 @@ struct esd_ctx {
     int m_bar = 0, m_tilde = 0;
     double *E = nullptr, *AE = nullptr, *W = nullptr, *AW = nullptr;
     float *W32 = nullptr, *AW32 = nullptr;
+    double *Y = nullptr;     // M^{-1} A W, column-major: (AW)^T z = Y^T r inside the update launch
+    float *Y32 = nullptr;
+    bool y_ok = false;       // Y matches the current W, values and factor
     double *W_rm = nullptr;  // row-major copies for the tall-skinny W^T v and (AW)^T v
     float *W32_rm = nullptr;
     double *AW_rm = nullptr;
@@ -126,7 +132,6 @@ struct esd_ctx {
     double vs64 = 1.0, vs32 = 1.0;
     // history of the last solve
     double *ha = nullptr, *hb = nullptr;
-    int64_t hcap = 0;
     std::vector<double> ha_h, hb_h;
     std::vector<std::pair<int, int>> segments; // (base, count) of every Krylov run
     // mixed precision parameters
@@ -147,7 +152,6 @@ struct esd_ctx {
     bool class_layout = true; // class-aligned matrix copies for the iteration kernels when they fit
     bool trace = false;       // ESD_TRACE set: one stderr line per refinement step of the mixed solver
     int rr_op = 0;            // Rayleigh-Ritz operator of build_aux: 0 A, 1 M^{-1}A
-    double *ME = nullptr;     // M E for the preconditioned Rayleigh-Ritz (allocated on first use)
     hipStream_t cap = nullptr; // private stream the chunks are captured on
     // kernel timing
     std::vector<hipEvent_t> ev;
@@ -166,54 +170,162 @@ namespace {
         }                                                                                          \
     } while (0)
 
-template <typename T> hipError_t dalloc(T **p, int64_t count) {
-    if (count <= 0) count = 1;
-    return hipMalloc((void **)p, sizeof(T) * (size_t)count);
-}
-
 esd_status fail(esd_ctx *c, esd_status s, const std::string &msg) {
     if (c) c->err = msg;
     return s;
 }
 
-esd_status upload_ell(esd_ctx *c, DevEll &D, const esd::HostEll &H) {
-    D.size = (int64_t)H.col.size();
-    HIPCHK(dalloc(&D.sptr, (int64_t)H.sptr.size()));
-    HIPCHK(dalloc(&D.col, D.size));
-    HIPCHK(dalloc(&D.v64, D.size));
-    HIPCHK(dalloc(&D.v32, D.size));
+// Sizes of everything a context keeps in device memory.  Computed exactly by
+// esd_setup from the host layout, and as an upper bound by
+// esd_workspace_bytes from n, nnz and the longest row.
+struct EllSizes {
+    int64_t nsl = 0;   // 64-row slices
+    int64_t size = 0;  // stored slots of the sorted layout
+    int64_t csize = 0; // slots of the class-aligned copy (0: none)
+};
+struct Sizes {
+    int64_t n = 0, nnz = 0;
+    EllSizes A, L, U;
+    int64_t tmap = 0, tmap_lvl = 0, sweep_cap = 0;
+    int m_max = 1;
+    bool mixed = true;
+    int64_t max_iters = 0;
+};
+
+// Hands out consecutive 256-byte aligned pieces of the workspace; with a null
+// base it only adds up the bytes.
+struct Carver {
+    char *base = nullptr;
+    size_t off = 0;
+    template <typename T> void take(T **p, int64_t count) {
+        off = (off + 255) & ~size_t(255);
+        if (count < 1) count = 1;
+        if (base) *p = reinterpret_cast<T *>(base + off);
+        off += sizeof(T) * (size_t)count;
+    }
+};
+
+void carve_ell(Carver &cv, DevEll &D, const EllSizes &z, bool mixed) {
+    D.size = z.size;
+    cv.take(&D.sptr, z.nsl + 1);
+    cv.take(&D.col, z.size);
+    cv.take(&D.v64, z.size);
+    if (mixed) cv.take(&D.v32, z.size);
+    D.csize = z.csize;
+    if (z.csize) {
+        cv.take(&D.csptr, z.nsl + 1);
+        cv.take(&D.soff, z.csize / esd::kSlice);
+        cv.take(&D.src, z.csize);
+        cv.take(&D.cv64, z.csize);
+        if (mixed) cv.take(&D.cv32, z.csize);
+    }
+}
+
+// Every device buffer of a context, in one fixed order.  FP32 copies exist
+// only in mixed-precision contexts.  Returns the bytes used.
+size_t carve(esd_ctx *c, const Sizes &z, char *base) {
+    Carver cv;
+    cv.base = base;
+    const bool mx = z.mixed;
+    const int64_t n = z.n, nv = n + 64, mm = std::max(1, z.m_max);
+    carve_ell(cv, c->A, z.A, mx);
+    carve_ell(cv, c->L, z.L, mx);
+    carve_ell(cv, c->U, z.U, mx);
+    cv.take(&c->a_src, z.A.size);
+    cv.take(&c->l_src, z.L.size);
+    cv.take(&c->d_src, n);
+    cv.take(&c->l_orig, z.L.size);
+    cv.take(&c->u_from_l, z.U.size);
+    cv.take(&c->adiag, nv);
+    cv.take(&c->ldiag, nv);
+    cv.take(&c->dinv, nv);
+    cv.take(&c->lsub, nv);
+    if (mx) {
+        cv.take(&c->dinv32, nv);
+        cv.take(&c->lsub32, nv);
+    }
+    cv.take(&c->p2u, nv);
+    cv.take(&c->tmap, z.tmap);
+    cv.take(&c->tmap_lvl, z.tmap_lvl);
+    cv.take(&c->urp, n + 1);
+    cv.take(&c->ucol, z.nnz);
+    cv.take(&c->bad, 1);
+    double **v64[] = {&c->b, &c->x, &c->r, &c->z, &c->zsc, &c->y, &c->q, &c->p[0], &c->p[1], &c->t, &c->v[0],
+                      &c->v[1], &c->xN};
+    for (double **p : v64) cv.take(p, nv);
+    if (mx) {
+        float **v32[] = {&c->r32, &c->z32, &c->zsc32, &c->y32, &c->q32, &c->p32[0], &c->p32[1], &c->d32,
+                         &c->v32[0], &c->v32[1]};
+        for (float **p : v32) cv.take(p, nv);
+    }
+    // block partials: every reducing launch keeps grid x stride within kPartBudget
+    cv.take(&c->part_spmv, esd::kPartBudget);
+    cv.take(&c->part_upd, esd::kPartBudget);
+    cv.take(&c->part_gen, esd::kPartBudget);
+    cv.take(&c->part_ts, esd::kPartBudget);
+    cv.take(&c->part_sweep, z.sweep_cap);
+    cv.take(&c->S, 1);
+    cv.take(&c->slots, mm * n);
+    cv.take(&c->E, mm * n);
+    cv.take(&c->AE, mm * n);
+    cv.take(&c->W, mm * n);
+    cv.take(&c->AW, mm * n);
+    cv.take(&c->W_rm, mm * n);
+    cv.take(&c->AW_rm, mm * n);
+    cv.take(&c->Y, mm * n);
+    if (mx) {
+        cv.take(&c->Y32, mm * n);
+        cv.take(&c->W32, mm * n);
+        cv.take(&c->AW32, mm * n);
+        cv.take(&c->W32_rm, mm * n);
+        cv.take(&c->AW32_rm, mm * n);
+    }
+    cv.take(&c->Cinv, 64 * 64);
+    cv.take(&c->G, 64 * 64);
+    cv.take(&c->Tm, 64 * 64);
+    cv.take(&c->gram_part, (int64_t)esd::gram_grid((int)n) * 4096);
+    cv.take(&c->ha, z.max_iters + 4);
+    cv.take(&c->hb, z.max_iters + 4);
+    cv.take(&c->slot_table, z.max_iters + 2);
+    return (cv.off + 255) & ~size_t(255);
+}
+
+// sweep partial slots: one per block of every level launch (or of the whole
+// range, or of the block-Jacobi launch)
+int64_t sweep_slots(int64_t n, const std::vector<int64_t> &lvl, int bj_nb) {
+    int64_t tot = 0;
+    for (size_t l = 0; l + 1 < lvl.size(); ++l) tot += esd::grid_red(lvl[l + 1] - lvl[l], 1);
+    int64_t cap = std::max<int64_t>(esd::grid_red(n, 1), tot);
+    if (bj_nb > 0) cap = std::max<int64_t>(cap, esd::bj_grid(bj_nb));
+    return cap;
+}
+
+// Host copy of the class-aligned form of an ELL layout, computed before the
+// workspace is carved (csptr empty: the sorted layout serves the iterations)
+struct HostClass {
+    std::vector<int64_t> csptr, src;
+    std::vector<int32_t> soff;
+};
+
+esd_status upload_ell(esd_ctx *c, DevEll &D, const esd::HostEll &H, const HostClass &K, bool mixed) {
     HIPCHK(hipMemcpyAsync(D.sptr, H.sptr.data(), sizeof(int64_t) * H.sptr.size(), hipMemcpyHostToDevice, c->stream));
     if (D.size) {
         HIPCHK(hipMemcpyAsync(D.col, H.col.data(), sizeof(int32_t) * D.size, hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(D.v64, H.val.data(), sizeof(double) * D.size, hipMemcpyHostToDevice, c->stream));
     }
-    esd::launch_cast(D.size, D.v64, D.v32, c->stream);
-    std::vector<int64_t> csptr, src;
-    std::vector<int32_t> soff;
-    if (c->class_layout && D.size && esd::ell_classes(H, c->n, 64, csptr, soff, src)) {
-        D.csize = csptr.back();
-        HIPCHK(dalloc(&D.csptr, (int64_t)csptr.size()));
-        HIPCHK(dalloc(&D.soff, (int64_t)soff.size()));
-        HIPCHK(dalloc(&D.src, D.csize));
-        HIPCHK(dalloc(&D.cv64, D.csize));
-        HIPCHK(dalloc(&D.cv32, D.csize));
-        HIPCHK(hipMemcpyAsync(D.csptr, csptr.data(), sizeof(int64_t) * csptr.size(), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(D.soff, soff.data(), sizeof(int32_t) * soff.size(), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(D.src, src.data(), sizeof(int64_t) * src.size(), hipMemcpyHostToDevice, c->stream));
+    if (mixed) esd::launch_cast(D.size, D.v64, D.v32, c->stream);
+    if (D.csize) {
+        HIPCHK(hipMemcpyAsync(D.csptr, K.csptr.data(), sizeof(int64_t) * K.csptr.size(), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipMemcpyAsync(D.soff, K.soff.data(), sizeof(int32_t) * K.soff.size(), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipMemcpyAsync(D.src, K.src.data(), sizeof(int64_t) * K.src.size(), hipMemcpyHostToDevice,
+                              c->stream));
         D.repack(c->stream);
-        HIPCHK(hipStreamSynchronize(c->stream)); // the host copies die here
     }
     return ESD_OK;
 }
 
-void free_ell(DevEll &D) {
-    void *ptrs[] = {D.sptr, D.col, D.v64, D.v32, D.csptr, D.soff, D.src, D.cv64, D.cv32};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    D = DevEll();
-}
-
-int grid_n(const esd_ctx *c) { return esd::grid_for(c->n); }
 
 esd_status sync_read(esd_ctx *c) {
     HIPCHK(hipMemcpyAsync(c->Sh, c->S, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
@@ -232,6 +344,7 @@ template <> VecSet<double> vecs<double>(esd_ctx *c) {
     V.x = c->x; V.r = c->r; V.z = c->z; V.zsc = c->zsc; V.y = c->y; V.q = c->q;
     V.p[0] = c->p[0]; V.p[1] = c->p[1]; V.v[0] = c->v[0]; V.v[1] = c->v[1];
     V.W = c->W; V.AW = c->AW; V.Wrm = c->W_rm; V.AWrm = c->AW_rm; V.dinv = c->dinv; V.lsub = c->lsub;
+    V.Y = c->Y;
     V.A = c->A.it64(); V.L = c->L.it64(); V.U = c->U.it64();
     return V;
 }
@@ -240,6 +353,7 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
     V.x = c->d32; V.r = c->r32; V.z = c->z32; V.zsc = c->zsc32; V.y = c->y32; V.q = c->q32;
     V.p[0] = c->p32[0]; V.p[1] = c->p32[1]; V.v[0] = c->v32[0]; V.v[1] = c->v32[1];
     V.W = c->W32; V.AW = c->AW32; V.Wrm = c->W32_rm; V.AWrm = c->AW32_rm; V.dinv = c->dinv32; V.lsub = c->lsub32;
+    V.Y = c->Y32;
     V.A = c->A.it32(); V.L = c->L.it32(); V.U = c->U.it32();
     return V;
 }
@@ -434,12 +548,25 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     }
     const int sstride = esd::spmv_stride(o.power);
     const int gs = esd::grid_red(n, sstride);
-    const int gu = esd::stream_grid<T>(n); // update launches and their partial rows
     const int nl = (int)c->lvl.size() - 1;
     const bool fuse_l0 = !o.noprec && nl >= 2;
     // block Jacobi without subspace correction: the update kernel also applies
     // the preconditioner to the new residual
     const bool bj_fused = c->bj_rows > 0 && !o.noprec && !sc;
+    // G^T r_{i+1} inside the update launch (m <= 16, not with the fused
+    // block-Jacobi update): the subspace correction's W^T r with G = W, and
+    // the deflation's (AW)^T z = (AW)^T M^{-1} r = (M^{-1} A W)^T r with
+    // G = Y = M^{-1} A W (G = AW without a preconditioner); otherwise a
+    // separate tall-skinny pass over r (W) or z (AW) after the update
+    const T *G = nullptr;
+    if (m > 0 && m <= 16 && !bj_fused) {
+        if (sc) G = V.W;
+        else if (defl) G = o.noprec ? V.AW : (c->y_ok ? V.Y : nullptr);
+    }
+    const int su = esd::update_stride(G ? m : 0); // partial columns of the update launch
+    // update launches and their partial rows (with G^T r: at most 2048 blocks,
+    // so that the finalize reads a short table)
+    const int gu = G ? std::min(esd::stream_grid<T>(n), 2048) : esd::stream_grid<T>(n);
     esd::UpdBj<T> ub{};
     ub.n = n; ub.s = (int)c->bj_rows; ub.nb = c->bj_nb; ub.S = c->S; ub.part = c->part_upd;
     ub.q = V.q; ub.x = V.x; ub.r = V.r; ub.lsub = V.lsub; ub.dinv = V.dinv; ub.z = V.z;
@@ -457,8 +584,9 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     esd::UpdIt<T> ua{};
     ua.n = n; ua.S = c->S; ua.part = c->part_upd; ua.q = V.q; ua.x = V.x; ua.r = V.r; ua.tmap = c->tmap;
     ua.l0 = fuse_l0 ? (int)c->lvl[1] : 0; ua.dinv = V.dinv; ua.y = V.y;
+    ua.G = G; ua.m = G ? m : 0;
     esd::FinRho fr{};
-    fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = 2;
+    fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = su;
     fr.rho_upd = (fuse_l0 && !sc) ? 1 : 0;
     if (bj_fused) {
         fr.nblk_upd = esd::bj_grid(c->bj_nb);
@@ -466,7 +594,11 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
         fr.nsweep = 0;
     }
     fr.part_sweep = c->part_sweep; fr.hist_beta = c->hb; fr.init = 0;
-    fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
+    fr.part_s = c->part_ts; fr.nblk_s = gt; fr.stride_s = st_t; fr.c0_s = 0; fr.m = defl ? m : 0; fr.Cinv = c->Cinv;
+    if (defl && G) {
+        // (AW)^T z_{i+1} = Y^T r_{i+1}: columns 2 .. of the update partials
+        fr.part_s = c->part_upd; fr.nblk_s = gu; fr.stride_s = su; fr.c0_s = 2;
+    }
     if (o.sampling && o.method_b) {
         fr.slot_table = c->slot_table;
         fr.nslots = c->m_req;
@@ -496,14 +628,18 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
             } else {
                 esd::launch_update_it(ua, gu, c->stream);
                 if (sc) {
-                    esd::launch_tsdot_rm(ta, gt, c->stream);
-                    esd::launch_fin_u(c->S, c->part_ts, gt, st_t, m, c->Cinv, c->stream);
+                    if (G) {
+                        esd::launch_fin_u(c->S, c->part_upd, gu, su, 2, m, c->Cinv, c->stream);
+                    } else {
+                        esd::launch_tsdot_rm(ta, gt, c->stream);
+                        esd::launch_fin_u(c->S, c->part_ts, gt, st_t, 0, m, c->Cinv, c->stream);
+                    }
                 }
                 if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 2], c->stream)) != hipSuccess) return e;
                 fr.nsweep = launch_prec<T>(c, V, o.noprec, sc, fuse_l0);
                 if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 3], c->stream)) != hipSuccess) return e;
             }
-            if (defl) esd::launch_tsdot_rm(ta, gt, c->stream);
+            if (defl && !G) esd::launch_tsdot_rm(ta, gt, c->stream);
             esd::launch_fin_rho(fr, c->stream);
             if (defl) {
                 // direction of iteration it + 1
@@ -536,7 +672,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
                           ((uint32_t)o.power << 4) | ((uint32_t)o.sampling << 5) | ((uint32_t)(*vbase & 1) << 6) |
                           ((uint32_t)fuse_l0 << 7) | ((uint32_t)o.resid << 8) | ((uint32_t)o.method_b << 9) |
                           // method B's finalize takes the slot count as an argument
-                          ((uint32_t)((o.sampling && o.method_b) ? c->m_req : 0) << 11);
+                          ((uint32_t)((o.sampling && o.method_b) ? c->m_req : 0) << 11) |
+                          ((uint32_t)(G != nullptr) << 18);
     // the cached graph of `count` iterations of this variant (nullptr: the
     // variant does not capture, stream launches for it)
     auto graph_for = [&](int count) -> hipGraphExec_t {
@@ -662,31 +799,18 @@ esd_status read_history(esd_ctx *c, int total) {
     return ESD_OK;
 }
 
-esd_status ensure_tables(esd_ctx *c, int maxit) {
-    const int64_t need = (int64_t)maxit + 4;
-    if (c->hcap < need) {
-        (void)hipFree(c->ha);
-        (void)hipFree(c->hb);
-        c->ha = c->hb = nullptr;
-        HIPCHK(dalloc(&c->ha, need));
-        HIPCHK(dalloc(&c->hb, need));
-        c->hcap = need;
-        c->epoch++;
-    }
+esd_status ensure_tables(esd_ctx *c, int maxit, bool events) {
+    // the alpha/beta history and the sampling table live in the workspace,
+    // sized by the context's max_iters
+    if ((int64_t)maxit > c->max_iters)
+        return fail(c, ESD_EINVAL, "maxit exceeds the max_iters the workspace was sized for");
     if (c->armed) {
         if (c->samp_method == 0) esd::sampling_table(c->m_req, (int64_t)maxit + 2, c->table_h);
         else c->table_h.assign((size_t)maxit + 2, -1); // method B: slots set on the device
-        if (c->slot_table_cap < (int64_t)c->table_h.size()) {
-            (void)hipFree(c->slot_table);
-            c->slot_table = nullptr;
-            HIPCHK(dalloc(&c->slot_table, (int64_t)c->table_h.size()));
-            c->slot_table_cap = (int64_t)c->table_h.size();
-            c->epoch++;
-        }
         HIPCHK(hipMemcpyAsync(c->slot_table, c->table_h.data(), sizeof(int32_t) * c->table_h.size(),
                               hipMemcpyHostToDevice, c->stream));
     }
-    if ((int)c->ev.size() >= 4 * 32) return ESD_OK;
+    if (!events || (int)c->ev.size() >= 4 * 32) return ESD_OK;
     c->ev.resize(4 * 32);
     // timing-only markers: no system-scope fence (no L2 writeback) at each
     // record, so a pair brackets the kernel rather than the kernel plus a flush
@@ -726,6 +850,7 @@ void clear_sweep_vectors(esd_ctx *c) {
     esd::launch_fill(nv, c->y, 0.0, c->stream);
     esd::launch_fill(nv, c->z, 0.0, c->stream);
     esd::launch_fill(nv, c->zsc, 0.0, c->stream);
+    if (!c->mixed) return;
     esd::launch_fill(nv, c->y32, 0.0f, c->stream);
     esd::launch_fill(nv, c->z32, 0.0f, c->stream);
     esd::launch_fill(nv, c->zsc32, 0.0f, c->stream);
@@ -1088,6 +1213,31 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     return converged ? ESD_OK : ESD_NOT_CONVERGED;
 }
 
+// Y = M^{-1} A W, one column at a time through the preconditioner (FP64
+// factor; FP32 copy for the mixed inner loop), so that the deflated
+// iteration's (AW)^T z = Y^T r can be reduced inside the update launch.
+// Needs the current factor: without it Y stays invalid until factor_ic0.
+esd_status refresh_y(esd_ctx *c) {
+    c->y_ok = false;
+    if (!c->aux_built || c->m_tilde <= 0 || c->m_tilde > 16 || !c->factored) return ESD_OK;
+    const int n = (int)c->n, k = c->m_tilde;
+    auto V = vecs<double>(c);
+    clear_sweep_vectors(c);
+    init_scal(c, 1, 1.0, 0);
+    esd_status st = put_scal(c);
+    if (st) return st;
+    for (int j = 0; j < k; ++j) {
+        HIPCHK(hipMemcpyAsync(c->r, c->AW + (size_t)j * n, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        launch_prec<double>(c, V, false, false);
+        HIPCHK(hipMemcpyAsync(c->Y + (size_t)j * n, c->z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (c->mixed) esd::launch_cast((int64_t)k * n, c->Y, c->Y32, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->y_ok = true;
+    return ESD_OK;
+}
+
 // C = W^T (A W) on the matrix cores, symmetrised; C^{-1} from its Cholesky
 // factor (host, FP64); FP32 copies of W and AW for the mixed inner loop.
 esd_status finish_aux(esd_ctx *c, int k) {
@@ -1104,8 +1254,10 @@ esd_status finish_aux(esd_ctx *c, int k) {
     if (!esd::cholesky_inverse(k, C, Cinv)) return fail(c, ESD_ENOTSPD, "W^T A W is not positive definite");
     c->Ch = C;
     HIPCHK(hipMemcpyAsync(c->Cinv, Cinv.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, c->stream));
-    esd::launch_cast((int64_t)k * n, c->W, c->W32, c->stream);
-    esd::launch_cast((int64_t)k * n, c->AW, c->AW32, c->stream);
+    if (c->mixed) {
+        esd::launch_cast((int64_t)k * n, c->W, c->W32, c->stream);
+        esd::launch_cast((int64_t)k * n, c->AW, c->AW32, c->stream);
+    }
     esd::launch_to_rowmajor(n, k, c->W, c->W_rm, c->W32_rm, c->stream);
     esd::launch_to_rowmajor(n, k, c->AW, c->AW_rm, c->AW32_rm, c->stream);
     HIPCHK(hipGetLastError());
@@ -1113,7 +1265,7 @@ esd_status finish_aux(esd_ctx *c, int k) {
     c->m_tilde = k;
     c->aux_built = true;
     c->epoch++;
-    return ESD_OK;
+    return refresh_y(c);
 }
 
 } // namespace
@@ -1135,6 +1287,7 @@ const char *esd_status_string(esd_status s) {
     case ESD_ENUMERIC: return "non-finite value";
     case ESD_ENOAUX: return "no auxiliary space built";
     case ESD_ENOSAMPLES: return "no samples";
+    case ESD_EWORKSPACE: return "workspace missing, too small or misaligned";
     }
     return "unknown status";
 }
@@ -1143,15 +1296,10 @@ const char *esd_last_error(const esd_ctx *c) { return c ? c->err.c_str() : "null
 
 void esd_destroy(esd_ctx *c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    free_ell(c->A); free_ell(c->L); free_ell(c->U);
-    void *ptrs[] = {c->u_from_l, c->l_orig, c->a_src, c->l_src, c->d_src, c->adiag, c->ldiag, c->dinv, c->dinv32, c->lsub, c->lsub32, c->p2u, c->urp, c->ucol, c->bad,
-                    c->b, c->x, c->r, c->z, c->zsc, c->y, c->q, c->p[0], c->p[1], c->t, c->v[0], c->v[1],
-                    c->r32, c->z32, c->zsc32, c->y32, c->q32, c->p32[0], c->p32[1], c->d32, c->v32[0], c->v32[1],
-                    c->tmap, c->tmap_lvl, c->part_spmv, c->part_upd, c->part_gen, c->part_sweep, c->part_ts, c->W_rm, c->W32_rm, c->AW_rm, c->AW32_rm, c->S, c->slots, c->slot_table, c->xN,
-                    c->E, c->AE, c->ME, c->W, c->AW, c->W32, c->AW32, c->Cinv, c->gram_part, c->G, c->Tm, c->ha, c->hb};
-    for (void *p : ptrs) if (p) hipFree(p);
-    if (c->Sh) hipHostFree(c->Sh);
+    // device memory belongs to the caller's workspace: only the host-side
+    // state, events, graphs and the capture stream are released here
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->Sh) (void)hipHostFree(c->Sh);
     for (auto &e : c->ev) (void)hipEventDestroy(e);
     for (auto &g : c->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -1159,23 +1307,91 @@ void esd_destroy(esd_ctx *c) {
     delete c;
 }
 
+} // extern "C"
+
 namespace {
-esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr, const int32_t *col,
-                      const double *val, const int32_t *colors, int64_t block_rows, int32_t m_max) {
-    if (!out || !rowptr || !col || !val || n <= 0 || m_max < 0 || m_max > esd::kMaxCols) return ESD_EINVAL;
+
+constexpr int64_t kDefaultMaxIters = 100000;
+
+bool options_ok(const esd_options *o) {
+    return o && o->m_max >= 1 && o->m_max <= esd::kMaxCols && o->max_iters >= 0 &&
+           (o->prec == ESD_PREC_FP64 || o->prec == ESD_PREC_MIXED) &&
+           (o->order == ESD_ORDER_NATURAL || o->order == ESD_ORDER_COLORS ||
+            (o->order == ESD_ORDER_BLOCK_JACOBI && o->block_rows >= 1));
+}
+
+int64_t max_iters_of(const esd_options *o) { return o->max_iters > 0 ? o->max_iters : kDefaultMaxIters; }
+
+// Upper bounds of every size for a matrix of n rows, nnz stored entries and
+// at most max_row entries per row: a sorted-layout slice is at most max_row
+// (L, U: max_row - 1) slots wide, a class-aligned copy at most 5/4 of it;
+// a level launch has at most ceil(rows / 256) + 7 blocks and there are at
+// most n levels, and a level of k rows at most ceil(k / 256) tiles.
+Sizes size_bound(int64_t n, int64_t nnz, int64_t max_row, const esd_options *o) {
+    Sizes z;
+    z.n = n;
+    z.nnz = nnz;
+    const int64_t nsl = (n + esd::kSlice - 1) / esd::kSlice;
+    const int64_t wa = std::min<int64_t>(max_row, n), wl = std::max<int64_t>(wa - 1, 0);
+    z.A = {nsl, nsl * esd::kSlice * wa, 0};
+    z.L = {nsl, nsl * esd::kSlice * wl, 0};
+    z.U = z.L;
+    for (EllSizes *e : {&z.A, &z.L, &z.U}) e->csize = e->size / 4 * 5 / esd::kSlice * esd::kSlice + esd::kSlice;
+    const int64_t tiles = (n + esd::kBlock - 1) / esd::kBlock;
+    z.tmap = tiles;
+    z.tmap_lvl = tiles + n;
+    z.sweep_cap = tiles + n + 7 * (n / 2048 + 1) + 8;
+    z.m_max = o->m_max;
+    z.mixed = o->prec == ESD_PREC_MIXED;
+    z.max_iters = max_iters_of(o);
+    return z;
+}
+
+esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, int64_t nnz, const int64_t *rowptr_d,
+                      const int32_t *col_d, const double *val_d, const int32_t *colors_d, const esd_options *opt,
+                      void *workspace, size_t ws_bytes, size_t *ws_needed) {
+    if (ws_needed) *ws_needed = 0;
+    if (!out) return ESD_EINVAL;
     *out = nullptr;
-    esd_ctx *c = new (std::nothrow) esd_ctx();
-    if (!c) return ESD_EINVAL;
-    c->stream = (hipStream_t)hip_stream;
-    c->m_max = m_max;
-    c->trace = std::getenv("ESD_TRACE") != nullptr;
-    esd::HostLayout H;
-    std::string why = esd::build_layout(n, rowptr, col, val, colors, block_rows, H);
-    if (!why.empty()) {
-        fprintf(stderr, "esd_setup: %s\n", why.c_str());
-        delete c;
+    if (!rowptr_d || !col_d || !val_d || n <= 0 || nnz < n || !options_ok(opt)) return ESD_EINVAL;
+    if (opt->order == ESD_ORDER_COLORS && !colors_d) return ESD_EINVAL;
+    if (n >= (int64_t(1) << 31) - 64 || nnz >= (int64_t(1) << 31)) return ESD_EINVAL;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    // the caller's device CSR (and colours) to the host for the analysis
+    std::vector<int64_t> rowptr(n + 1);
+    std::vector<int32_t> col(nnz), colors;
+    std::vector<double> val(nnz);
+    bool hip_ok = hipMemcpyAsync(rowptr.data(), rowptr_d, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost,
+                                 stream) == hipSuccess &&
+                  hipMemcpyAsync(col.data(), col_d, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, stream) ==
+                      hipSuccess &&
+                  hipMemcpyAsync(val.data(), val_d, sizeof(double) * nnz, hipMemcpyDeviceToHost, stream) ==
+                      hipSuccess;
+    if (hip_ok && opt->order == ESD_ORDER_COLORS) {
+        colors.resize(n);
+        hip_ok = hipMemcpyAsync(colors.data(), colors_d, sizeof(int32_t) * n, hipMemcpyDeviceToHost, stream) ==
+                 hipSuccess;
+    }
+    if (!hip_ok || hipStreamSynchronize(stream) != hipSuccess) return ESD_EHIP;
+    if (rowptr[n] != nnz) {
+        fprintf(stderr, "esd_setup: rowptr[n] != nnz\n");
         return ESD_EINVAL;
     }
+    const int64_t block_rows = opt->order == ESD_ORDER_BLOCK_JACOBI ? opt->block_rows : 0;
+    const int32_t *colp = opt->order == ESD_ORDER_COLORS ? colors.data() : nullptr;
+    esd::HostLayout H;
+    std::string why = esd::build_layout(n, rowptr.data(), col.data(), val.data(), colp, block_rows, H);
+    if (!why.empty()) {
+        fprintf(stderr, "esd_setup: %s\n", why.c_str());
+        return ESD_EINVAL;
+    }
+    esd_ctx *c = new (std::nothrow) esd_ctx();
+    if (!c) return ESD_EINVAL;
+    c->stream = stream;
+    c->m_max = opt->m_max;
+    c->mixed = opt->prec == ESD_PREC_MIXED;
+    c->max_iters = max_iters_of(opt);
+    c->trace = std::getenv("ESD_TRACE") != nullptr;
     c->n = n;
     c->nnz = H.nnz;
     c->ncolors = H.ncolors;
@@ -1186,6 +1402,40 @@ esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, const int64_t 
     c->lvl = H.lvl_ptr;
     c->p2u_h = H.p2u;
     c->lperm_h = H.lperm;
+    // class-aligned copies and tile orders on the host, then the exact sizes
+    HostClass KA, KL, KU;
+    const esd::HostEll *ells[3] = {&H.A, &H.L, &H.U};
+    HostClass *ks[3] = {&KA, &KL, &KU};
+    for (int e = 0; e < 3; ++e)
+        if (c->class_layout && !ells[e]->col.empty() &&
+            !esd::ell_classes(*ells[e], n, 64, ks[e]->csptr, ks[e]->soff, ks[e]->src))
+            ks[e]->csptr.clear();
+    std::vector<int32_t> tf, tl;
+    esd::tile_orders(H, colp, esd::kBlock, tf, tl, c->tmap_off);
+    Sizes z;
+    z.n = n;
+    z.nnz = H.nnz;
+    EllSizes *zs[3] = {&z.A, &z.L, &z.U};
+    for (int e = 0; e < 3; ++e) {
+        zs[e]->nsl = (int64_t)ells[e]->sptr.size() - 1;
+        zs[e]->size = (int64_t)ells[e]->col.size();
+        zs[e]->csize = ks[e]->csptr.empty() ? 0 : ks[e]->csptr.back();
+    }
+    z.tmap = (int64_t)tf.size();
+    z.tmap_lvl = (int64_t)tl.size();
+    z.sweep_cap = sweep_slots(n, c->lvl, c->bj_nb);
+    c->sweep_cap = z.sweep_cap;
+    z.m_max = opt->m_max;
+    z.mixed = c->mixed;
+    z.max_iters = c->max_iters;
+    const size_t need = carve(c, z, nullptr);
+    if (ws_needed) *ws_needed = need;
+    if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255)) {
+        delete c;
+        return ESD_EWORKSPACE;
+    }
+    (void)carve(c, z, static_cast<char *>(workspace));
+    c->ws_used = need;
     esd_status st;
 #define SETUP_CHK(x)                                                                               \
     do {                                                                                           \
@@ -1196,96 +1446,40 @@ esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, const int64_t 
     do {                                                                                           \
         if ((x) != hipSuccess) { esd_destroy(c); return ESD_EHIP; }                                \
     } while (0)
-    SETUP_CHK(upload_ell(c, c->A, H.A));
-    SETUP_CHK(upload_ell(c, c->L, H.L));
-    SETUP_CHK(upload_ell(c, c->U, H.U));
-    SETUP_HIP(dalloc(&c->a_src, c->A.size));
-    SETUP_HIP(dalloc(&c->l_src, c->L.size));
-    SETUP_HIP(dalloc(&c->d_src, n));
+    SETUP_CHK(upload_ell(c, c->A, H.A, KA, c->mixed));
+    SETUP_CHK(upload_ell(c, c->L, H.L, KL, c->mixed));
+    SETUP_CHK(upload_ell(c, c->U, H.U, KU, c->mixed));
     if (c->A.size)
         SETUP_HIP(hipMemcpyAsync(c->a_src, H.a_src.data(), sizeof(int32_t) * c->A.size, hipMemcpyHostToDevice, c->stream));
     if (c->L.size)
         SETUP_HIP(hipMemcpyAsync(c->l_src, H.l_src.data(), sizeof(int32_t) * c->L.size, hipMemcpyHostToDevice, c->stream));
     SETUP_HIP(hipMemcpyAsync(c->d_src, H.d_src.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
-    SETUP_HIP(dalloc(&c->l_orig, c->L.size));
     if (c->L.size)
         SETUP_HIP(hipMemcpyAsync(c->l_orig, c->L.v64, sizeof(double) * c->L.size, hipMemcpyDeviceToDevice, c->stream));
-    SETUP_HIP(dalloc(&c->u_from_l, (int64_t)H.u_from_l.size()));
     if (!H.u_from_l.empty())
         SETUP_HIP(hipMemcpyAsync(c->u_from_l, H.u_from_l.data(), sizeof(int64_t) * H.u_from_l.size(),
                                  hipMemcpyHostToDevice, c->stream));
     const int64_t nv = n + 64;
-    SETUP_HIP(dalloc(&c->adiag, nv));
     SETUP_HIP(hipMemcpyAsync(c->adiag, H.adiag.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-    SETUP_HIP(dalloc(&c->ldiag, nv));
-    SETUP_HIP(dalloc(&c->dinv, nv));
-    SETUP_HIP(dalloc(&c->dinv32, nv));
-    SETUP_HIP(dalloc(&c->lsub, nv));
-    SETUP_HIP(dalloc(&c->lsub32, nv));
     esd::launch_fill((int)nv, c->lsub, 0.0, c->stream);
-    esd::launch_fill((int)nv, c->lsub32, 0.0f, c->stream);
-    SETUP_HIP(dalloc(&c->p2u, nv));
+    if (c->mixed) esd::launch_fill((int)nv, c->lsub32, 0.0f, c->stream);
     SETUP_HIP(hipMemcpyAsync(c->p2u, H.p2u.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
-    {
-        std::vector<int32_t> tf, tl;
-        esd::tile_orders(H, colors, esd::kBlock, tf, tl, c->tmap_off);
-        SETUP_HIP(dalloc(&c->tmap, (int64_t)tf.size()));
-        SETUP_HIP(dalloc(&c->tmap_lvl, (int64_t)tl.size()));
-        SETUP_HIP(hipMemcpyAsync(c->tmap, tf.data(), sizeof(int32_t) * tf.size(), hipMemcpyHostToDevice, c->stream));
+    SETUP_HIP(hipMemcpyAsync(c->tmap, tf.data(), sizeof(int32_t) * tf.size(), hipMemcpyHostToDevice, c->stream));
+    if (!tl.empty())
         SETUP_HIP(hipMemcpyAsync(c->tmap_lvl, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, c->stream));
-        // the host vectors die here: finish the copies first
-        SETUP_HIP(hipStreamSynchronize(c->stream));
+    // the pattern in the caller's CSR order, for the gradient
+    SETUP_HIP(hipMemcpyAsync(c->urp, rowptr_d, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, c->stream));
+    SETUP_HIP(hipMemcpyAsync(c->ucol, col_d, sizeof(int32_t) * H.nnz, hipMemcpyDeviceToDevice, c->stream));
+    double *v64[] = {c->b, c->x, c->r, c->z, c->zsc, c->y, c->q, c->p[0], c->p[1], c->t, c->v[0], c->v[1], c->xN};
+    for (double *p : v64) esd::launch_fill((int)nv, p, 0.0, c->stream);
+    if (c->mixed) {
+        float *v32[] = {c->r32, c->z32, c->zsc32, c->y32, c->q32, c->p32[0], c->p32[1], c->d32, c->v32[0], c->v32[1]};
+        for (float *p : v32) esd::launch_fill((int)nv, p, 0.0f, c->stream);
     }
-    SETUP_HIP(dalloc(&c->urp, n + 1));
-    SETUP_HIP(dalloc(&c->ucol, H.nnz));
-    SETUP_HIP(hipMemcpyAsync(c->urp, rowptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, c->stream));
-    SETUP_HIP(hipMemcpyAsync(c->ucol, col, sizeof(int32_t) * H.nnz, hipMemcpyHostToDevice, c->stream));
-    SETUP_HIP(dalloc(&c->bad, 1));
-    double **v64[] = {&c->b, &c->x, &c->r, &c->z, &c->zsc, &c->y, &c->q, &c->p[0], &c->p[1], &c->t, &c->v[0],
-                      &c->v[1]};
-    for (double **p : v64) {
-        SETUP_HIP(dalloc(p, nv));
-        esd::launch_fill((int)nv, *p, 0.0, c->stream);
-    }
-    float **v32[] = {&c->r32, &c->z32, &c->zsc32, &c->y32, &c->q32, &c->p32[0], &c->p32[1], &c->d32, &c->v32[0],
-                     &c->v32[1]};
-    for (float **p : v32) {
-        SETUP_HIP(dalloc(p, nv));
-        esd::launch_fill((int)nv, *p, 0.0f, c->stream);
-    }
-    SETUP_HIP(dalloc(&c->part_spmv, (int64_t)esd::kMaxGrid * esd::kMaxNV));
-    SETUP_HIP(dalloc(&c->part_upd, (int64_t)esd::kMaxGrid * esd::kMaxNV));
-    SETUP_HIP(dalloc(&c->part_gen, (int64_t)esd::kMaxGrid * esd::kMaxNV));
-    SETUP_HIP(dalloc(&c->part_ts, (int64_t)esd::kMaxGrid * esd::kMaxNV));
-    {
-        int64_t cap = esd::grid_red(n, 1);
-        int64_t tot = 0;
-        for (size_t l = 0; l + 1 < c->lvl.size(); ++l) tot += esd::grid_red(c->lvl[l + 1] - c->lvl[l], 1);
-        c->sweep_cap = std::max(cap, tot);
-        if (c->bj_nb > 0) c->sweep_cap = std::max<int64_t>(c->sweep_cap, esd::bj_grid(c->bj_nb));
-        SETUP_HIP(dalloc(&c->part_sweep, c->sweep_cap));
-    }
-    SETUP_HIP(dalloc(&c->S, 1));
     SETUP_HIP(hipMemsetAsync(c->S, 0, sizeof(Scal), c->stream));
     SETUP_HIP(hipHostMalloc((void **)&c->Sh, sizeof(Scal), hipHostMallocDefault));
     std::memset(c->Sh, 0, sizeof(Scal));
-    const int mm = std::max(1, m_max);
-    SETUP_HIP(dalloc(&c->slots, (int64_t)mm * n));
-    SETUP_HIP(dalloc(&c->xN, nv));
-    SETUP_HIP(dalloc(&c->E, (int64_t)mm * n));
-    SETUP_HIP(dalloc(&c->AE, (int64_t)mm * n));
-    SETUP_HIP(dalloc(&c->W, (int64_t)esd::kMaxCols * n));
-    SETUP_HIP(dalloc(&c->AW, (int64_t)esd::kMaxCols * n));
-    SETUP_HIP(dalloc(&c->W32, (int64_t)esd::kMaxCols * n));
-    SETUP_HIP(dalloc(&c->AW32, (int64_t)esd::kMaxCols * n));
-    SETUP_HIP(dalloc(&c->W_rm, (int64_t)esd::kMaxCols * n));
-    SETUP_HIP(dalloc(&c->W32_rm, (int64_t)esd::kMaxCols * n));
-    SETUP_HIP(dalloc(&c->AW_rm, (int64_t)esd::kMaxCols * n));
-    SETUP_HIP(dalloc(&c->AW32_rm, (int64_t)esd::kMaxCols * n));
-    SETUP_HIP(dalloc(&c->Cinv, 64 * 64));
-    SETUP_HIP(dalloc(&c->gram_part, (int64_t)esd::gram_grid((int)n) * 4096));
-    SETUP_HIP(dalloc(&c->G, 64 * 64));
-    SETUP_HIP(dalloc(&c->Tm, 64 * 64));
+    // the host copies die here: finish every transfer first
     if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
         esd_destroy(c);
         return ESD_EHIP;
@@ -1297,15 +1491,24 @@ esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, const int64_t 
 }
 } // namespace
 
-esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr, const int32_t *col,
-                     const double *val, const int32_t *colors, int32_t m_max) {
-    return setup_impl(out, hip_stream, n, rowptr, col, val, colors, 0, m_max);
+extern "C" {
+
+size_t esd_workspace_bytes(int64_t n, int64_t nnz, int32_t max_row, const esd_options *opt) {
+    if (n <= 0 || nnz < n || max_row < 1 || !options_ok(opt)) return 0;
+    esd_ctx probe; // pointers are only counted, never assigned
+    return carve(&probe, size_bound(n, nnz, max_row, opt), nullptr);
 }
 
-esd_status esd_setup_block_jacobi(esd_ctx **out, void *hip_stream, int64_t n, const int64_t *rowptr,
-                                  const int32_t *col, const double *val, int32_t block_rows, int32_t m_max) {
-    if (block_rows < 1) return ESD_EINVAL;
-    return setup_impl(out, hip_stream, n, rowptr, col, val, nullptr, block_rows, m_max);
+esd_status esd_setup(esd_ctx **out, void *hip_stream, int64_t n, int64_t nnz, const int64_t *rowptr,
+                     const int32_t *col, const double *val, const int32_t *colors, const esd_options *opt,
+                     void *workspace, size_t ws_bytes, size_t *ws_needed) {
+    return setup_impl(out, hip_stream, n, nnz, rowptr, col, val, colors, opt, workspace, ws_bytes, ws_needed);
+}
+
+esd_status esd_workspace_used(const esd_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return ESD_EINVAL;
+    *bytes = c->ws_used;
+    return ESD_OK;
 }
 
 
@@ -1327,8 +1530,10 @@ esd_status esd_factor_ic0(esd_ctx *c) {
                                      c->bad, c->stream);
     esd::launch_finish_factor(n, c->ldiag, c->dinv, c->dinv32, c->stream);
     esd::launch_gather_u(c->U.size, c->u_from_l, c->L.v64, c->U.v64, c->stream);
-    esd::launch_cast(c->L.size, c->L.v64, c->L.v32, c->stream);
-    esd::launch_cast(c->U.size, c->U.v64, c->U.v32, c->stream);
+    if (c->mixed) {
+        esd::launch_cast(c->L.size, c->L.v64, c->L.v32, c->stream);
+        esd::launch_cast(c->U.size, c->U.v64, c->U.v32, c->stream);
+    }
     c->L.repack(c->stream);
     c->U.repack(c->stream);
     HIPCHK(hipGetLastError());
@@ -1337,10 +1542,11 @@ esd_status esd_factor_ic0(esd_ctx *c) {
     HIPCHK(hipStreamSynchronize(c->stream));
     if (bad) {
         c->factored = false;
+        c->y_ok = false;
         return fail(c, ESD_ENOTSPD, "IC(0) pivot <= 0");
     }
     c->factored = true;
-    return ESD_OK;
+    return refresh_y(c); // M^{-1} A W for the new factor
 }
 
 esd_status esd_update_values(esd_ctx *c, const double *val) {
@@ -1351,6 +1557,7 @@ esd_status esd_update_values(esd_ctx *c, const double *val) {
     esd::launch_map_values(c->n, c->d_src, val, c->adiag, nullptr, c->stream);
     HIPCHK(hipGetLastError());
     c->factored = false;
+    c->y_ok = false;
     c->lam_last = 0.0;
     if (c->aux_built && c->m_tilde > 0) {
         // keep W, refresh AW = A W and C = W^T A W for the new values
@@ -1403,7 +1610,7 @@ esd_status esd_set_power_start(esd_ctx *c, const double *v0) {
     if (!c || !v0) return ESD_EINVAL;
     const int n = (int)c->n;
     esd::launch_gather(n, c->p2u, v0, c->v[0], c->stream);
-    esd::launch_cast(n, c->v[0], c->v32[0], c->stream);
+    if (c->mixed) esd::launch_cast(n, c->v[0], c->v32[0], c->stream);
     c->vb64 = c->vb32 = 0;
     c->vs64 = c->vs32 = 1.0;
     c->have_v = true;
@@ -1411,18 +1618,23 @@ esd_status esd_set_power_start(esd_ctx *c, const double *v0) {
     return ESD_OK;
 }
 
-esd_status esd_solve(esd_ctx *c, const double *b, const double *x0, double tol, int32_t maxit, int32_t mode,
-                     int32_t flags, double *x, esd_info *info) {
+} // extern "C"
+
+namespace {
+esd_status solve_entry(esd_ctx *c, const double *b, const double *x0, double tol, int32_t maxit, int32_t mode,
+                       int32_t flags, double *x, esd_info *info) {
     if (!c || !b || !x || maxit < 0 || !(tol >= 0) || mode < 0 || mode > 2) return ESD_EINVAL;
     if (!c->factored && !(flags & ESD_FLAG_NOPREC)) return fail(c, ESD_EINVAL, "factor_ic0 not called");
     if ((flags & ESD_FLAG_POWER) && !c->have_v) return fail(c, ESD_EINVAL, "power start vector not set");
+    if ((flags & ESD_FLAG_MIXED) && !c->mixed)
+        return fail(c, ESD_EINVAL, "ESD_FLAG_MIXED needs a context set up with ESD_PREC_MIXED");
     esd_status warn = ESD_OK;
     int kind = mode;
     if (mode != ESD_PLAIN) {
         if (!c->aux_built) return fail(c, ESD_ENOAUX, "no auxiliary space: call build_aux or set_aux");
         if (c->m_tilde == 0) { kind = ESD_PLAIN; warn = ESD_AUX_EMPTY; }
     }
-    esd_status st = ensure_tables(c, maxit);
+    esd_status st = ensure_tables(c, maxit, (flags & kFlagTiming) != 0);
     if (st) return st;
     if (flags & kFlagTiming) { c->t_spmv = c->t_sweep = c->t_upd = 0; c->t_count = 0; }
     esd_info tmp{};
@@ -1449,6 +1661,14 @@ esd_status esd_solve(esd_ctx *c, const double *b, const double *x0, double tol, 
     if (st == ESD_OK && warn != ESD_OK) return warn;
     return st;
 }
+} // namespace
+
+extern "C" {
+
+esd_status esd_solve(esd_ctx *c, const double *b, const double *x0, double tol, int32_t maxit, int32_t mode,
+                     int32_t flags, double *x, esd_info *info) {
+    return solve_entry(c, b, x0, tol, maxit, mode, flags, x, info);
+}
 
 esd_status esd_sequence_rhs(esd_ctx *c, const double *f, const double *xprev, double cc, double *b) {
     if (!c || !f || !b) return ESD_EINVAL;
@@ -1462,6 +1682,15 @@ esd_status esd_grad_values(esd_ctx *c, const double *lam, const double *x, doubl
     esd::launch_grad((int)c->n, c->urp, c->ucol, lam, x, gval, c->stream);
     HIPCHK(hipGetLastError()); // device output only: ordered on the stream, no synchronisation
     return ESD_OK;
+}
+
+esd_status esd_hbm_probe(void *hip_stream, int32_t kind, const double *src, double *dst, int64_t n, int32_t grid) {
+    if ((kind != ESD_PROBE_COPY && kind != ESD_PROBE_READ) || !src || !dst || n < 2 || (n & 1) ||
+        ((uintptr_t)src & 15) || ((uintptr_t)dst & 15) || grid < 0 || grid > 65536)
+        return ESD_EINVAL;
+    esd::launch_probe(kind == ESD_PROBE_COPY ? 0 : 1, src, dst, n, grid > 0 ? grid : 4096,
+                      (hipStream_t)hip_stream);
+    return hipGetLastError() == hipSuccess ? ESD_OK : ESD_EHIP;
 }
 
 esd_status esd_spmv(esd_ctx *c, const double *x, double *y) {
@@ -1559,12 +1788,13 @@ esd_status esd_get_timing(esd_ctx *c, double *out4) {
 esd_status esd_build_aux(esd_ctx *c, double theta, double *ritz, int32_t *m_bar, int32_t *m_tilde) {
     if (!c) return ESD_EINVAL;
     if (!c->have_samples) return fail(c, ESD_ENOSAMPLES, "no sampling solve before build_aux");
-    const int n = (int)c->n, g = grid_n(c);
+    const int n = (int)c->n;
     std::vector<int> order;
     for (int s = 0; s < (int)c->slot_iter.size(); ++s)
         if (c->slot_iter[s] > 0) order.push_back(s);
     std::sort(order.begin(), order.end(), [&](int a, int b) { return c->slot_iter[a] < c->slot_iter[b]; });
     c->aux_built = false;
+    c->y_ok = false;
     c->m_tilde = 0;
     int kept = 0;
     esd_status st;
@@ -1616,12 +1846,13 @@ esd_status esd_build_aux(esd_ctx *c, double theta, double *ritz, int32_t *m_bar,
         // preconditioned matrix (footnote of eq. (Rayleigh-Ritz)) in the M
         // inner product: G t = lambda B t with B = E^T M E, M e = L (L^T e)
         if (!c->factored) return fail(c, ESD_EINVAL, "Rayleigh-Ritz on M^{-1}A needs the IC(0) factor");
-        if (!c->ME) HIPCHK(dalloc(&c->ME, (int64_t)c->m_max * n));
+        // M E goes to W's buffer (m_max columns, rebuilt from E below)
+        double *ME = c->W;
         for (int j = 0; j < kept; ++j) {
             esd::launch_tri_mul(n, c->U.e64(), c->ldiag, c->E + (size_t)j * n, c->t, c->stream);
-            esd::launch_tri_mul(n, c->L.e64(), c->ldiag, c->t, c->ME + (size_t)j * n, c->stream);
+            esd::launch_tri_mul(n, c->L.e64(), c->ldiag, c->t, ME + (size_t)j * n, c->stream);
         }
-        esd::launch_gram(n, c->E, kept, c->ME, kept, c->gram_part, c->G, esd::gram_grid(n), c->stream);
+        esd::launch_gram(n, c->E, kept, ME, kept, c->gram_part, c->G, esd::gram_grid(n), c->stream);
         std::vector<double> B((size_t)kept * kept);
         HIPCHK(hipMemcpyAsync(B.data(), c->G, sizeof(double) * kept * kept, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -1660,7 +1891,8 @@ esd_status esd_set_rayleigh_ritz(esd_ctx *c, int32_t op) {
 }
 
 esd_status esd_set_aux(esd_ctx *c, const double *W, int32_t k) {
-    if (!c || !W || k < 1 || k > esd::kMaxCols) return ESD_EINVAL;
+    if (!c || !W) return ESD_EINVAL;
+    if (k < 1 || k > c->m_max) return fail(c, ESD_EINVAL, "k must be in [1, m_max]");
     const int n = (int)c->n;
     for (int j = 0; j < k; ++j) esd::launch_gather(n, c->p2u, W + (size_t)j * n, c->W + (size_t)j * n, c->stream);
     esd::launch_spmm(n, c->A.e64(), c->W, k, c->AW, c->stream);
@@ -1668,6 +1900,7 @@ esd_status esd_set_aux(esd_ctx *c, const double *W, int32_t k) {
     c->ritz.clear();
     c->m_bar = k;
     c->aux_built = false;
+    c->y_ok = false;
     return finish_aux(c, k);
 }
 

@@ -95,8 +95,16 @@ template <typename T> struct UpdIt {
     const T *dinv;
     T *y;
     const int32_t *tmap; // tile order (nullptr: natural)
-    // partials: column 0 ||r||^2, column 1 ||y||^2 of the fused level-0 rows
+    // optional G^T r of the new residual (G column-major n x m, m <= 16):
+    // G = M^{-1} A W gives the deflation's (AW)^T z = G^T r, G = W the
+    // subspace correction's W^T r, without a separate pass over z or r
+    const T *G;
+    int m;
+    // partials: column 0 ||r||^2, column 1 ||y||^2 of the fused level-0 rows,
+    // columns 2 .. 2 + m of G^T r (row stride update_stride(m))
 };
+// partial columns of an update launch with G^T r of m columns (m = 0: none)
+inline int update_stride(int m) { return m <= 0 ? 2 : (m <= 8 ? 10 : 18); }
 
 // Tall-skinny s = W^T v with W row-major (n x m, W[i m + k]): lane t of a
 // wavefront owns column t % P and row offset t / P (P = next power of two
@@ -181,8 +189,8 @@ struct FinRho {
     double *hist_beta;
     int init; // 1: first preconditioner application of a solve (only rho);
               // 2: after a residual replacement (rho and beta of the new residual)
-    const double *part_s; // (AW)^T z partials (deflated), nblk_s x stride_s
-    int nblk_s, stride_s, m;
+    const double *part_s; // (AW)^T z partials (deflated), nblk_s x stride_s, columns c0_s ..
+    int nblk_s, stride_s, c0_s, m;
     const double *Cinv;
     int32_t *slot_table;  // sampling method B: slot of the next store, set here (nullptr: none)
     int nslots;
@@ -255,7 +263,9 @@ int launch_update_bj(const UpdBj<float> &a, hipStream_t s);
 void launch_copyz(const Sweep<double> &a, bool sc, int grid, hipStream_t s);
 void launch_copyz(const Sweep<float> &a, bool sc, int grid, hipStream_t s);
 void launch_fin_alpha(const FinAlpha &f, hipStream_t s);
-void launch_fin_u(Scal *S, const double *part, int nblk, int stride, int m, const double *Cinv, hipStream_t s);
+// u = C^{-1} s with s = columns c0 .. c0 + m of a partial table
+void launch_fin_u(Scal *S, const double *part, int nblk, int stride, int c0, int m, const double *Cinv,
+                  hipStream_t s);
 void launch_fin_rho(const FinRho &f, hipStream_t s);
 void launch_fin_gen(const FinGen &f, hipStream_t s);
 // stride of the partial rows of the iteration kernels
@@ -324,6 +334,11 @@ void launch_tsgemm(int n, const double *X, int ma, const double *T, int mb, doub
 // gradient with respect to stored values: g[k] = -lam[row k] x[col k] (user CSR)
 void launch_grad(int n, const int64_t *rowptr, const int32_t *col, const double *lam,
                  const double *x, double *g, hipStream_t s);
+
+// streaming probes (not part of the method): kind 0 copies n doubles src ->
+// dst, kind 1 sums them (one partial per block into dst); n even, 16-byte
+// aligned pointers
+void launch_probe(int kind, const double *src, double *dst, int64_t n, int grid, hipStream_t s);
 
 // a level of more tiles than one round of resident wavefronts (8 per SIMD
 // on 256 CUs: 2048 blocks of kBlock threads) runs two rows per thread

@@ -85,7 +85,7 @@ __device__ void fin_colsums(const ColTab (&tab)[NTAB]) {
     static_assert(NTAB >= 1 && NTAB <= 4, "at most four tables");
     __shared__ double red[kFinThreads / 64][64];
     const int slot = threadIdx.x / NT, t = threadIdx.x % NT;
-    const int lane = threadIdx.x & 63, wv = t >> 6;
+    const int lane = threadIdx.x & 63;
     ColTab T = tab[0];
 #pragma unroll
     for (int q = 1; q < NTAB; ++q)
@@ -288,18 +288,28 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
 }
 
 // x += alpha p, r -= alpha q, ||r||^2; rows of the first sweep level (i < l0)
-// also take y = r / l_ii and ||y||^2 (the level-0 forward sweep fused here)
-template <typename T>
+// also take y = r / l_ii and ||y||^2 (the level-0 forward sweep fused here);
+// MT > 0: also G^T r of the new residual (G column-major, a.m <= MT columns,
+// one coalesced load per column)
+template <typename T, int MT>
 __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
     const T ta = (T)S->alpha;
-    double acc[2] = {0.0, 0.0};
+    constexpr int NV = MT > 0 ? 2 + MT : 2;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
     const int n = a.n;
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= n) continue;
+        T g[MT > 0 ? MT : 1];
+        if constexpr (MT > 0) {
+#pragma unroll
+            for (int k = 0; k < MT; ++k) g[k] = (k < a.m) ? a.G[(size_t)k * n + i] : T(0);
+        }
         a.x[i] += ta * a.p[i];
         const T ri = a.r[i] - ta * a.q[i];
         a.r[i] = ri;
@@ -309,8 +319,12 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
             a.y[i] = yi;
             acc[1] += (double)yi * (double)yi;
         }
+        if constexpr (MT > 0) {
+#pragma unroll
+            for (int k = 0; k < MT; ++k) acc[2 + k] += (double)g[k] * (double)ri;
+        }
     }
-    block_partials<2>(acc, a.part, 2);
+    block_partials<NV>(acc, a.part, NV);
 }
 
 // FP32 vector update (plain / projected form) with two rows per thread, tiles
@@ -318,18 +332,22 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
 // row moves half the bytes of an FP64 one per load instruction, so one row
 // per thread leaves the FP32 streams short of loads in flight.  Same
 // arithmetic per row as k_update_it.
-template <typename T>
+template <typename T, int MT>
 __global__ __launch_bounds__(kBlock) void k_update_it2(UpdIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
     const T ta = (T)S->alpha;
-    double acc[2] = {0.0, 0.0};
+    constexpr int NV = MT > 0 ? 2 + MT : 2;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
     const int n = a.n;
     const Tiles tl = my_tiles(n);
     for (int t = tl.t0; t < tl.t1; t += 2) {
         int i[2];
         bool h[2];
         T qv[2], pv[2], xv[2], rv[2], dv[2];
+        T g[2][MT > 0 ? MT : 1];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int tt = t + u;
@@ -340,6 +358,10 @@ __global__ __launch_bounds__(kBlock) void k_update_it2(UpdIt<T> a) {
             xv[u] = h[u] ? a.x[i[u]] : T(0);
             rv[u] = h[u] ? a.r[i[u]] : T(0);
             dv[u] = (h[u] && i[u] < a.l0) ? a.dinv[i[u]] : T(0);
+            if constexpr (MT > 0) {
+#pragma unroll
+                for (int k = 0; k < MT; ++k) g[u][k] = (h[u] && k < a.m) ? a.G[(size_t)k * n + i[u]] : T(0);
+            }
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -353,9 +375,13 @@ __global__ __launch_bounds__(kBlock) void k_update_it2(UpdIt<T> a) {
                 a.y[i[u]] = yi;
                 acc[1] += (double)yi * (double)yi;
             }
+            if constexpr (MT > 0) {
+#pragma unroll
+                for (int k = 0; k < MT; ++k) acc[2 + k] += (double)g[u][k] * (double)ri;
+            }
         }
     }
-    block_partials<2>(acc, a.part, 2);
+    block_partials<NV>(acc, a.part, NV);
 }
 
 // s = W^T v, W row-major n x m; P = next power of two >= m.  Lane l of a
@@ -398,7 +424,7 @@ __global__ void k_to_rowmajor(int n, int m, const double *W, double *Wrm, float 
     for (int k = 0; k < m; ++k) {
         const double v = W[(size_t)k * n + i];
         Wrm[(size_t)i * m + k] = v;
-        Wrm32[(size_t)i * m + k] = (float)v;
+        if (Wrm32) Wrm32[(size_t)i * m + k] = (float)v;
     }
 }
 
@@ -812,11 +838,11 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(FinAlpha f) {
     }
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_fin_u(Scal *S, const double *part, int nblk, int stride, int m,
-                                                       const double *Cinv) {
+__global__ __launch_bounds__(kFinThreads) void k_fin_u(Scal *S, const double *part, int nblk, int stride, int c0,
+                                                       int m, const double *Cinv) {
     if (S->done) return;
     __shared__ double tot[64];
-    fin_colsum(part, nblk, stride, 0, m, tot);
+    fin_colsum(part, nblk, stride, c0, m, tot);
     const int t = threadIdx.x;
     if (t < m) {
         double acc = 0.0;
@@ -851,7 +877,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
         if (f.m > 0) {
             const ColTab tab[3] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 2},
                                    {f.part_upd, nu, f.stride_upd, 0, 2, tot + 0},
-                                   {f.part_s, f.nblk_s, f.stride_s, 0, f.m, sv}};
+                                   {f.part_s, f.nblk_s, f.stride_s, f.c0_s, f.m, sv}};
             fin_colsums<3>(tab);
         } else {
             const ColTab tab[2] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 2},
@@ -1029,7 +1055,7 @@ __global__ void k_repack(int64_t size, const int64_t *src, const double *from, d
     const int64_t j = src[e];
     const double v = j >= 0 ? from[j] : 0.0;
     to64[e] = v;
-    to32[e] = (float)v;
+    if (to32) to32[e] = (float)v;
 }
 
 __global__ void k_gather(int n, const int32_t *idx, const double *src, double *dst) {
@@ -1224,7 +1250,7 @@ __global__ void k_finish_factor(int n, const double *ldiag, double *dinv, float 
     if (i < n) {
         const double d = 1.0 / ldiag[i];
         dinv[i] = d;
-        dinv32[i] = (float)d;
+        if (dinv32) dinv32[i] = (float)d;
     }
 }
 
@@ -1258,7 +1284,7 @@ __global__ void k_factor_bj(int n, int s, Ell<double> L, double *lval, const dou
         dprev = sqrt(d);
         ldiag[p] = dprev;
         lsub[p] = l;
-        lsub32[p] = (float)l;
+        if (lsub32) lsub32[p] = (float)l;
     }
 }
 
@@ -1497,9 +1523,14 @@ template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, bool power, i
 void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 
+template <typename T, int MT> static void update_it_mt(const UpdIt<T> &a, int grid, hipStream_t s) {
+    if (stream_pairs<T>(a.n)) k_update_it2<T, MT><<<grid, kBlock, 0, s>>>(a);
+    else k_update_it<T, MT><<<grid, kBlock, 0, s>>>(a);
+}
 template <typename T> static void update_it_impl(const UpdIt<T> &a, int grid, hipStream_t s) {
-    if (stream_pairs<T>(a.n)) k_update_it2<T><<<grid, kBlock, 0, s>>>(a);
-    else k_update_it<T><<<grid, kBlock, 0, s>>>(a);
+    if (!a.G || a.m <= 0) update_it_mt<T, 0>(a, grid, s);
+    else if (a.m <= 8) update_it_mt<T, 8>(a, grid, s);
+    else update_it_mt<T, 16>(a, grid, s);
 }
 void launch_update_it(const UpdIt<double> &a, int grid, hipStream_t s) { update_it_impl(a, grid, s); }
 void launch_update_it(const UpdIt<float> &a, int grid, hipStream_t s) { update_it_impl(a, grid, s); }
@@ -1600,8 +1631,9 @@ void launch_copyz(const Sweep<double> &a, bool sc, int grid, hipStream_t s) { co
 void launch_copyz(const Sweep<float> &a, bool sc, int grid, hipStream_t s) { copyz_impl(a, sc, grid, s); }
 
 void launch_fin_alpha(const FinAlpha &f, hipStream_t s) { k_fin_alpha<<<1, kFinThreads, 0, s>>>(f); }
-void launch_fin_u(Scal *S, const double *part, int nblk, int stride, int m, const double *Cinv, hipStream_t s) {
-    k_fin_u<<<1, kFinThreads, 0, s>>>(S, part, nblk, stride, m, Cinv);
+void launch_fin_u(Scal *S, const double *part, int nblk, int stride, int c0, int m, const double *Cinv,
+                  hipStream_t s) {
+    k_fin_u<<<1, kFinThreads, 0, s>>>(S, part, nblk, stride, c0, m, Cinv);
 }
 void launch_fin_rho(const FinRho &f, hipStream_t s) { k_fin_rho<<<1, kFinThreads, 0, s>>>(f); }
 void launch_fin_gen(const FinGen &f, hipStream_t s) { k_fin_gen<<<1, kFinThreads, 0, s>>>(f); }
@@ -1720,6 +1752,42 @@ void launch_tsgemm(int n, const double *X, int ma, const double *T, int mb, doub
 void launch_grad(int n, const int64_t *rowptr, const int32_t *col, const double *lam, const double *x, double *g,
                  hipStream_t s) {
     k_grad<<<blocks(n), kBlock, 0, s>>>(n, rowptr, col, lam, x, g);
+}
+
+// ---- streaming probes of the achievable HBM bandwidth (not part of the method)
+// Grid-stride over 16-byte vectors, consecutive lanes on consecutive vectors
+// (one 1 KB coalesced access per wavefront and load), four independent loads
+// in flight per thread before any store or add.
+__global__ __launch_bounds__(kBlock) void k_probe_copy(const double2 *__restrict__ src, double2 *__restrict__ dst,
+                                                        int64_t n2) {
+    const int64_t st = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * st < n2; i += 4 * st) {
+        const double2 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
+        dst[i] = a;
+        dst[i + st] = b;
+        dst[i + 2 * st] = c;
+        dst[i + 3 * st] = d;
+    }
+    for (; i < n2; i += st) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_probe_read(const double2 *__restrict__ src, int64_t n2, double *part) {
+    const int64_t st = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double acc[1] = {0.0};
+    for (; i + 3 * st < n2; i += 4 * st) {
+        const double2 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
+        acc[0] += ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
+    }
+    for (; i < n2; i += st) acc[0] += src[i].x + src[i].y;
+    block_partials<1>(acc, part, 1);
+}
+
+void launch_probe(int kind, const double *src, double *dst, int64_t n, int grid, hipStream_t s) {
+    const int64_t n2 = n / 2;
+    if (kind == 0) k_probe_copy<<<grid, kBlock, 0, s>>>((const double2 *)src, (double2 *)dst, n2);
+    else k_probe_read<<<grid, kBlock, 0, s>>>((const double2 *)src, n2, dst);
 }
 
 } // namespace esd

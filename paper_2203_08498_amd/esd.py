@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import time
 
 import numpy as np
 
@@ -22,7 +23,15 @@ FLAG_MIXED_KEEP = 256
 SAMPLING_A, SAMPLING_B, SAMPLE_RESIDUALS = 0, 1, 16
 RR_A, RR_PRECONDITIONED = 0, 1
 OK, NOT_CONVERGED, AUX_EMPTY = 0, 1, 2
-EINVAL, ENOTSPD, EHIP, ENUMERIC, ENOAUX, ENOSAMPLES = -1, -2, -3, -4, -5, -6
+EINVAL, ENOTSPD, EHIP, ENUMERIC, ENOAUX, ENOSAMPLES, EWORKSPACE = -1, -2, -3, -4, -5, -6, -7
+ORDER_NATURAL, ORDER_COLORS, ORDER_BLOCK_JACOBI = 0, 1, 2
+PROBE_COPY, PROBE_READ = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class EsdOptions(C.Structure):
+    _fields_ = [("order", C.c_int32), ("block_rows", C.c_int32), ("prec", C.c_int32), ("m_max", C.c_int32),
+                ("max_iters", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class EsdInfo(C.Structure):
@@ -40,8 +49,8 @@ class EsdInfo(C.Structure):
 
 
 EXPORTS = [
-    "esd_setup", "esd_setup_block_jacobi", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
-    "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
+    "esd_workspace_bytes", "esd_setup", "esd_workspace_used", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
+    "esd_hbm_probe", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
     "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag", "esd_get_history", "esd_get_samples",
     "esd_get_sample_vector", "esd_set_rayleigh_ritz",
     "esd_get_layout", "esd_get_timing", "esd_status_string", "esd_last_error", "esd_destroy",
@@ -60,8 +69,13 @@ def load_library(path: str = LIB_PATH):
                            "python paper_2203_08498_amd/build.py): %s" % path)
     L = C.CDLL(path)
     P, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
-    L.esd_setup.argtypes = [C.POINTER(P), P, i64, P, P, P, P, i32]
-    L.esd_setup_block_jacobi.argtypes = [C.POINTER(P), P, i64, P, P, P, i32, i32]
+    L.esd_workspace_bytes.argtypes = [i64, i64, i32, C.POINTER(EsdOptions)]
+    L.esd_workspace_bytes.restype = C.c_size_t
+    L.esd_setup.argtypes = [C.POINTER(P), P, i64, i64, P, P, P, P, C.POINTER(EsdOptions), P, C.c_size_t,
+                            C.POINTER(C.c_size_t)]
+    L.esd_workspace_used.argtypes = [P, C.POINTER(C.c_size_t)]
+    L.esd_hbm_probe.argtypes = [P, i32, P, P, i64, i32]
+    L.esd_hbm_probe.restype = C.c_int
     L.esd_factor_ic0.argtypes = [P]
     L.esd_update_values.argtypes = [P, P]
     L.esd_sample_errors.argtypes = [P, i32, i32]
@@ -89,7 +103,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_last_error.argtypes = [P]
     L.esd_last_error.restype = C.c_char_p
     L.esd_destroy.argtypes = [P]
-    for name in ("esd_setup", "esd_setup_block_jacobi", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
+    for name in ("esd_setup", "esd_workspace_used", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
                  "esd_set_aux",
                  "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs",
                  "esd_grad_values", "esd_spmv", "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag",
@@ -114,13 +128,32 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-class Solver:
-    """One SPD matrix on the GPU: ordering, IC(0) factor, auxiliary space W."""
+def options(order=ORDER_COLORS, block_rows=0, prec=PREC_MIXED, m_max=16, max_iters=0):
+    o = EsdOptions()
+    o.order, o.block_rows, o.prec, o.m_max, o.max_iters = int(order), int(block_rows), int(prec), int(m_max), \
+        int(max_iters)
+    return o
 
-    def __init__(self, rowptr, col, val, colors=None, m_max: int = 16, device="cuda:0", block_rows=None):
+
+def workspace_bytes(n, nnz, max_row, opt):
+    """esd_workspace_bytes: upper bound of the device workspace esd_setup needs."""
+    return int(load_library().esd_workspace_bytes(int(n), int(nnz), int(max_row), C.byref(opt)))
+
+
+class Solver:
+    """One SPD matrix on the GPU: ordering, IC(0) factor, auxiliary space W.
+
+    The device workspace is a torch uint8 tensor sized by esd_workspace_bytes
+    (held by this object for the context's life); the CSR is handed to
+    esd_setup as device tensors and dropped afterwards."""
+
+    def __init__(self, rowptr, col, val, colors=None, m_max: int = 16, device="cuda:0", block_rows=None,
+                 precision: str = "mixed", max_iters: int = 100000):
         """colors: ordering by a stable sort on colour (None: natural order).
-        block_rows: block-Jacobi IC(0) (Sec. 5.3) with tridiagonal blocks of
-        that many consecutive rows (natural order; colors must be None)."""
+        block_rows: block-Jacobi IC(0) (Sec. 5.3) with blocks of that many
+        consecutive rows (natural order; colors must be None).
+        precision: "mixed" keeps FP32 copies for ESD_FLAG_MIXED, "fp64" does not.
+        max_iters: the largest maxit a solve may use."""
         import torch
 
         if not torch.cuda.is_available():
@@ -128,30 +161,46 @@ class Solver:
         self.torch = torch
         self.device = torch.device(device)
         self.L = load_library()
-        self.rowptr = _np(rowptr, np.int64)
-        self.col = _np(col, np.int32)
-        self.val = _np(val, np.float64)
-        self.colors = None if colors is None else _np(colors, np.int32)
-        self.n = self.rowptr.shape[0] - 1
-        self.nnz = int(self.rowptr[-1])
+        rowptr = _np(rowptr, np.int64)
+        self.n = rowptr.shape[0] - 1
+        self.nnz = int(rowptr[-1])
         self.m_max = m_max
         self.block_rows = block_rows
         if block_rows is not None and colors is not None:
             raise ValueError("block Jacobi keeps the natural order: pass colors=None")
+        if precision not in ("mixed", "fp64"):
+            raise ValueError("precision is 'mixed' or 'fp64'")
+        if block_rows is not None:
+            order = ORDER_BLOCK_JACOBI
+        else:
+            order = ORDER_NATURAL if colors is None else ORDER_COLORS
+        self.opt = options(order, 0 if block_rows is None else block_rows,
+                           PREC_MIXED if precision == "mixed" else PREC_FP64, m_max, max_iters)
+        max_row = int(np.diff(rowptr).max()) if self.n > 0 else 1
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
+            dev = dict(device=self.device)
+            rp = torch.as_tensor(rowptr, **dev)
+            cl = torch.as_tensor(_np(col, np.int32), **dev)
+            vl = torch.as_tensor(_np(val, np.float64), **dev)
+            co = None if colors is None else torch.as_tensor(_np(colors, np.int32), **dev)
+            nbytes = self.L.esd_workspace_bytes(self.n, self.nnz, max_row, C.byref(self.opt))
+            if nbytes == 0:
+                raise EsdError(EINVAL, "invalid setup arguments")
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, **dev)
             h = C.c_void_p()
-            args = (C.byref(h), C.c_void_p(self.stream.cuda_stream), self.n,
-                    self.rowptr.ctypes.data_as(C.c_void_p), self.col.ctypes.data_as(C.c_void_p),
-                    self.val.ctypes.data_as(C.c_void_p))
-            if block_rows is None:
-                st = self.L.esd_setup(*args, None if self.colors is None else self.colors.ctypes.data_as(C.c_void_p),
-                                      int(m_max))
-            else:
-                st = self.L.esd_setup_block_jacobi(*args, int(block_rows), int(m_max))
+            need = C.c_size_t()
+            torch.cuda.synchronize(self.device)
+            t0 = time.perf_counter()
+            st = self.L.esd_setup(C.byref(h), C.c_void_p(self.stream.cuda_stream), self.n, self.nnz, _dptr(rp),
+                                  _dptr(cl), _dptr(vl), None if co is None else _dptr(co), C.byref(self.opt),
+                                  _dptr(self.workspace), nbytes, C.byref(need))
+            self.setup_s = time.perf_counter() - t0  # esd_setup synchronises before returning
+            del rp, cl, vl, co
         if st != 0:
             raise EsdError(st, self.L.esd_status_string(st).decode())
         self.h = h
+        self.ws_needed = need.value
 
     @classmethod
     def from_problem(cls, prob, m_max=None, block_rows=None, **kw):
@@ -177,6 +226,7 @@ class Solver:
             self.torch.cuda.synchronize(self.device)
             self.L.esd_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -257,7 +307,7 @@ class Solver:
         x = out if out is not None else self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
         info = EsdInfo()
         st = self.L.esd_solve(self.h, _dptr(b), None if x0 is None else _dptr(x0), float(tol), int(maxit),
-                              int(mode), int(flags), _dptr(x), C.byref(info))
+                int(mode), int(flags), _dptr(x), C.byref(info))
         if st < 0:
             raise EsdError(st, self.L.esd_last_error(self.h).decode())
         d = info.as_dict()
@@ -335,6 +385,11 @@ class Solver:
         self._check(self.L.esd_get_sample_vector(self.h, int(slot), _dptr(out)))
         return out
 
+    def workspace_used(self):
+        out = C.c_size_t()
+        self._check(self.L.esd_workspace_used(self.h, C.byref(out)))
+        return int(out.value)
+
     def layout(self):
         out = np.zeros(8, np.int32)
         self._check(self.L.esd_get_layout(self.h, out.ctypes.data_as(C.c_void_p)))
@@ -345,3 +400,14 @@ class Solver:
         out = np.zeros(4)
         self._check(self.L.esd_get_timing(self.h, out.ctypes.data_as(C.c_void_p)))
         return dict(spmv_ms=out[0], sweep_ms=out[1], update_ms=out[2], iters=int(out[3]))
+
+
+def hbm_probe(kind, src, dst, grid=0, stream=None):
+    """esd_hbm_probe on torch float64 CUDA tensors (enqueued, no sync)."""
+    import torch
+
+    st = torch.cuda.current_stream() if stream is None else stream
+    r = load_library().esd_hbm_probe(C.c_void_p(st.cuda_stream), int(kind), _dptr(src), _dptr(dst),
+                                     int(src.numel()), int(grid))
+    if r != 0:
+        raise EsdError(r, "bad probe arguments")

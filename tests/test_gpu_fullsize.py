@@ -93,7 +93,7 @@ def test_config2_full_parity_sampling_build_deflated():
           i4["true_relres"], "err vs FP64 oracle", _relerr(x4, y2), "FP64 gpu err", _relerr(x2, y2), flush=True)
     assert i4["true_relres"] <= 1.01e-8
     # regression guard: measured 3.1e-10 at this size (the kappa bound is far looser)
-    assert _relerr(x4, y2) <= 1e-7
+    assert _relerr(x4, y2) <= 3e-9
     # residual replacement (one continued FP32 run) on the same system, both forms
     _, i6 = s.solve(b2, tol=1e-8, maxit=20000, mode=esd.PLAIN)
     fp64_its = {esd.DEFLATED: i2["iters"], esd.PLAIN: i6["iters"]}

@@ -83,6 +83,94 @@ def case(request):
     s.close()
 
 
+def _raw_setup(p, s, ws, nbytes, need):
+    """esd_setup through the C ABI with the caller's device CSR and a given
+    workspace pointer / size; returns (status, handle)."""
+    import ctypes
+
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    dev = s.device
+    rp = torch.as_tensor(np.asarray(p.rowptr, np.int64), device=dev)
+    cl = torch.as_tensor(np.asarray(p.col, np.int32), device=dev)
+    vl = torch.as_tensor(np.asarray(p.val, np.float64), device=dev)
+    co = None if p.colors is None or _bj(p) else torch.as_tensor(np.asarray(p.colors, np.int32), device=dev)
+    h = ctypes.c_void_p()
+    st = s.L.esd_setup(ctypes.byref(h), ctypes.c_void_p(s.stream.cuda_stream), p.n, p.nnz, esd._dptr(rp),
+                       esd._dptr(cl), esd._dptr(vl), None if co is None else esd._dptr(co), ctypes.byref(s.opt),
+                       ws, nbytes, ctypes.byref(need))
+    return st, h
+
+
+def test_workspace_contract(case):
+    """The caller owns every byte of device memory (Sec. 2's call sequence
+    behind a C ABI whose device state lives in one workspace): the exact need
+    esd_setup reports is within esd_workspace_bytes' bound and equals what the
+    context occupies; a NULL workspace is a size query (ESD_EWORKSPACE with the
+    need); a workspace 256 bytes short or misaligned is refused with
+    ESD_EWORKSPACE; a context in a workspace of exactly the need solves to the
+    same bits as the binding's context in its bound-sized one."""
+    import ctypes
+
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    bound = s.workspace.numel()
+    need = s.ws_needed
+    print(name, "workspace bound", bound, "exact", need, "ratio", bound / need, flush=True)
+    assert 0 < need <= bound and s.workspace_used() == need
+    n1 = ctypes.c_size_t()
+    st, h = _raw_setup(p, s, None, 0, n1)
+    assert st == esd.EWORKSPACE and n1.value == need and not h.value
+    ws = torch.empty(need + 512, dtype=torch.uint8, device=s.device)
+    st, h = _raw_setup(p, s, esd._dptr(ws), need - 256, n1)
+    assert st == esd.EWORKSPACE and not h.value
+    st, h = _raw_setup(p, s, ctypes.c_void_p(ws.data_ptr() + 64), need, n1)
+    assert st == esd.EWORKSPACE and not h.value
+    st, h = _raw_setup(p, s, esd._dptr(ws), need, n1)
+    assert st == esd.OK and h.value
+    try:
+        assert s.L.esd_factor_ic0(h) == 0
+        b = torch.as_tensor(p.f, device=s.device)
+        x = torch.empty(p.n, dtype=torch.float64, device=s.device)
+        info = esd.EsdInfo()
+        st = s.L.esd_solve(h, esd._dptr(b), None, 1e-8, 5000, esd.PLAIN, esd.FLAG_STREAM, esd._dptr(x),
+                           ctypes.byref(info))
+        xr, ir = s.solve(p.f, tol=1e-8, maxit=5000, flags=esd.FLAG_STREAM)
+        assert st == 0 and info.iters == ir["iters"] and torch.equal(x, xr)
+        with pytest.raises(esd.EsdError):
+            s.solve(p.f, tol=1e-8, maxit=100001)  # above the context's max_iters
+    finally:
+        s.L.esd_destroy(h)
+
+
+def test_fp64_context_has_no_fp32_copies(case):
+    """A context set up with ESD_PREC_FP64 needs a smaller workspace, solves
+    FP64 to the same bits as a mixed-precision context and rejects
+    ESD_FLAG_MIXED."""
+    import torch
+
+    from paper_2203_08498_amd import esd
+
+    name, p, s, o = case
+    s64 = esd.Solver.from_problem(p, m_max=16, block_rows=_bj(p), precision="fp64")
+    try:
+        assert s64.ws_needed < s.ws_needed
+        s64.factor_ic0()
+        x, i = s64.solve(p.f, tol=1e-8, maxit=5000)
+        xr, ir = s.solve(p.f, tol=1e-8, maxit=5000)
+        assert i["iters"] == ir["iters"] and torch.equal(x, xr)
+        with pytest.raises(esd.EsdError) as e:
+            s64.solve(p.f, tol=1e-8, maxit=5000, flags=esd.FLAG_MIXED)
+        assert e.value.status == esd.EINVAL
+    finally:
+        s64.close()
+
+
 def test_permutation_bitexact(case):
     name, p, s, o = case
     assert np.array_equal(s.perm(), o.perm)

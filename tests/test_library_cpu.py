@@ -86,7 +86,14 @@ def test_setup_rejects_bad_input_without_gpu(lib):
 
     L = esd.load_library()
     h = ctypes.c_void_p()
-    assert L.esd_setup(ctypes.byref(h), None, 0, None, None, None, None, 4) == esd.EINVAL
+    opt = esd.options(esd.ORDER_NATURAL, 0, esd.PREC_MIXED, 4)
+    need = ctypes.c_size_t(7)
+    assert L.esd_setup(ctypes.byref(h), None, 0, 0, None, None, None, None, ctypes.byref(opt), None, 0,
+                       ctypes.byref(need)) == esd.EINVAL
+    assert need.value == 0 and not h.value
+    bad = esd.options(esd.ORDER_BLOCK_JACOBI, 0, esd.PREC_MIXED, 4)  # block Jacobi without a block size
+    assert L.esd_setup(ctypes.byref(h), None, 4, 4, None, None, None, None, ctypes.byref(bad), None, 0,
+                       None) == esd.EINVAL
     assert L.esd_solve(None, None, None, 1e-8, 10, 0, 0, None, None) == esd.EINVAL
     assert L.esd_factor_ic0(None) == esd.EINVAL
 
@@ -101,3 +108,32 @@ def test_solver_refuses_without_gpu():
     p = P.config1(N=16, nbox=1, box=4)
     with pytest.raises(RuntimeError):
         esd.Solver.from_problem(p)
+
+
+def test_workspace_bound_arithmetic():
+    """esd_workspace_bytes is host arithmetic (no GPU): 0 for invalid
+    arguments; it grows with the longest row, m_max and max_iters; an FP64
+    context needs less than a mixed one (no FP32 copies); and for a 7-point
+    stencil (at most 7 entries per row) the mixed bound at 128^3, m_max = 16,
+    lies between the bytes the data structures must hold and that plus a
+    small per-row slack."""
+    from paper_2203_08498_amd import esd
+
+    n, nnz = 128 ** 3, 14581760
+    mixed = esd.options(esd.ORDER_COLORS, 0, esd.PREC_MIXED, 16)
+    fp64 = esd.options(esd.ORDER_COLORS, 0, esd.PREC_FP64, 16)
+    b = esd.workspace_bytes(n, nnz, 7, mixed)
+    assert esd.workspace_bytes(0, 0, 7, mixed) == 0
+    assert esd.workspace_bytes(n, nnz, 0, mixed) == 0
+    assert esd.workspace_bytes(n, nnz, 7, esd.options(esd.ORDER_COLORS, 0, esd.PREC_MIXED, 65)) == 0
+    assert esd.workspace_bytes(n, nnz, 7, esd.options(esd.ORDER_BLOCK_JACOBI, 0, esd.PREC_MIXED, 16)) == 0
+    assert esd.workspace_bytes(n, nnz, 8, mixed) > b
+    assert esd.workspace_bytes(n, nnz, 7, esd.options(esd.ORDER_COLORS, 0, esd.PREC_MIXED, 32)) > b
+    assert esd.workspace_bytes(n, nnz, 7, esd.options(esd.ORDER_COLORS, 0, esd.PREC_MIXED, 16, 200000)) > b
+    assert esd.workspace_bytes(n, nnz, 7, fp64) < b
+    # what must be stored at least: A's nnz values (FP64 + FP32) with their
+    # column indices, 13 FP64 and 10 FP32 vectors, 7 n x m_max FP64 blocks
+    # (samples, E, AE, W, AW and row-major W, AW) and 4 FP32 ones; the bound
+    # takes every slice of L and U as wide as the longest row less one
+    floor = 16 * nnz + 13 * 8 * n + 10 * 4 * n + 16 * n * (7 * 8 + 4 * 4)
+    assert floor < b < 2 * floor
