@@ -2,11 +2,13 @@
 """Benchmark: time-to-solution per system of a sequence of SPD systems sharing
 one matrix, deflated (error-vector sampling) versus plain ICCG, on one MI355X.
 
-Workload (default): 3-D 7-point FV diffusion on 128^3 cells, lognormal
-coefficients (sigma = 2) with 16 low-conductivity spheres (radius 6, contrast
-1e-5), diagonal scaling, 8 parity colours, IC(0); a sequence of 10 systems
-b_k = f + 0.1 x_{k-1}; m = 16 sampled vectors, theta = 1e-3; FP64; relative
-residual 1e-8.  All inputs are seeded and synthetic.
+Workload (default, `value`): 3-D 7-point FV diffusion on 128^3 cells,
+lognormal coefficients (sigma = 2) with 16 low-conductivity spheres (radius
+6, contrast 1e-5), diagonal scaling, 8 parity colours, IC(0); a sequence of
+10 systems b_k = f + 0.1 x_{k-1} (built on the device); m = 16 sampled
+vectors, theta = 1e-3; FP64; relative residual 1e-8.  All inputs are seeded
+and synthetic; the matrix, its layouts and f are in device memory before the
+timed region.
 
 One step = factor_ic0 + the whole sequence: system 1 is plain ICCG with
 sampling method A and the power iteration, then build_aux (error vectors,
@@ -18,25 +20,26 @@ solver, deflated and plain, with restarted refinement steps and with
 residual replacement (ESD_FLAG_MIXED_KEEP, one continued FP32 CG run), and the
 block-Jacobi IC(0) preconditioner of the paper's parallel solver (natural
 order, one grid line of N rows per block), plain, deflated and
-mixed-precision plain (both refinement forms), with the duration of its one
-launch per iteration that updates x and r and applies the preconditioner to
-the new r.
+mixed-precision plain (both refinement forms).  `setup_s`: the constructor
+(ordering, level schedule, layouts, upload), once per matrix.
 
 Roofline: the dominant kernel is the per-iteration SpMV launch; its duration
 is measured with hipEvents on the solver's stream around every executed
-launch of system 2 (the first deflated solve) of each timed step, which runs
-with stream launches; all other solves replay the captured iteration graphs.
-The same events bracket the IC(0) sweep launches of each iteration (sweeps
-GB/s).  `traffic` comes from the committed rocprofv3 counter summary.
-cpu_baseline: the FP64 C oracle, one thread.
+launch of system 2 of the deflated and of the plain sequence of each timed
+step (both run that system with stream launches, all other solves replay the
+captured iteration graphs).  The same events bracket the IC(0) sweep
+launches (sweeps GB/s).  `traffic` comes from the committed rocprofv3 counter
+summary.  `hbm_ceiling`: the library's hand-written streaming probes (copy
+and read-only reduction) beside torch's copy.  cpu_baseline: the FP64 C
+oracle, one thread.
 
-`large_kernels` (after the timed steps, not part of `value`): the FP32 SpMV
-and IC(0) sweep launches of the mixed solver's inner iterations at 256^3
-(config-3 recipe) and on the Q1 27-point matrix with 160^3 nodes (config-4
-recipe), timed the same way; at 128^3 the FP64 working set is about the size
-of the 256 MB last-level cache, these two are well beyond it.  On the Q1
-matrix also FP64 deflated against plain ICCG for one system after a sampling
-solve (its 64 floating blocks give isolated small eigenvalues).
+After the timed steps, once each (not part of `value`): configs 3 (256^3,
+mixed, m = 32, 10 systems, deflated vs plain, per-system error against the
+FP64 GPU solution), 4 (Q1 27-point on 160^3 nodes with 64 floating blocks,
+m = 64, 20 systems, FP64 and mixed, plain vs deflated, all at one
+true-residual target, kappa per system) and 5 (gradient of a loss through
+the deflated mixed solver at 128^3 against central differences along 32
+directions), with the FP32 SpMV and sweep rates of configs 3 and 4.
 """
 import argparse
 import json
@@ -62,7 +65,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-bj", action="store_true", help="skip the block-Jacobi sequences")
-    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 and Q1 160^3 kernel timings")
+    ap.add_argument("--no-large", action="store_true", help="skip configs 3 (256^3) and 4 (Q1 160^3)")
+    ap.add_argument("--no-grad", action="store_true", help="skip the config-5 gradient check")
     ap.add_argument("--cpu-iters", type=int, default=300)
     ap.add_argument("--keep-eta", type=float, default=1e-2,
                     help="reduction between residual replacements of the mixed solver with ESD_FLAG_MIXED_KEEP")
@@ -137,82 +141,304 @@ def grad_rate(s, p):
 
 
 def copy_ceiling():
-    """Device-to-device copy of 1 GiB (FP64), the practical HBM ceiling on this
-    GPU: read + written bytes over the mean of 10 copies (hipEvents)."""
+    """The practical HBM ceiling on this GPU: the library's hand-written
+    streaming probes (esd_hbm_probe) over 1 GiB of FP64, a copy (read + write)
+    and a read-only reduction, each at grids of 1024-16384 blocks (best
+    reported), beside torch's device copy; bytes moved over the mean of 10
+    launches between hipEvents."""
     import torch
 
-    src = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    from paper_2203_08498_amd import esd
+
+    n = 128 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(10):
-        dst.copy_(src)
-    b.record()
-    b.synchronize()
-    us = a.elapsed_time(b) * 1e3 / 10
-    nbytes = 2.0 * src.numel() * 8
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def rate(fn, nbytes):
+        for _ in range(3):
+            fn()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(10):
+            fn()
+        b.record()
+        b.synchronize()
+        us = a.elapsed_time(b) * 1e3 / 10
+        return {"avg_us": us, "gbs": nbytes / us / 1e3, "frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
+
+    out = {"bytes": 8.0 * n, "torch_copy": rate(lambda: dst.copy_(src), 16.0 * n)}
+    for kind, name, nb in ((esd.PROBE_COPY, "probe_copy", 16.0 * n), (esd.PROBE_READ, "probe_read", 8.0 * n)):
+        best = None
+        for g in (1024, 2048, 4096, 8192, 16384):
+            r = rate(lambda: esd.hbm_probe(kind, src, dst, g), nb)
+            r["grid"] = g
+            if best is None or r["gbs"] > best["gbs"]:
+                best = r
+        out[name] = best
     del src, dst
-    return {"bytes_per_copy": nbytes, "avg_us": us, "gbs": nbytes / us / 1e3, "frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
+    out["gbs"] = max(out["probe_copy"]["gbs"], out["probe_read"]["gbs"], out["torch_copy"]["gbs"])
+    out["frac"] = out["gbs"] / HBM_PEAK_GBS
+    return out
 
 
-def large_kernels(esd, P):
-    """FP32 SpMV and sweep-pair rates inside the mixed solver's inner
-    iterations on the config-3 and config-4 matrices (plain form, no W)."""
+def _rec(info, extra=None):
+    r = {k: info[k] for k in ("iters", "outer_iters", "fp64_iters", "true_relres", "seconds", "kappa", "kappa_es")}
+    r["kappa"], r["kappa_es"] = round(r["kappa"], 3), round(r["kappa_es"], 3)
+    if extra:
+        r.update(extra)
+    return r
+
+
+def _fp64_floor(p, x, b):
+    """Attainable relative residual of an FP64 solve: b - A x is itself only
+    known to about gamma_k || |A| |x| || / ||b|| (k = longest row)."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    absA = sp.csr_matrix((np.abs(p.val), p.col, p.rowptr), shape=(p.n, p.n))
+    k = int(np.diff(p.rowptr).max())
+    u = 2.0 ** -53
+    return k * u / (1 - k * u) * float(np.linalg.norm(absA @ np.abs(x)) / np.linalg.norm(b))
+
+
+def run_spec_sequence(s, f, esd, K, m, theta, mode, flags, tol, maxit, ref=None, ref_tol=None):
+    """One sequence as the configs specify it: b_1 = f, b_k = f + 0.1 x_{k-1}
+    built on the device; an accelerated mode samples m vectors in system 1
+    (method A, power iteration on) and builds W at theta after it.  With
+    ref (flags of an FP64 reference solve), every system's solution is also
+    compared with the FP64 GPU solution of the same b at ref_tol (deflated
+    where the sequence is, plain for system 1).  Returns per-system records,
+    the sequence's wall time (sampling and build_aux included, reference
+    solves excluded) and the build record."""
     import torch
 
-    out = {}
-    for name, make, maxit in (("cfg3_fv3d_256", P.config3, 50000), ("cfg4_q1_160", P.config4, 300)):
-        p = make()
-        print("# large kernels: %s n=%d nnz=%d" % (name, p.n, p.nnz), file=sys.stderr, flush=True)
-        s = esd.Solver.from_problem(p, m_max=p.params["m"] if name == "cfg4_q1_160" else 1)
-        s.factor_ic0()
-        f = torch.as_tensor(p.f, device=s.device)
-        # config 4: the first 300 FP32 inner iterations only (its mixed solve
-        # later finishes in FP64, whose iterations would enter the averages)
-        x, info = s.solve(f, tol=1e-8, maxit=maxit, flags=esd.FLAG_MIXED | esd.FLAG_TIMING)
-        tm = s.timing()
-        n, nnz = p.n, p.nnz
-        # FP32 (w = 4): plain-form SpMV gathers z and p_old, writes p and q;
-        # sweep pair reads both triangles with their diagonals, r, y, writes y, z
-        b_spmv = 8.0 * nnz + 16.0 * n
-        b_sw = 8.0 * (nnz + n) + 16.0 * n
-        ok = info["fp64_iters"] == 0 and tm["iters"] > 0
-        sp_s, sw_s = tm["spmv_ms"] * 1e-3, tm["sweep_ms"] * 1e-3
-        out[name] = {
-            "n": n, "nnz": nnz, "fp32_iterations_timed": tm["iters"],
-            "spmv": {"bytes_per_launch": b_spmv, "avg_launch_us": sp_s * 1e6,
-                     "achieved": b_spmv / sp_s / 1e9 if ok else None,
-                     "frac": b_spmv / sp_s / 1e9 / HBM_PEAK_GBS if ok else None},
-            "sweeps": {"bytes_per_pair": b_sw, "avg_pair_us": sw_s * 1e6,
-                       "achieved": b_sw / sw_s / 1e9 if ok else None,
-                       "frac": b_sw / sw_s / 1e9 / HBM_PEAK_GBS if ok else None},
-            "unit": "GB/s", "peak": HBM_PEAK_GBS,
-        }
-        if name == "cfg4_q1_160":
-            # FP64 deflated vs plain ICCG on this matrix's many isolated small
-            # eigenvalues: sampling solve (m = 64), build_aux, system 2 both ways
-            m, theta = p.params["m"], 1e-3
-            s.sample_errors(m)
-            x1, i1 = s.solve(f, tol=1e-8, maxit=50000)
-            st, ritz, mb, mt = s.build_aux(theta)
-            b2 = s.sequence_rhs(f, x1, 0.1)
-            res = {}
-            for label, mode in (("plain", esd.PLAIN), ("deflated", esd.DEFLATED)):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                x2, i2 = s.solve(b2, tol=1e-8, maxit=50000, mode=mode)
-                torch.cuda.synchronize()
-                res[label] = {"iters": i2["iters"], "s": time.perf_counter() - t0, "true_relres": i2["true_relres"]}
-            out[name]["fp64_deflation"] = {
-                "m": m, "theta": theta, "m_bar": mb, "m_tilde": mt, "sampling_iters": i1["iters"],
-                "plain": res["plain"], "deflated": res["deflated"],
-                "speedup_vs_plain": res["plain"]["s"] / res["deflated"]["s"],
-            }
-        s.close()
-        del p
+    recs, x = [], None
+    build = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_ref = 0.0
+    for k in range(K):
+        b = s.sequence_rhs(f, x, 0.1)
+        if k == 0:
+            if mode != esd.PLAIN:
+                s.sample_errors(m)
+            x, info = s.solve(b, tol=tol, maxit=maxit, flags=flags | esd.FLAG_POWER)
+            if mode != esd.PLAIN:
+                tb = time.perf_counter()
+                st, ritz, mb, mt = s.build_aux(theta)
+                build = {"build_aux_s": time.perf_counter() - tb, "m_bar": mb, "m_tilde": mt,
+                         "ritz_smallest": [float(v) for v in ritz[:8]],
+                         "theta_sweep_m_tilde": {"%g" % th: int(sum(1 for v in ritz if v < th))
+                                                 for th in (1e-2, 1e-3, 1e-4, 1e-5)}}
+        else:
+            x, info = s.solve(b, tol=tol, maxit=maxit, mode=mode, flags=flags)
+        extra = {}
+        if ref is not None:
+            torch.cuda.synchronize()
+            tr = time.perf_counter()
+            rmode = esd.DEFLATED if (k > 0 and mode != esd.PLAIN) else esd.PLAIN
+            xr, ir = s.solve(b, tol=ref_tol, maxit=maxit, mode=rmode, flags=ref)
+            extra = {"err_vs_fp64": float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr)),
+                     "fp64_ref_true_relres": ir["true_relres"], "fp64_ref_iters": ir["iters"]}
+            torch.cuda.synchronize()
+            t_ref += time.perf_counter() - tr
+        recs.append(_rec(info, extra))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0 - t_ref
+    return recs, wall, build, x
+
+
+def _seq_summary(recs, wall, build, K):
+    import numpy as np
+
+    out = {"s_per_system": wall / K,
+           "s_systems_2_to_K": float(np.mean([r["seconds"] for r in recs[1:]])),
+           "iters_systems_2_to_K": float(np.mean([r["iters"] for r in recs[1:]])),
+           "iters_system_1": recs[0]["iters"],
+           "true_relres_max": max(r["true_relres"] for r in recs),
+           "fp64_iters_total": int(sum(r["fp64_iters"] for r in recs)),
+           "per_system": {k: [r[k] for r in recs] for k in recs[0]}}
+    if build:
+        out.update(build)
+    if "err_vs_fp64" in recs[0]:
+        out["err_vs_fp64_max"] = max(r["err_vs_fp64"] for r in recs)
     return out
+
+
+def fp32_kernel_rates(s, f, esd, maxit):
+    """FP32 SpMV and sweep-pair rates of the mixed solver's inner iterations
+    (plain form; hipEvents around every launch of one solve)."""
+    x, info = s.solve(f, tol=1e-8, maxit=maxit, flags=esd.FLAG_MIXED | esd.FLAG_TIMING)
+    tm = s.timing()
+    n, nnz = s.n, s.nnz
+    # FP32 (w = 4): plain-form SpMV gathers z and p_old, writes p and q;
+    # sweep pair reads both triangles with their diagonals, r, y, writes y, z
+    b_spmv = 8.0 * nnz + 16.0 * n
+    b_sw = 8.0 * (nnz + n) + 16.0 * n
+    ok = info["fp64_iters"] == 0 and tm["iters"] > 0
+    sp_s, sw_s = tm["spmv_ms"] * 1e-3, tm["sweep_ms"] * 1e-3
+    return {
+        "fp32_iterations_timed": tm["iters"],
+        "spmv": {"bytes_per_launch": b_spmv, "avg_launch_us": sp_s * 1e6,
+                 "achieved": b_spmv / sp_s / 1e9 if ok else None,
+                 "frac": b_spmv / sp_s / 1e9 / HBM_PEAK_GBS if ok else None},
+        "sweeps": {"bytes_per_pair": b_sw, "avg_pair_us": sw_s * 1e6,
+                   "achieved": b_sw / sw_s / 1e9 if ok else None,
+                   "frac": b_sw / sw_s / 1e9 / HBM_PEAK_GBS if ok else None},
+        "unit": "GB/s", "peak": HBM_PEAK_GBS,
+    }
+
+
+def config3_spec(esd, P, theta):
+    """Config 3 as specified: 256^3 config-2 recipe, FP32 inner / FP64 outer
+    (mixed), m = 32, 10 systems, deflated against plain; every system of the
+    mixed deflated sequence against the FP64 deflated GPU solution of the same
+    b at relres 1e-12 (whose parity with the oracle is pinned at 128^3 and
+    131^3)."""
+    import torch
+
+    p = P.config3()
+    m, K = p.params["m"], p.params["systems"]
+    print("# config 3: n=%d nnz=%d" % (p.n, p.nnz), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    s = esd.Solver.from_problem(p, m_max=m, max_iters=60000)
+    setup_s = time.perf_counter() - t0
+    try:
+        t0 = time.perf_counter()
+        s.factor_ic0()
+        torch.cuda.synchronize()
+        fac_s = time.perf_counter() - t0
+        s.set_power_start(P.power_start(3, p.n))
+        f = torch.as_tensor(p.f, device=s.device)
+        out = {"n": p.n, "nnz": p.nnz, "m": m, "theta": theta, "systems": K, "setup_s": setup_s,
+               "esd_setup_s": s.setup_s, "factor_s": fac_s, "workspace_bytes": s.ws_needed}
+        out.update(fp32_kernel_rates(s, f, esd, 60000))
+        for label, mode, ref in (("mixed_plain", esd.PLAIN, None), ("mixed_deflated", esd.DEFLATED, 0)):
+            recs, wall, build, _ = run_spec_sequence(s, f, esd, K, m, theta, mode, esd.FLAG_MIXED, 1e-8, 60000,
+                                                     ref=ref, ref_tol=1e-12)
+            out[label] = _seq_summary(recs, wall, build, K)
+            print("# config 3 %s: %.4f s/system" % (label, out[label]["s_per_system"]), file=sys.stderr, flush=True)
+        out["speedup_deflated_vs_plain"] = out["mixed_plain"]["s_per_system"] / out["mixed_deflated"]["s_per_system"]
+        return out
+    finally:
+        s.close()
+
+
+def config4_spec(esd, P, theta):
+    """Config 4 as specified: Q1 27-point on 160^3 nodes with 64 floating
+    blocks, m = 64, 20 systems, kappa per system; FP64 and FP32/FP64 mixed,
+    plain against deflated.  Every solve is driven to one true-residual
+    target: relres 1e-8, or 3x the FP64 rounding floor of b - A x when that
+    is higher (FP64 solves test the recomputed residual, ESD_FLAG_TRUE_RES;
+    mixed solves test it by construction).  The mixed deflated sequence's
+    systems are compared with the FP64 deflated solution of the same b."""
+    import torch
+
+    p = P.config4()
+    m, K = p.params["m"], p.params["systems"]
+    print("# config 4: n=%d nnz=%d" % (p.n, p.nnz), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    s = esd.Solver.from_problem(p, m_max=m, max_iters=60000)
+    setup_s = time.perf_counter() - t0
+    try:
+        s.factor_ic0()
+        s.set_power_start(P.power_start(4, p.n))
+        f = torch.as_tensor(p.f, device=s.device)
+        out = {"n": p.n, "nnz": p.nnz, "m": m, "theta": theta, "systems": K, "setup_s": setup_s,
+               "esd_setup_s": s.setup_s, "workspace_bytes": s.ws_needed}
+        # the first 300 FP32 inner iterations (the solve may finish in FP64)
+        out.update(fp32_kernel_rates(s, f, esd, 300))
+        x1, i1 = s.solve(f, tol=1e-8, maxit=60000)
+        floor = _fp64_floor(p, x1.cpu().numpy(), p.f)
+        tol = max(1e-8, 3.0 * floor)
+        out["fp64_floor"] = floor
+        out["tol_true_relres"] = tol
+        for label, mode, flags, ref in (("fp64_plain", esd.PLAIN, esd.FLAG_TRUE_RES, None),
+                                        ("fp64_deflated", esd.DEFLATED, esd.FLAG_TRUE_RES, None),
+                                        ("mixed_plain", esd.PLAIN, esd.FLAG_MIXED, None),
+                                        ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED, esd.FLAG_TRUE_RES)):
+            recs, wall, build, _ = run_spec_sequence(s, f, esd, K, m, theta, mode, flags, tol, 60000,
+                                                     ref=ref, ref_tol=tol)
+            out[label] = _seq_summary(recs, wall, build, K)
+            print("# config 4 %s: %.4f s/system" % (label, out[label]["s_per_system"]), file=sys.stderr, flush=True)
+        for pre in ("fp64", "mixed"):
+            out["speedup_deflated_vs_plain_" + pre] = out[pre + "_plain"]["s_per_system"] / \
+                out[pre + "_deflated"]["s_per_system"]
+        out["speedup_mixed_deflated_vs_fp64_plain"] = out["fp64_plain"]["s_per_system"] / \
+            out["mixed_deflated"]["s_per_system"]
+        return out
+    finally:
+        s.close()
+
+
+def config5_spec(esd, P):
+    """Config 5 as specified: the 128^3 config-2 field, forward and adjoint
+    solves with the deflated mixed solver (m = 16, theta = 1e-3, relres
+    1e-12) in the autograd Function, loss 0.5 ||x - x_t||^2, gradients with
+    respect to b and every stored value against central differences
+    (h = 1e-6) along 32 seeded directions (symmetric value perturbation and a
+    right-hand-side perturbation), and the Richardson combination of h and
+    2h; FD solves FP64 deflated at relres 1e-13."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    from paper_2203_08498_amd import autograd as AG
+
+    p = P.config2(N=128, cfg=2)
+    s = esd.Solver.from_problem(p, m_max=16)
+    try:
+        s.factor_ic0()
+        s.sample_errors(16)
+        s.solve(p.f, tol=1e-8, maxit=20000)
+        s.build_aux(1e-3)
+        vals = torch.tensor(p.val, device=s.device, dtype=torch.float64, requires_grad=True)
+        b = torch.tensor(p.f, device=s.device, requires_grad=True)
+        xt = torch.tensor(P.rng_for(5, P.STREAM_XT).standard_normal(p.n), device=s.device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = AG.solve(vals, b, s, mode=esd.DEFLATED, tol=1e-12, maxit=20000, flags=esd.FLAG_MIXED)
+        loss = 0.5 * ((x - xt) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        t_grad = time.perf_counter() - t0
+        gv, gb = vals.grad.cpu().numpy(), b.grad.cpu().numpy()
+        M = sp.csr_matrix((np.arange(1, p.nnz + 1, dtype=np.float64), p.col, p.rowptr), shape=(p.n, p.n))
+        T = M.T.tocsr()
+        T.sort_indices()
+        tmap = T.data.astype(np.int64) - 1
+        rng = P.rng_for(5, P.STREAM_FD)
+        h = 1e-6
+
+        def L(v, bb):
+            s.update_values(v)
+            s.factor_ic0()
+            xx, info = s.solve(bb, tol=1e-13, maxit=50000, mode=esd.DEFLATED)
+            return 0.5 * float(((xx - xt) ** 2).sum())
+
+        def D(d, db, hh):
+            return (L(p.val + hh * d, p.f + hh * db) - L(p.val - hh * d, p.f - hh * db)) / (2 * hh)
+
+        errs, errs2, rich = [], [], []
+        for _ in range(32):
+            d = rng.standard_normal(p.nnz)
+            d = 0.5 * (d + d[tmap])
+            db = rng.standard_normal(p.n)
+            an = gv @ d + gb @ db
+            d1, d2 = D(d, db, h), D(d, db, 2 * h)
+            errs.append(abs(d1 - an) / abs(an))
+            errs2.append(abs(d2 - an) / abs(an))
+            rich.append(abs((4 * d1 - d2) / 3 - an) / abs(an))
+        s.update_values(p.val)
+        # the central difference's own O(h^2) truncation dominates its error
+        # (4x at 2h); Richardson's (4 D(h) - D(2h)) / 3 removes it
+        return {"directions": 32, "h": h, "forward_plus_adjoint_s": t_grad,
+                "cd_rel_err_max": max(errs), "cd_rel_err_median": float(np.median(errs)),
+                "cd_2h_over_h_err_ratio_median": float(np.median(np.array(errs2) / np.array(errs))),
+                "richardson_rel_err_max": max(rich), "richardson_rel_err_median": float(np.median(rich))}
+    finally:
+        s.close()
 
 
 def counter_traffic(kernel):
@@ -302,7 +528,12 @@ def main():
         print("# copy calibration: 3 copies of 268435456 bytes", file=sys.stderr, flush=True)
     p = P.config2(N=args.N, m=args.m, systems=args.systems)
     print("# workload %s n=%d nnz=%d" % (p.name, p.n, p.nnz), file=sys.stderr, flush=True)
+    # setup (ordering, level schedule, layouts, upload; once per matrix, not
+    # part of a step): the whole constructor and the esd_setup call inside it
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     s = esd.Solver.from_problem(p, m_max=args.m)
+    setup_wall = time.perf_counter() - t0
     s.set_power_start(P.power_start(2, p.n))
     # block-Jacobi IC(0), one grid line (N consecutive rows) per block
     sbj = None
@@ -337,19 +568,27 @@ def main():
     torch.cuda.synchronize()
     walls = {name: [] for name, _, _ in seqs}
     recs = {}
+    # kernel timing: system 2 of the deflated and the plain sequence (and of
+    # both block-Jacobi ones) runs with hipEvents around its launches, so
+    # deflated and plain carry the same (small) cost of stream launches
+    timed_seqs = ("deflated", "plain", "bj_deflated", "bj_plain")
     spmv_ms = sweep_ms = 0.0
     spmv_n = 0
+    spmv_plain_ms, spmv_plain_n = 0.0, 0
     bj_ms = 0.0
     bj_n = 0
     for k in range(args.steps):
         for name, mode, pf in seqs:
-            r, wall, tm = run(name, mode, pf, name in ("deflated", "bj_deflated"))
+            r, wall, tm = run(name, mode, pf, name in timed_seqs)
             walls[name].append(wall)
             recs[name] = r
             if tm and name == "deflated":
                 spmv_ms += tm["spmv_ms"] * tm["iters"]
                 sweep_ms += tm["sweep_ms"] * tm["iters"]
                 spmv_n += tm["iters"]
+            elif tm and name == "plain":
+                spmv_plain_ms += tm["spmv_ms"] * tm["iters"]
+                spmv_plain_n += tm["iters"]
             elif tm:
                 bj_ms += tm["sweep_ms"] * tm["iters"]
                 bj_n += tm["iters"]
@@ -433,6 +672,10 @@ def main():
                         % (args.N, args.systems, args.m, args.theta),
             "n": n, "nnz": nnz, "systems": args.systems, "m": args.m, "theta": args.theta,
         },
+        "setup_s": setup_wall,
+        "esd_setup_s": s.setup_s,
+        "workspace_bytes": s.ws_needed,
+        "workspace_bound_bytes": int(s.workspace.numel()),
         "plain_s_per_system": per_sys_plain,
         "speedup_vs_plain": per_sys_plain / per_sys if per_sys > 0 else None,
         "subspace_s_per_system": per["subspace"],
@@ -483,11 +726,22 @@ def main():
             "avg_launch_us": avg_spmv_s * 1e6,
             "launches": spmv_n,
         },
+        # the plain form's SpMV (p = z + beta p_old formed on the fly: z and
+        # p_old gathered, p and q written), timed the same way in the plain sequence
+        "spmv_plain_form": {"bytes_per_launch": 12.0 * nnz + 32.0 * n,
+                            "avg_launch_us": spmv_plain_ms / max(spmv_plain_n, 1) * 1e3,
+                            "achieved": (12.0 * nnz + 32.0 * n) / (spmv_plain_ms / max(spmv_plain_n, 1) * 1e-3) / 1e9
+                            if spmv_plain_n else None},
     }
-    out["hbm_copy"] = copy_ceiling()
+    out["hbm_ceiling"] = copy_ceiling()
     out["gradient"] = grad_rate(s, p)
+    # the other configurations as specified, once, after the timed steps
     if not args.no_large and args.N == 128:
-        out["large_kernels"] = large_kernels(esd, P)
+        out["config3"] = config3_spec(esd, P, args.theta)
+        out["config4"] = config4_spec(esd, P, args.theta)
+    if not args.no_grad and args.N == 128:
+        print("# config 5 gradient check ...", file=sys.stderr, flush=True)
+        out["config5"] = config5_spec(esd, P)
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p, args, mt, float(np.mean(its_defl)) if its_defl else its_plain[0])
