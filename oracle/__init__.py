@@ -22,10 +22,22 @@ OK, NOT_CONVERGED, AUX_EMPTY = 0, 1, 2
 EINVAL, ENOTSPD, ENUMERIC, ENOAUX, ENOSAMPLES = -1, -2, -4, -5, -6
 
 
+# ORACLE_SANITIZE=1: a separate build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (aborting on the first report), loaded instead
+# of the plain one; the process must preload libasan (the sanitizer test does)
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+if _SANITIZE:
+    _SO = os.path.join(_HERE, "liboracle_san.so")
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no FMA contraction)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", _SO, _SRC, "-lm"]
+        flags = ["-O2"]
+        if _SANITIZE:
+            flags = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                     "-fno-omit-frame-pointer"]
+        cmd = ["gcc", *flags, "-ffp-contract=off", "-fPIC", "-shared", "-o", _SO, _SRC, "-lm"]
         subprocess.check_call(cmd)
     return _SO
 

@@ -24,8 +24,12 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 @pytest.fixture(scope="module")
 def driver(tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("host") / "host_driver")
-    subprocess.check_call(["g++", "-O1", "-std=c++17", "-fopenmp", "-I", CSRC, "-I", os.path.join(ROOT, "include"),
-                           os.path.join(os.path.dirname(__file__), "host_driver.cpp"),
+    # ESD_HOST_SANITIZE=1: the driver and the host setup code built with
+    # AddressSanitizer and UndefinedBehaviorSanitizer (abort on the first report)
+    san = ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"] \
+        if os.environ.get("ESD_HOST_SANITIZE") == "1" else []
+    subprocess.check_call(["g++", "-O1", *san, "-std=c++17", "-fopenmp", "-I", CSRC, "-I",
+                           os.path.join(ROOT, "include"), os.path.join(os.path.dirname(__file__), "host_driver.cpp"),
                            os.path.join(CSRC, "host_setup.cpp"), "-o", exe])
     return exe
 
