@@ -287,6 +287,27 @@ esd_status esd_set_mixed_params(esd_ctx *ctx, double inner_tol, int32_t max_oute
 esd_status esd_solve(esd_ctx *ctx, const double *b, const double *x0, double tol, int32_t maxit,
                      int32_t mode, int32_t flags, double *x, esd_info *info);
 
+/* esd_solve_noalloc - esd_solve for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, results and kernels as esd_solve with ESD_FLAG_STREAM,
+ * but the call allocates nothing -- no device memory, no HIP event, no graph
+ * (the kernels are launched on the stream one by one).  The per-solve scratch
+ * that esd_solve keeps in the context's workspace (the device scalar block
+ * and the block-partial tables of every reduction) comes from one static
+ * device array of 2.1 MB per GPU instead (4 KB scalar block, 4 x 384 KB
+ * partial tables, 512 KB of sweep partials), held by every GPU the library
+ * runs on until the process ends; the context's workspace still holds the
+ * matrix, factor, auxiliary space and work vectors.  Every call on one GPU
+ * shares that array, so calls that overlap on one GPU (on two streams or from
+ * two threads) race: serialise them.  Nothing in it has to start at zero:
+ * each solve writes the scalar block and every partial row before reading
+ * them.  info->seconds is host wall time.  ESD_EINVAL for ESD_FLAG_TIMING /
+ * ESD_FLAG_TIMING_SPMV, or when the context's sweep levels need more than
+ * 65536 partial slots (more levels than the array holds: use esd_solve);
+ * ESD_EHIP if the array's device address could not be resolved at setup. */
+esd_status esd_solve_noalloc(esd_ctx *ctx, const double *b, const double *x0, double tol, int32_t maxit,
+                             int32_t mode, int32_t flags, double *x, esd_info *info);
+
 /* esd_sequence_rhs - right-hand side of the next system of the sequence
  * (Sec. 2: b_k depends on the earlier solutions): b = f + c * xprev, with
  * f(d), xprev(d), b(d) float64[n]; xprev may be NULL (b = f).  Enqueued on

@@ -4,10 +4,12 @@
 // kernels of kernels.hip; this file only sequences launches and reads back a
 // small status block once per chunk of iterations.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -54,6 +56,42 @@ template <typename T> struct VecSet {
 
 constexpr int kFlagTiming = ESD_FLAG_TIMING | ESD_FLAG_TIMING_SPMV;
 
+// Scratch of the allocation-free solve (esd_solve_noalloc): the device scalar
+// block and the block-partial tables of one solve, in one array per GPU that
+// lives as long as the process.  Host code never passes the array's name to a
+// kernel: its device address on the current GPU comes from
+// hipGetSymbolAddress, resolved once per device when a context is set up.
+constexpr int64_t kScratchScal = 4096 / 8; // doubles reserved for the scalar block
+constexpr int64_t kScratchSweep = 65536;   // sweep partial slots (one per block of every level launch)
+constexpr int64_t kScratchDoubles = kScratchScal + 4 * (int64_t)esd::kPartBudget + kScratchSweep;
+static_assert(sizeof(esd::Scal) <= 8 * kScratchScal, "scalar block larger than its scratch slot");
+
+} // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+hipError_t scratch_for_current_device(double **out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<double *>(g_scratch_ptr[dev]);
+    return hipSuccess;
+}
 } // namespace
 
 struct esd_ctx {
@@ -151,6 +189,7 @@ struct esd_ctx {
     bool use_graphs = true;
     bool class_layout = true; // class-aligned matrix copies for the iteration kernels when they fit
     bool trace = false;       // ESD_TRACE set: one stderr line per refinement step of the mixed solver
+    double *scratch = nullptr; // this device's copy of the allocation-free solve's scratch (null: unavailable)
     int rr_op = 0;            // Rayleigh-Ritz operator of build_aux: 0 A, 1 M^{-1}A
     hipStream_t cap = nullptr; // private stream the chunks are captured on
     // kernel timing
@@ -1478,6 +1517,12 @@ esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, int64_t nnz, c
     }
     SETUP_HIP(hipMemsetAsync(c->S, 0, sizeof(Scal), c->stream));
     SETUP_HIP(hipHostMalloc((void **)&c->Sh, sizeof(Scal), hipHostMallocDefault));
+    // the allocation-free solve's scratch on this device (a failure here only
+    // disables esd_solve_noalloc)
+    if (scratch_for_current_device(&c->scratch) != hipSuccess) {
+        c->scratch = nullptr;
+        (void)hipGetLastError();
+    }
     std::memset(c->Sh, 0, sizeof(Scal));
     // the host copies die here: finish every transfer first
     if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
@@ -1621,13 +1666,46 @@ esd_status esd_set_power_start(esd_ctx *c, const double *v0) {
 } // extern "C"
 
 namespace {
+// Swaps the context's scalar block and block-partial tables for the scratch
+// array for the duration of one allocation-free solve.
+struct ScratchSwap {
+    esd_ctx *c;
+    Scal *S;
+    double *spmv, *upd, *gen, *ts, *sweep;
+    ScratchSwap(esd_ctx *ctx, double *base)
+        : c(ctx), S(ctx->S), spmv(ctx->part_spmv), upd(ctx->part_upd), gen(ctx->part_gen), ts(ctx->part_ts),
+          sweep(ctx->part_sweep) {
+        c->S = reinterpret_cast<Scal *>(base);
+        c->part_spmv = base + kScratchScal;
+        c->part_upd = c->part_spmv + esd::kPartBudget;
+        c->part_gen = c->part_upd + esd::kPartBudget;
+        c->part_ts = c->part_gen + esd::kPartBudget;
+        c->part_sweep = c->part_ts + esd::kPartBudget;
+    }
+    ~ScratchSwap() {
+        c->S = S;
+        c->part_spmv = spmv;
+        c->part_upd = upd;
+        c->part_gen = gen;
+        c->part_ts = ts;
+        c->part_sweep = sweep;
+    }
+};
+
 esd_status solve_entry(esd_ctx *c, const double *b, const double *x0, double tol, int32_t maxit, int32_t mode,
-                       int32_t flags, double *x, esd_info *info) {
+                       int32_t flags, double *x, esd_info *info, bool noalloc) {
     if (!c || !b || !x || maxit < 0 || !(tol >= 0) || mode < 0 || mode > 2) return ESD_EINVAL;
     if (!c->factored && !(flags & ESD_FLAG_NOPREC)) return fail(c, ESD_EINVAL, "factor_ic0 not called");
     if ((flags & ESD_FLAG_POWER) && !c->have_v) return fail(c, ESD_EINVAL, "power start vector not set");
     if ((flags & ESD_FLAG_MIXED) && !c->mixed)
         return fail(c, ESD_EINVAL, "ESD_FLAG_MIXED needs a context set up with ESD_PREC_MIXED");
+    if (noalloc) {
+        if (flags & kFlagTiming) return fail(c, ESD_EINVAL, "esd_solve_noalloc takes no timing flags");
+        if (!c->scratch) return fail(c, ESD_EHIP, "the scratch array of this device is unavailable");
+        if (c->sweep_cap > kScratchSweep)
+            return fail(c, ESD_EINVAL, "more sweep partial slots than the scratch array holds");
+        flags |= ESD_FLAG_STREAM; // replaying a graph could need its instantiation first
+    }
     esd_status warn = ESD_OK;
     int kind = mode;
     if (mode != ESD_PLAIN) {
@@ -1640,19 +1718,30 @@ esd_status solve_entry(esd_ctx *c, const double *b, const double *x0, double tol
     esd_info tmp{};
     esd_info *inf = info ? info : &tmp;
     std::memset(inf, 0, sizeof(esd_info));
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, c->stream));
-    if (flags & ESD_FLAG_MIXED) st = solve_mixed(c, b, x0, tol, maxit, kind, flags, x, inf);
-    else st = solve_fp64(c, b, x0, tol, maxit, kind, flags, x, inf);
-    (void)hipEventRecord(e1, c->stream);
-    (void)hipEventSynchronize(e1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    inf->seconds = ms * 1e-3;
+    if (noalloc) {
+        // wall time on the host: the solve ends with a stream synchronisation
+        const auto t0 = std::chrono::steady_clock::now();
+        {
+            ScratchSwap sw(c, c->scratch);
+            if (flags & ESD_FLAG_MIXED) st = solve_mixed(c, b, x0, tol, maxit, kind, flags, x, inf);
+            else st = solve_fp64(c, b, x0, tol, maxit, kind, flags, x, inf);
+        }
+        inf->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    } else {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, c->stream));
+        if (flags & ESD_FLAG_MIXED) st = solve_mixed(c, b, x0, tol, maxit, kind, flags, x, inf);
+        else st = solve_fp64(c, b, x0, tol, maxit, kind, flags, x, inf);
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        inf->seconds = ms * 1e-3;
+    }
     if ((flags & ESD_FLAG_POWER) && st >= 0) c->lam_last = c->Sh->lam;
     inf->lambda_max = c->lam_last;
     inf->lambda_min_ritz = c->ritz.empty() ? 0.0 : c->ritz[0];
@@ -1667,7 +1756,12 @@ extern "C" {
 
 esd_status esd_solve(esd_ctx *c, const double *b, const double *x0, double tol, int32_t maxit, int32_t mode,
                      int32_t flags, double *x, esd_info *info) {
-    return solve_entry(c, b, x0, tol, maxit, mode, flags, x, info);
+    return solve_entry(c, b, x0, tol, maxit, mode, flags, x, info, false);
+}
+
+esd_status esd_solve_noalloc(esd_ctx *c, const double *b, const double *x0, double tol, int32_t maxit,
+                             int32_t mode, int32_t flags, double *x, esd_info *info) {
+    return solve_entry(c, b, x0, tol, maxit, mode, flags, x, info, true);
 }
 
 esd_status esd_sequence_rhs(esd_ctx *c, const double *f, const double *xprev, double cc, double *b) {

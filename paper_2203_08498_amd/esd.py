@@ -50,7 +50,7 @@ class EsdInfo(C.Structure):
 
 EXPORTS = [
     "esd_workspace_bytes", "esd_setup", "esd_workspace_used", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux", "esd_set_aux", "esd_get_aux",
-    "esd_hbm_probe", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
+    "esd_hbm_probe", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_solve_noalloc", "esd_sequence_rhs", "esd_grad_values", "esd_spmv",
     "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag", "esd_get_history", "esd_get_samples",
     "esd_get_sample_vector", "esd_set_rayleigh_ritz",
     "esd_get_layout", "esd_get_timing", "esd_status_string", "esd_last_error", "esd_destroy",
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_set_power_start.argtypes = [P, P]
     L.esd_set_mixed_params.argtypes = [P, dbl, i32]
     L.esd_solve.argtypes = [P, P, P, dbl, i32, i32, i32, P, C.POINTER(EsdInfo)]
+    L.esd_solve_noalloc.argtypes = [P, P, P, dbl, i32, i32, i32, P, C.POINTER(EsdInfo)]
     L.esd_sequence_rhs.argtypes = [P, P, P, dbl, P]
     L.esd_grad_values.argtypes = [P, P, P, P]
     L.esd_spmv.argtypes = [P, P, P]
@@ -105,7 +106,7 @@ def load_library(path: str = LIB_PATH):
     L.esd_destroy.argtypes = [P]
     for name in ("esd_setup", "esd_workspace_used", "esd_update_values", "esd_factor_ic0", "esd_sample_errors", "esd_load_samples", "esd_build_aux",
                  "esd_set_aux",
-                 "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_sequence_rhs",
+                 "esd_get_aux", "esd_set_power_start", "esd_set_mixed_params", "esd_solve", "esd_solve_noalloc", "esd_sequence_rhs",
                  "esd_grad_values", "esd_spmv", "esd_prec_apply", "esd_get_perm", "esd_get_factor_diag",
                  "esd_get_history", "esd_get_samples", "esd_get_sample_vector", "esd_get_layout", "esd_get_timing",
                  "esd_set_rayleigh_ritz"):
@@ -301,12 +302,14 @@ class Solver:
         if st != 0:
             raise EsdError(st, "bad mixed parameters")
 
-    def solve(self, b, x0=None, tol=1e-8, maxit=10000, mode=PLAIN, flags=0, out=None):
+    def solve(self, b, x0=None, tol=1e-8, maxit=10000, mode=PLAIN, flags=0, out=None, noalloc=False):
+        """esd_solve (noalloc=True: esd_solve_noalloc, which allocates nothing)."""
         b = self._vec(b)
         x0 = None if x0 is None else self._vec(x0)
         x = out if out is not None else self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
         info = EsdInfo()
-        st = self.L.esd_solve(self.h, _dptr(b), None if x0 is None else _dptr(x0), float(tol), int(maxit),
+        fn = self.L.esd_solve_noalloc if noalloc else self.L.esd_solve
+        st = fn(self.h, _dptr(b), None if x0 is None else _dptr(x0), float(tol), int(maxit),
                 int(mode), int(flags), _dptr(x), C.byref(info))
         if st < 0:
             raise EsdError(st, self.L.esd_last_error(self.h).decode())
