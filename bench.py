@@ -72,6 +72,10 @@ def parse():
                     help="reduction between residual replacements of the mixed solver with ESD_FLAG_MIXED_KEEP")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--profile-case", choices=("cfg3", "cfg4"), default=None,
+                    help="a short run for rocprofv3 counters instead of the benchmark: the probe copy "
+                         "of 256 MiB (calibration), then 200 FP32 inner iterations and 50 FP64 "
+                         "iterations of the named matrix with stream launches")
     return ap.parse_args()
 
 
@@ -441,6 +445,32 @@ def config5_spec(esd, P):
         s.close()
 
 
+def profile_case(esd, P, case):
+    """A short, fixed launch sequence for HBM counters: 3 probe copies of
+    256 MiB (known bytes, the calibration kernel), then on the 256^3 (cfg3)
+    or Q1 160^3 (cfg4) matrix 200 FP32 inner iterations of the mixed solver
+    and 50 FP64 iterations, every kernel launched on the stream."""
+    import torch
+
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        esd.hbm_probe(esd.PROBE_COPY, src, dst, 4096)
+    torch.cuda.synchronize()
+    del src, dst
+    print("# calibration: 3 probe copies of 268435456 bytes", file=sys.stderr, flush=True)
+    p = P.config3() if case == "cfg3" else P.config4()
+    s = esd.Solver.from_problem(p, m_max=1)
+    s.factor_ic0()
+    f = torch.as_tensor(p.f, device=s.device)
+    x, i32 = s.solve(f, tol=1e-8, maxit=200, flags=esd.FLAG_MIXED | esd.FLAG_STREAM)
+    x, i64 = s.solve(f, tol=1e-8, maxit=50, flags=esd.FLAG_STREAM)
+    torch.cuda.synchronize()
+    print("# %s: n=%d nnz=%d, %d FP32 inner and %d FP64 iterations" % (case, p.n, p.nnz, i32["iters"], i64["iters"]),
+          file=sys.stderr, flush=True)
+    s.close()
+
+
 def counter_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None
@@ -516,16 +546,20 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.profile_case:
+        profile_case(esd, P, args.profile_case)
+        return
     if args.copy_calib:
-        # a plain copy of known size: what the HBM byte counters read for it
-        # calibrates the counters of the solver kernels (256 MiB read + written)
+        # a plain copy of known size (the library's probe kernel): what the HBM
+        # byte counters read for it calibrates the counters of the solver
+        # kernels (256 MiB read + written per copy)
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            esd.hbm_probe(esd.PROBE_COPY, src, dst, 4096)
         torch.cuda.synchronize()
         del src, dst
-        print("# copy calibration: 3 copies of 268435456 bytes", file=sys.stderr, flush=True)
+        print("# copy calibration: 3 probe copies of 268435456 bytes", file=sys.stderr, flush=True)
     p = P.config2(N=args.N, m=args.m, systems=args.systems)
     print("# workload %s n=%d nnz=%d" % (p.name, p.n, p.nnz), file=sys.stderr, flush=True)
     # setup (ordering, level schedule, layouts, upload; once per matrix, not
