@@ -1757,37 +1757,47 @@ void launch_grad(int n, const int64_t *rowptr, const int32_t *col, const double 
 // ---- streaming probes of the achievable HBM bandwidth (not part of the method)
 // Grid-stride over 16-byte vectors, consecutive lanes on consecutive vectors
 // (one 1 KB coalesced access per wavefront and load), four independent loads
-// in flight per thread before any store or add.
-__global__ __launch_bounds__(kBlock) void k_probe_copy(const double2 *__restrict__ src, double2 *__restrict__ dst,
+// in flight per thread before any store or add; non-temporal loads and
+// stores (streamed data is not kept in the caches).
+typedef double probe_v2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(kBlock) void k_probe_copy(const probe_v2 *__restrict__ src, probe_v2 *__restrict__ dst,
                                                         int64_t n2) {
     const int64_t st = (int64_t)gridDim.x * kBlock;
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     for (; i + 3 * st < n2; i += 4 * st) {
-        const double2 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
-        dst[i] = a;
-        dst[i + st] = b;
-        dst[i + 2 * st] = c;
-        dst[i + 3 * st] = d;
+        const probe_v2 a = __builtin_nontemporal_load(src + i), b = __builtin_nontemporal_load(src + i + st),
+                       c = __builtin_nontemporal_load(src + i + 2 * st),
+                       d = __builtin_nontemporal_load(src + i + 3 * st);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + st);
+        __builtin_nontemporal_store(c, dst + i + 2 * st);
+        __builtin_nontemporal_store(d, dst + i + 3 * st);
     }
-    for (; i < n2; i += st) dst[i] = src[i];
+    for (; i < n2; i += st) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
-__global__ __launch_bounds__(kBlock) void k_probe_read(const double2 *__restrict__ src, int64_t n2, double *part) {
+__global__ __launch_bounds__(kBlock) void k_probe_read(const probe_v2 *__restrict__ src, int64_t n2, double *part) {
     const int64_t st = (int64_t)gridDim.x * kBlock;
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double acc[1] = {0.0};
     for (; i + 3 * st < n2; i += 4 * st) {
-        const double2 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
+        const probe_v2 a = __builtin_nontemporal_load(src + i), b = __builtin_nontemporal_load(src + i + st),
+                       c = __builtin_nontemporal_load(src + i + 2 * st),
+                       d = __builtin_nontemporal_load(src + i + 3 * st);
         acc[0] += ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
     }
-    for (; i < n2; i += st) acc[0] += src[i].x + src[i].y;
+    for (; i < n2; i += st) {
+        const probe_v2 a = __builtin_nontemporal_load(src + i);
+        acc[0] += a.x + a.y;
+    }
     block_partials<1>(acc, part, 1);
 }
 
 void launch_probe(int kind, const double *src, double *dst, int64_t n, int grid, hipStream_t s) {
     const int64_t n2 = n / 2;
-    if (kind == 0) k_probe_copy<<<grid, kBlock, 0, s>>>((const double2 *)src, (double2 *)dst, n2);
-    else k_probe_read<<<grid, kBlock, 0, s>>>((const double2 *)src, n2, dst);
+    if (kind == 0) k_probe_copy<<<grid, kBlock, 0, s>>>((const probe_v2 *)src, (probe_v2 *)dst, n2);
+    else k_probe_read<<<grid, kBlock, 0, s>>>((const probe_v2 *)src, n2, dst);
 }
 
 } // namespace esd
