@@ -307,8 +307,10 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
         if (i >= n) continue;
         T g[MT > 0 ? MT : 1];
         if constexpr (MT > 0) {
+            // columns past m re-read column m - 1 (unused sums): no condition
+            // on the loads, so they are all in flight together
 #pragma unroll
-            for (int k = 0; k < MT; ++k) g[k] = (k < a.m) ? a.G[(size_t)k * n + i] : T(0);
+            for (int k = 0; k < MT; ++k) g[k] = a.G[(size_t)(k < a.m ? k : a.m - 1) * n + i];
         }
         a.x[i] += ta * a.p[i];
         const T ri = a.r[i] - ta * a.q[i];
@@ -359,8 +361,9 @@ __global__ __launch_bounds__(kBlock) void k_update_it2(UpdIt<T> a) {
             rv[u] = h[u] ? a.r[i[u]] : T(0);
             dv[u] = (h[u] && i[u] < a.l0) ? a.dinv[i[u]] : T(0);
             if constexpr (MT > 0) {
+                const int iu = h[u] ? i[u] : 0;
 #pragma unroll
-                for (int k = 0; k < MT; ++k) g[u][k] = (h[u] && k < a.m) ? a.G[(size_t)k * n + i[u]] : T(0);
+                for (int k = 0; k < MT; ++k) g[u][k] = a.G[(size_t)(k < a.m ? k : a.m - 1) * n + iu];
             }
         }
 #pragma unroll
@@ -968,12 +971,19 @@ __global__ __launch_bounds__(kBlock) void k_proj(Proj<T> a) {
     for (int t = tl.t0; t < tl.t1; ++t) {
         const int i = (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
         if (i >= n) continue;
-        double s = (double)a.z[i];
+        // every column load issued before the sums: columns past m re-read
+        // column m - 1 (cached) and meet mu = 0, so the loads carry no
+        // condition and stay in flight together
+        T w[MT];
 #pragma unroll
-        for (int k = 0; k < MT; ++k)
-            if (k < a.m) s -= (double)a.W[(size_t)k * n + i] * mu[k];
+        for (int k = 0; k < MT; ++k) w[k] = a.W[(size_t)(k < a.m ? k : a.m - 1) * n + i];
+        const T zi = a.z[i];
+        const T po = first ? T(0) : a.pold[i];
+        double s = (double)zi;
+#pragma unroll
+        for (int k = 0; k < MT; ++k) s -= (double)w[k] * mu[k];
         const T zh = (T)s;
-        a.pnew[i] = first ? zh : zh + beta * a.pold[i];
+        a.pnew[i] = first ? zh : zh + beta * po;
     }
 }
 
@@ -1001,16 +1011,16 @@ __global__ __launch_bounds__(kBlock) void k_proj2(Proj<T> a) {
             h[u] = i[u] < n;
             zv[u] = h[u] ? a.z[i[u]] : T(0);
             pv[u] = (h[u] && !first) ? a.pold[i[u]] : T(0);
+            const int iu = h[u] ? i[u] : 0;
 #pragma unroll
-            for (int k = 0; k < MT; ++k) wv[u][k] = (h[u] && k < a.m) ? a.W[(size_t)k * n + i[u]] : T(0);
+            for (int k = 0; k < MT; ++k) wv[u][k] = a.W[(size_t)(k < a.m ? k : a.m - 1) * n + iu];
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (!h[u]) continue;
             double s = (double)zv[u];
 #pragma unroll
-            for (int k = 0; k < MT; ++k)
-                if (k < a.m) s -= (double)wv[u][k] * mu[k];
+            for (int k = 0; k < MT; ++k) s -= (double)wv[u][k] * mu[k];
             const T zh = (T)s;
             a.pnew[i[u]] = first ? zh : zh + beta * pv[u];
         }
@@ -1524,8 +1534,14 @@ void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s
 void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 
 template <typename T, int MT> static void update_it_mt(const UpdIt<T> &a, int grid, hipStream_t s) {
-    if (stream_pairs<T>(a.n)) k_update_it2<T, MT><<<grid, kBlock, 0, s>>>(a);
-    else k_update_it<T, MT><<<grid, kBlock, 0, s>>>(a);
+    // with G^T r a row already has MT + 4 loads in flight: one row per thread
+    if constexpr (MT == 0) {
+        if (stream_pairs<T>(a.n)) {
+            k_update_it2<T, 0><<<grid, kBlock, 0, s>>>(a);
+            return;
+        }
+    }
+    k_update_it<T, MT><<<grid, kBlock, 0, s>>>(a);
 }
 template <typename T> static void update_it_impl(const UpdIt<T> &a, int grid, hipStream_t s) {
     if (!a.G || a.m <= 0) update_it_mt<T, 0>(a, grid, s);
@@ -1536,9 +1552,8 @@ void launch_update_it(const UpdIt<double> &a, int grid, hipStream_t s) { update_
 void launch_update_it(const UpdIt<float> &a, int grid, hipStream_t s) { update_it_impl(a, grid, s); }
 
 template <typename T> static void proj_impl(const Proj<T> &a, int grid, hipStream_t s) {
-    if (stream_pairs<T>(a.n) && a.m <= 16) {
-        if (a.m <= 8) k_proj2<T, 8><<<grid, kBlock, 0, s>>>(a);
-        else k_proj2<T, 16><<<grid, kBlock, 0, s>>>(a);
+    if (stream_pairs<T>(a.n) && a.m <= 8) {
+        k_proj2<T, 8><<<grid, kBlock, 0, s>>>(a);
         return;
     }
     ESD_MT_SWITCH(a.m, (k_proj<T, (MTV > 0 ? MTV : 8)><<<grid, kBlock, 0, s>>>(a)));
