@@ -91,7 +91,9 @@ typedef struct {
 #define ESD_FLAG_POWER 2  /* power iteration fused into the SpMV, (q v) = A (p v) (Alg. PCG-con) */
 #define ESD_FLAG_MIXED 4  /* (ESD_PREC_MIXED contexts) FP32 inner solves inside an FP64 iterative-refinement loop; if a
                              refinement step fails to halve the FP64 residual the solve is
-                             finished by FP64 CG (reported in esd_info.fp64_iters) */
+                             finished by FP64 CG (reported in esd_info.fp64_iters), restarted
+                             from x (at most 4 times) while the recomputed residual misses tol
+                             and still drops by 10% per restart */
 #define ESD_FLAG_SYNC_EVERY 8 /* check convergence after every iteration (no speculative chunk) */
 #define ESD_FLAG_TIMING 16    /* hipEvents around the SpMV, update and sweep launches of every executed iteration */
 #define ESD_FLAG_TIMING_SPMV 32 /* hipEvents around the SpMV launch of every executed iteration only */

@@ -1063,7 +1063,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     st = sync_read(c);
     if (st) return st;
     const double bn2 = c->Sh->bnorm2, tol2 = c->Sh->tol2;
-    int total = 0, outer = 0, done_in = 0, fp64_iters = 0;
+    int total = 0, outer = 0, done_in = 0, fp64_iters = 0, fp64_restarts = 0;
     bool converged = false, fp64 = false;
     const bool method_b = sampling && c->samp_method == 1;
     if (method_b) arm_method_b(c, tol);
@@ -1096,10 +1096,13 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         if (total >= maxit || outer == c->max_outer) break;
         // a refinement step that does not halve the residual: the FP32 inner
         // operator is too far from A (kappa * u_32 >~ 1); finish in FP64
-        if (rn2_prev >= 0.0 && rn2 > 0.25 * rn2_prev) {
-            // an FP64 step that does not halve it either: the residual is at
-            // the FP64 rounding floor of b - A x; stop (not converged)
-            if (fp64) break;
+        if (fp64) {
+            // FP64 CG ran to the target on its recurrence residual and the
+            // recomputed one missed it: restart from x (at most 4 times) while
+            // that still takes 10% off the residual; otherwise the residual
+            // sits at the FP64 rounding floor of b - A x: stop (not converged)
+            if (rn2 > 0.81 * rn2_prev || ++fp64_restarts > 4) break;
+        } else if (rn2_prev >= 0.0 && rn2 > 0.25 * rn2_prev) {
             fp64 = true;
         }
         rn2_prev = rn2;
@@ -1450,7 +1453,7 @@ esd_status setup_impl(esd_ctx **out, void *hip_stream, int64_t n, int64_t nnz, c
             !esd::ell_classes(*ells[e], n, 64, ks[e]->csptr, ks[e]->soff, ks[e]->src))
             ks[e]->csptr.clear();
     std::vector<int32_t> tf, tl;
-    esd::tile_orders(H, colp, esd::kBlock, tf, tl, c->tmap_off);
+    esd::tile_orders(H, colp, esd::kBlock, tf, tl, c->tmap_off, esd::tile_parts(n), 1);
     Sizes z;
     z.n = n;
     z.nnz = H.nnz;

@@ -361,7 +361,7 @@ void tridiag_extremes(int k, const double *alpha, const double *beta, double *tm
 
 
 void tile_orders(const HostLayout &H, const int32_t *colors, int tile_rows, std::vector<int32_t> &full,
-                 std::vector<int32_t> &lvl, std::vector<int64_t> &lvl_off) {
+                 std::vector<int32_t> &lvl, std::vector<int64_t> &lvl_off, int sub_full, int sub_lvl) {
     const int64_t n = H.n;
     const int nl = (int)H.lvl_ptr.size() - 1;
     // segment of every physical row: runs of equal (level, colour)
@@ -382,12 +382,18 @@ void tile_orders(const HostLayout &H, const int32_t *colors, int tile_rows, std:
             a = b;
         }
     }
-    auto order = [&](int64_t r0, int64_t r1, std::vector<int32_t> &out) {
+    // key of a tile: the eighth of its segment (the XCD), then the sub-th part
+    // of that eighth; tiles of equal key keep their order (segment by
+    // segment).  With sub > 1 an XCD walks its eighth of every colour
+    // together, part by part, so the neighbours a part gathers from the
+    // other colours were fetched into its L2 shortly before.
+    auto order = [&](int64_t r0, int64_t r1, std::vector<int32_t> &out, int sub) {
+        const int nk = 8 * std::max(sub, 1);
         const int64_t nt = (r1 - r0 + tile_rows - 1) / tile_rows;
-        std::vector<std::vector<int32_t>> byk(8);
+        std::vector<std::vector<int32_t>> byk(nk);
         for (int64_t t = 0; t < nt; ++t) {
             const int64_t p = r0 + t * tile_rows;
-            const int k = (int)std::min<int64_t>(7, 8 * (p - seg_start[p]) / seg_len[p]);
+            const int k = (int)std::min<int64_t>(nk - 1, nk * (p - seg_start[p]) / seg_len[p]);
             byk[k].push_back((int32_t)t);
         }
         for (auto &v : byk) out.insert(out.end(), v.begin(), v.end());
@@ -396,10 +402,10 @@ void tile_orders(const HostLayout &H, const int32_t *colors, int tile_rows, std:
     lvl.clear();
     lvl_off.assign(nl + 1, 0);
     if (n == 0) return;
-    order(0, n, full);
+    order(0, n, full, sub_full);
     for (int l = 0; l < nl; ++l) {
         lvl_off[l] = (int64_t)lvl.size();
-        order(H.lvl_ptr[l], H.lvl_ptr[l + 1], lvl);
+        order(H.lvl_ptr[l], H.lvl_ptr[l + 1], lvl, sub_lvl);
     }
     lvl_off[nl] = (int64_t)lvl.size();
 }

@@ -117,6 +117,11 @@ int layout(const char *in, const char *out) {
     write_vec(o, tf);
     write_vec(o, tl);
     write_vec(o, toff);
+    // the same with 4 parts per eighth in the whole range and 2 in the levels
+    esd::tile_orders(H, has_colors ? colors.data() : nullptr, 256, tf, tl, toff, 4, 2);
+    write_vec(o, tf);
+    write_vec(o, tl);
+    write_vec(o, toff);
     fclose(o);
     return 0;
 }

@@ -76,6 +76,7 @@ def _run_layout(driver, tmp, p, block_rows=0):
         out[name + "_cls"] = int(R.one(np.int32))
         out[name + "_c"] = (R.vec(np.int64), R.vec(np.int64), R.vec(np.float64))
     out["tf"], out["tl"], out["toff"] = R.vec(np.int32), R.vec(np.int32), R.vec(np.int64)
+    out["tf4"], out["tl2"], out["toff2"] = R.vec(np.int32), R.vec(np.int32), R.vec(np.int64)
     return out
 
 
@@ -157,12 +158,16 @@ def test_layout_reproduces_the_matrix(driver, tmp_path, name):
             got = sorted(zip(*[x.tolist() for x in out[m + "_c"]]))
             exp = sorted(zip(*[x.tolist() for x in out[m]]))
             assert got == exp
-    # tile orders are permutations of the tiles of each range
-    assert np.array_equal(np.sort(out["tf"]), np.arange((n + 255) // 256))
-    for lv in range(len(out["lvl"]) - 1):
-        rows = out["lvl"][lv + 1] - out["lvl"][lv]
-        seg = out["tl"][out["toff"][lv]:out["toff"][lv + 1]]
-        assert np.array_equal(np.sort(seg), np.arange((rows + 255) // 256))
+    # tile orders are permutations of the tiles of each range, with one or
+    # several parts per eighth
+    nt = (n + 255) // 256
+    for tf, tl, toff in ((out["tf"], out["tl"], out["toff"]), (out["tf4"], out["tl2"], out["toff2"])):
+        assert np.array_equal(np.sort(tf), np.arange(nt))
+        for lv in range(len(out["lvl"]) - 1):
+            rows = out["lvl"][lv + 1] - out["lvl"][lv]
+            seg = tl[toff[lv]:toff[lv + 1]]
+            assert np.array_equal(np.sort(seg), np.arange((rows + 255) // 256))
+    assert np.array_equal(out["toff"], out["toff2"])
 
 
 def test_class_layout_is_taken_where_it_fits(driver, tmp_path):
