@@ -90,7 +90,8 @@ typedef struct {
 #define ESD_FLAG_NOPREC 1 /* M = I (unpreconditioned CG), used for closed-form checks */
 #define ESD_FLAG_POWER 2  /* power iteration fused into the SpMV, (q v) = A (p v) (Alg. PCG-con) */
 #define ESD_FLAG_MIXED 4  /* (ESD_PREC_MIXED contexts) FP32 inner solves inside an FP64 iterative-refinement loop; if a
-                             refinement step fails to halve the FP64 residual the solve is
+                             refinement step fails to halve the FP64 residual, or its inner run
+                             stagnated before reducing it 100-fold, the solve is
                              finished by FP64 CG (reported in esd_info.fp64_iters), restarted
                              from x (at most 4 times) while the recomputed residual misses tol
                              and still drops by 10% per restart */

@@ -1102,7 +1102,9 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
             // that still takes 10% off the residual; otherwise the residual
             // sits at the FP64 rounding floor of b - A x: stop (not converged)
             if (rn2 > 0.81 * rn2_prev || ++fp64_restarts > 4) break;
-        } else if (rn2_prev >= 0.0 && rn2 > 0.25 * rn2_prev) {
+        } else if (rn2_prev >= 0.0 && (rn2 > 0.25 * rn2_prev || (done_in == 4 && rn2 > 1e-4 * rn2_prev))) {
+            // ... or an inner run that stagnated before taking two orders of
+            // magnitude off the residual: FP32 cannot resolve this operator
             fp64 = true;
         }
         rn2_prev = rn2;
