@@ -93,8 +93,7 @@ typedef struct {
                              refinement step fails to halve the FP64 residual, or its inner run
                              stagnated before reducing it 100-fold, the solve is
                              finished by FP64 CG (reported in esd_info.fp64_iters), restarted
-                             from x (at most 4 times) while the recomputed residual misses tol
-                             and still drops by 10% per restart */
+                             from x (at most 4 times) while the recomputed residual misses tol */
 #define ESD_FLAG_SYNC_EVERY 8 /* check convergence after every iteration (no speculative chunk) */
 #define ESD_FLAG_TIMING 16    /* hipEvents around the SpMV, update and sweep launches of every executed iteration */
 #define ESD_FLAG_TIMING_SPMV 32 /* hipEvents around the SpMV launch of every executed iteration only */

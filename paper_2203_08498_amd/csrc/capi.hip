@@ -796,7 +796,10 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
         }
     }
     *iters = c->Sh->iter - iter0;
-    *vbase = (*vbase + *iters) & 1;
+    // the power iterate alternates between v[0] and v[1] only in runs that
+    // carry it: a run without it must not move the next power run's start
+    // to the other (possibly never written) buffer
+    if (o.power) *vbase = (*vbase + *iters) & 1;
     return ESD_OK;
 }
 
@@ -1098,10 +1101,10 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
         // operator is too far from A (kappa * u_32 >~ 1); finish in FP64
         if (fp64) {
             // FP64 CG ran to the target on its recurrence residual and the
-            // recomputed one missed it: restart from x (at most 4 times) while
-            // that still takes 10% off the residual; otherwise the residual
-            // sits at the FP64 rounding floor of b - A x: stop (not converged)
-            if (rn2 > 0.81 * rn2_prev || ++fp64_restarts > 4) break;
+            // recomputed one missed it: restart from x, at most 4 times (as
+            // ESD_FLAG_TRUE_RES does); a residual at the FP64 rounding floor of
+            // b - A x ends the solve there, not converged
+            if (++fp64_restarts > 4) break;
         } else if (rn2_prev >= 0.0 && (rn2 > 0.25 * rn2_prev || (done_in == 4 && rn2 > 1e-4 * rn2_prev))) {
             // ... or an inner run that stagnated before taking two orders of
             // magnitude off the residual: FP32 cannot resolve this operator

@@ -601,6 +601,32 @@ def test_power_iteration_kappa_es(case):
     assert abs(i2["kappa_es"] / j2.kappa_es - 1) <= 1e-6
 
 
+def test_power_iteration_after_solves_without_it():
+    """The power iterate lives in two buffers that the iterations alternate
+    between; solves without the power iteration (here with odd iteration
+    counts, FP64 and mixed) must leave the next power solve starting from the
+    vector set by set_power_start: lambda_max equal to a fresh context's."""
+    from paper_2203_08498_amd import esd
+
+    p = CASES["fv3d_colors"]
+    v0 = P.power_start(3, p.n)
+    fresh = _solver(p)
+    fresh.factor_ic0()
+    fresh.set_power_start(v0)
+    _, ref = fresh.solve(p.f, tol=1e-8, maxit=5000, flags=esd.FLAG_POWER)
+    fresh.close()
+    s = _solver(p)
+    s.factor_ic0()
+    s.set_power_start(v0)
+    for its in (7, 13):
+        s.solve(p.f, tol=0.0, maxit=its)
+        s.solve(p.f, tol=0.0, maxit=its, flags=esd.FLAG_MIXED)
+    _, info = s.solve(p.f, tol=1e-8, maxit=5000, flags=esd.FLAG_POWER)
+    print("lambda_max after solves without the power iteration", info["lambda_max"], ref["lambda_max"], flush=True)
+    assert np.isfinite(info["lambda_max"]) and info["lambda_max"] == ref["lambda_max"]
+    s.close()
+
+
 def test_mixed_precision_meets_fp64_tolerance(case):
     from paper_2203_08498_amd import esd
 
