@@ -55,6 +55,9 @@ template <typename T> struct Ell {
     // is read and multiplied by zero).  The layout moves no column indices,
     // only one offset per 64 entries.
     const int32_t *soff;
+    // nonzero: values (and columns) are loaded non-temporally, for matrices
+    // that outgrow the last-level cache together with the iteration's vectors
+    int nt;
 };
 
 // Reducing kernels write one row of `stride` doubles per block to `part`

@@ -138,22 +138,21 @@ __device__ __forceinline__ void fin_colsum(const double *part, int nblk, int str
 // per-iteration kernels
 // ------------------------------------------------------------------------
 
-// Loads the columns and values of slots k0 .. k0+7 of row i (slice starting
-// at entry `base`, width w > k0); slots past w get column n and value 0.  No
-// loaded value is used before all loads of the chunk are issued.  Class-
-// aligned layout: column = row + offset of the slot, clamped into [0, n]; a
-// row without an entry in a slot holds the value 0 there, so whatever finite
-// value the clamped column gathers is multiplied by zero.
-template <typename T, int K = 8>
-__device__ __forceinline__ void ell_chunk(const Ell<T> &M, int64_t base, int w, int k0, int i, int n, int (&c)[K],
-                                          T (&a)[K]) {
+template <bool NT, typename T> __device__ __forceinline__ T ld_slot(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT, typename T, int K>
+__device__ __forceinline__ void ell_chunk_ld(const Ell<T> &M, int64_t base, int w, int k0, int i, int n, int (&c)[K],
+                                             T (&a)[K]) {
     const int lane = i & 63;
     if (M.soff) {
         int off[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (k0 + k < w) {
-                a[k] = M.val[base + (int64_t)(k0 + k) * 64 + lane];
+                a[k] = ld_slot<NT>(&M.val[base + (int64_t)(k0 + k) * 64 + lane]);
                 off[k] = M.soff[(base >> 6) + k0 + k];
             } else {
                 a[k] = T(0);
@@ -167,14 +166,29 @@ __device__ __forceinline__ void ell_chunk(const Ell<T> &M, int64_t base, int w, 
         for (int k = 0; k < K; ++k) {
             if (k0 + k < w) {
                 const int64_t pos = base + (int64_t)(k0 + k) * 64 + lane;
-                a[k] = M.val[pos];
-                c[k] = M.col[pos];
+                a[k] = ld_slot<NT>(&M.val[pos]);
+                c[k] = ld_slot<NT>(&M.col[pos]);
             } else {
                 a[k] = T(0);
                 c[k] = n;
             }
         }
     }
+}
+
+// Loads the columns and values of slots k0 .. k0+K-1 of row i (slice starting
+// at entry `base`, width w > k0); slots past w get column n and value 0.  No
+// loaded value is used before all loads of the chunk are issued.  Class-
+// aligned layout: column = row + offset of the slot, clamped into [0, n]; a
+// row without an entry in a slot holds the value 0 there, so whatever finite
+// value the clamped column gathers is multiplied by zero.  M.nt: the slot
+// loads are non-temporal, so the matrix streams past the caches and they keep
+// the gathered vectors instead.
+template <typename T, int K = 8>
+__device__ __forceinline__ void ell_chunk(const Ell<T> &M, int64_t base, int w, int k0, int i, int n, int (&c)[K],
+                                          T (&a)[K]) {
+    if (M.nt) ell_chunk_ld<true>(M, base, w, k0, i, n, c, a);
+    else ell_chunk_ld<false>(M, base, w, k0, i, n, c, a);
 }
 
 // Start entry and width of row i's slice.  U: the caller guarantees that all
