@@ -643,6 +643,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     ua.n = n; ua.S = c->S; ua.part = c->part_upd; ua.q = V.q; ua.x = V.x; ua.r = V.r; ua.tmap = c->tmap;
     ua.l0 = fuse_l0 ? (int)c->lvl[1] : 0; ua.dinv = V.dinv; ua.y = V.y;
     ua.G = G; ua.m = G ? m : 0;
+    ua.xnt = V.A.nt; // with the matrix: x then outgrows the caches as well
+    ua.gnt = defl ? 1 : 0; // Y is read only here; the subspace correction's W again by the sweep
     esd::FinRho fr{};
     fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = su;
     fr.rho_upd = (fuse_l0 && !sc) ? 1 : 0;

@@ -103,6 +103,8 @@ template <typename T> struct UpdIt {
     // subspace correction's W^T r, without a separate pass over z or r
     const T *G;
     int m;
+    int xnt; // nonzero: x (read and written only here) is loaded and stored non-temporally
+    int gnt; // nonzero: the columns of G are loaded non-temporally (G read by no other launch)
     // partials: column 0 ||r||^2, column 1 ||y||^2 of the fused level-0 rows,
     // columns 2 .. 2 + m of G^T r (row stride update_stride(m))
 };

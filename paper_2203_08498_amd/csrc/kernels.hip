@@ -142,6 +142,14 @@ template <bool NT, typename T> __device__ __forceinline__ T ld_slot(const T *p) 
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
+template <bool NT, typename T> __device__ __forceinline__ void st_slot(T v, T *p) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Columns of W, AW or Y are read once per iteration: non-temporal loads keep
+// them from evicting the vectors that the next launches read again.
+template <typename T> __device__ __forceinline__ T ld_col(const T *p) { return __builtin_nontemporal_load(p); }
 
 template <bool NT, typename T, int K>
 __device__ __forceinline__ void ell_chunk_ld(const Ell<T> &M, int64_t base, int w, int k0, int i, int n, int (&c)[K],
@@ -304,8 +312,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_it(SpmvIt<T> a) {
 // x += alpha p, r -= alpha q, ||r||^2; rows of the first sweep level (i < l0)
 // also take y = r / l_ii and ||y||^2 (the level-0 forward sweep fused here);
 // MT > 0: also G^T r of the new residual (G column-major, a.m <= MT columns,
-// one coalesced load per column)
-template <typename T, int MT>
+// one coalesced load per column).  XNT / GNT: x / the columns of G are
+// loaded (and x stored) non-temporally.
+template <typename T, int MT, bool XNT, bool GNT>
 __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
@@ -324,9 +333,9 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
             // columns past m re-read column m - 1 (unused sums): no condition
             // on the loads, so they are all in flight together
 #pragma unroll
-            for (int k = 0; k < MT; ++k) g[k] = a.G[(size_t)(k < a.m ? k : a.m - 1) * n + i];
+            for (int k = 0; k < MT; ++k) g[k] = ld_slot<GNT>(&a.G[(size_t)(k < a.m ? k : a.m - 1) * n + i]);
         }
-        a.x[i] += ta * a.p[i];
+        st_slot<XNT>(ld_slot<XNT>(&a.x[i]) + ta * a.p[i], &a.x[i]);
         const T ri = a.r[i] - ta * a.q[i];
         a.r[i] = ri;
         acc[0] += (double)ri * (double)ri;
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_update_it(UpdIt<T> a) {
 // row moves half the bytes of an FP64 one per load instruction, so one row
 // per thread leaves the FP32 streams short of loads in flight.  Same
 // arithmetic per row as k_update_it.
-template <typename T, int MT>
+template <typename T, int MT, bool XNT, bool GNT>
 __global__ __launch_bounds__(kBlock) void k_update_it2(UpdIt<T> a) {
     Scal *S = a.S;
     if (S->done) return;
@@ -371,19 +380,19 @@ __global__ __launch_bounds__(kBlock) void k_update_it2(UpdIt<T> a) {
             h[u] = i[u] < n;
             qv[u] = h[u] ? a.q[i[u]] : T(0);
             pv[u] = h[u] ? a.p[i[u]] : T(0);
-            xv[u] = h[u] ? a.x[i[u]] : T(0);
+            xv[u] = h[u] ? ld_slot<XNT>(&a.x[i[u]]) : T(0);
             rv[u] = h[u] ? a.r[i[u]] : T(0);
             dv[u] = (h[u] && i[u] < a.l0) ? a.dinv[i[u]] : T(0);
             if constexpr (MT > 0) {
                 const int iu = h[u] ? i[u] : 0;
 #pragma unroll
-                for (int k = 0; k < MT; ++k) g[u][k] = a.G[(size_t)(k < a.m ? k : a.m - 1) * n + iu];
+                for (int k = 0; k < MT; ++k) g[u][k] = ld_slot<GNT>(&a.G[(size_t)(k < a.m ? k : a.m - 1) * n + iu]);
             }
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (!h[u]) continue;
-            a.x[i[u]] = xv[u] + ta * pv[u];
+            st_slot<XNT>(xv[u] + ta * pv[u], &a.x[i[u]]);
             const T ri = rv[u] - ta * qv[u];
             a.r[i[u]] = ri;
             acc[0] += (double)ri * (double)ri;
@@ -420,7 +429,7 @@ __global__ __launch_bounds__(kTsBlock) void k_tsdot_rm(TsDot<T> a) {
     if (k < m) {
 #pragma unroll 4
         for (int r = r0 + wid * RPW + ro; r < r1; r += STEP)
-            acc += (double)a.Wrm[(size_t)r * m + k] * (double)a.v[r];
+            acc += (double)ld_col(&a.Wrm[(size_t)r * m + k]) * (double)a.v[r];
     }
 #pragma unroll
     for (int off = 32; off >= P; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -990,7 +999,7 @@ __global__ __launch_bounds__(kBlock) void k_proj(Proj<T> a) {
         // condition and stay in flight together
         T w[MT];
 #pragma unroll
-        for (int k = 0; k < MT; ++k) w[k] = a.W[(size_t)(k < a.m ? k : a.m - 1) * n + i];
+        for (int k = 0; k < MT; ++k) w[k] = ld_col(&a.W[(size_t)(k < a.m ? k : a.m - 1) * n + i]);
         const T zi = a.z[i];
         const T po = first ? T(0) : a.pold[i];
         double s = (double)zi;
@@ -1027,7 +1036,7 @@ __global__ __launch_bounds__(kBlock) void k_proj2(Proj<T> a) {
             pv[u] = (h[u] && !first) ? a.pold[i[u]] : T(0);
             const int iu = h[u] ? i[u] : 0;
 #pragma unroll
-            for (int k = 0; k < MT; ++k) wv[u][k] = a.W[(size_t)(k < a.m ? k : a.m - 1) * n + iu];
+            for (int k = 0; k < MT; ++k) wv[u][k] = ld_col(&a.W[(size_t)(k < a.m ? k : a.m - 1) * n + iu]);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -1547,15 +1556,25 @@ template <typename T> static void spmv_it_impl(const SpmvIt<T> &a, bool power, i
 void launch_spmv_it(const SpmvIt<double> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 void launch_spmv_it(const SpmvIt<float> &a, bool power, int grid, hipStream_t s) { spmv_it_impl(a, power, grid, s); }
 
-template <typename T, int MT> static void update_it_mt(const UpdIt<T> &a, int grid, hipStream_t s) {
+template <typename T, int MT, bool XNT, bool GNT>
+static void update_it_nt(const UpdIt<T> &a, int grid, hipStream_t s) {
     // with G^T r a row already has MT + 4 loads in flight: one row per thread
     if constexpr (MT == 0) {
         if (stream_pairs<T>(a.n)) {
-            k_update_it2<T, 0><<<grid, kBlock, 0, s>>>(a);
+            k_update_it2<T, 0, XNT, false><<<grid, kBlock, 0, s>>>(a);
             return;
         }
     }
-    k_update_it<T, MT><<<grid, kBlock, 0, s>>>(a);
+    k_update_it<T, MT, XNT, GNT><<<grid, kBlock, 0, s>>>(a);
+}
+template <typename T, int MT> static void update_it_mt(const UpdIt<T> &a, int grid, hipStream_t s) {
+    if (a.xnt) {
+        if (a.gnt) update_it_nt<T, MT, true, true>(a, grid, s);
+        else update_it_nt<T, MT, true, false>(a, grid, s);
+    } else {
+        if (a.gnt) update_it_nt<T, MT, false, true>(a, grid, s);
+        else update_it_nt<T, MT, false, false>(a, grid, s);
+    }
 }
 template <typename T> static void update_it_impl(const UpdIt<T> &a, int grid, hipStream_t s) {
     if (!a.G || a.m <= 0) update_it_mt<T, 0>(a, grid, s);
