@@ -387,10 +387,14 @@ constexpr double kLlcBytes = 256.0 * 1024 * 1024;
 // caches (FP64 at 128^3: SpMV 45.1 -> 42.8 us, sweep pair 60.1 -> 56.4 us;
 // FP32 sweeps on the Q1 160^3 matrix 166 -> 143 us).  A matrix that fits
 // keeps ordinary loads (FP32 at 128^3: 20.8 against 23.2 us per SpMV with
-// streamed loads, which re-read it from HBM every iteration).
+// streamed loads, which re-read it from HBM every iteration; the FP64
+// block-Jacobi iteration at 128^3, A and eight vectors in 251 MB: 30.7
+// against 41.3 us).  The scan block-Jacobi iteration reads no triangle: its
+// factor is two of the eight vectors.
 template <typename T> int stream_matrix(const esd_ctx *c) {
     auto slots = [](const DevEll &e) { return (double)(e.csize ? e.csize : e.size); };
-    const double bytes = (slots(c->A) + slots(c->L) + slots(c->U)) * sizeof(T) + 8.0 * (double)c->n * sizeof(T);
+    const double tri = c->bj_rows > 0 ? 0.0 : slots(c->L) + slots(c->U);
+    const double bytes = (slots(c->A) + tri) * sizeof(T) + 8.0 * (double)c->n * sizeof(T);
     return bytes > kLlcBytes ? 1 : 0;
 }
 

@@ -1568,11 +1568,12 @@ static void update_it_nt(const UpdIt<T> &a, int grid, hipStream_t s) {
     k_update_it<T, MT, XNT, GNT><<<grid, kBlock, 0, s>>>(a);
 }
 template <typename T, int MT> static void update_it_mt(const UpdIt<T> &a, int grid, hipStream_t s) {
+    const bool gnt = MT > 0 && a.gnt; // without G the flag means nothing: one kernel fewer
     if (a.xnt) {
-        if (a.gnt) update_it_nt<T, MT, true, true>(a, grid, s);
+        if (gnt) update_it_nt<T, MT, true, MT != 0>(a, grid, s);
         else update_it_nt<T, MT, true, false>(a, grid, s);
     } else {
-        if (a.gnt) update_it_nt<T, MT, false, true>(a, grid, s);
+        if (gnt) update_it_nt<T, MT, false, MT != 0>(a, grid, s);
         else update_it_nt<T, MT, false, false>(a, grid, s);
     }
 }
