@@ -98,7 +98,9 @@ typedef struct {
 #define ESD_FLAG_TIMING 16    /* hipEvents around the SpMV, update and sweep launches of every executed iteration */
 #define ESD_FLAG_TIMING_SPMV 32 /* hipEvents around the SpMV launch of every executed iteration only */
 #define ESD_FLAG_TRUE_RES 64  /* FP64: after the recurrence test, restart from x while the recomputed
-                                 residual misses tol (at most 4 restarts) */
+                                 residual misses tol (at most 4 restarts); a deflated restart that
+                                 does not halve the recomputed residual is followed by plain PCG
+                                 restarts (the same rule holds in the FP64 finish of ESD_FLAG_MIXED) */
 #define ESD_FLAG_STREAM 128   /* launch every kernel on the stream; by default the iterations run as
                                  replays of captured 16- and 4-iteration HIP graphs (the short one
                                  near the stop the residual's rate predicts), cached in the context
@@ -202,9 +204,9 @@ esd_status esd_workspace_used(const esd_ctx *ctx, size_t *bytes);
 esd_status esd_update_values(esd_ctx *ctx, const double *val);
 
 /* esd_factor_ic0 - IC(0) on the stored lower pattern in the chosen order (the
- * paper's IC preconditioner, Sec. 4.4); after esd_setup_block_jacobi, IC(0)
- * of the block-diagonal part (Sec. 5.3).  FP64 factor plus an FP32 copy.
- * ESD_ENOTSPD on a non-positive pivot. */
+ * paper's IC preconditioner, Sec. 4.4); with ESD_ORDER_BLOCK_JACOBI, IC(0)
+ * of the block-diagonal part (Sec. 5.3).  FP64 factor, plus an FP32 copy in
+ * ESD_PREC_MIXED contexts.  ESD_ENOTSPD on a non-positive pivot. */
 esd_status esd_factor_ic0(esd_ctx *ctx);
 
 /* esd_sample_errors - arm sampling with m slots (1 <= m <= m_max) for the next

@@ -380,22 +380,25 @@ esd_status put_scal(esd_ctx *c) {
 // Last-level cache of the GPU (MI355X: 256 MB of Infinity Cache).
 constexpr double kLlcBytes = 256.0 * 1024 * 1024;
 
-// Non-temporal matrix loads for the iteration in precision T when its matrix
-// values (A and the two triangles) and eight vectors outgrow the last-level
-// cache: the matrix cannot stay cached from one iteration to the next then,
-// and streaming it keeps the gathered and the next launch's vectors in the
-// caches (FP64 at 128^3: SpMV 45.1 -> 42.8 us, sweep pair 60.1 -> 56.4 us;
-// FP32 sweeps on the Q1 160^3 matrix 166 -> 143 us).  A matrix that fits
-// keeps ordinary loads (FP32 at 128^3: 20.8 against 23.2 us per SpMV with
-// streamed loads, which re-read it from HBM every iteration; the FP64
-// block-Jacobi iteration at 128^3, A and eight vectors in 251 MB: 30.7
-// against 41.3 us).  The scan block-Jacobi iteration reads no triangle: its
-// factor is two of the eight vectors.
-template <typename T> int stream_matrix(const esd_ctx *c) {
+// Non-temporal loads for the iteration's matrices in precision T, chosen
+// against the last-level cache.  When A, the two triangles and eight vectors
+// (plus `keep` bytes more that the iteration reads twice) outgrow it, the
+// triangles stream (non-temporal loads), so that A and the vectors can stay
+// cached from one iteration to the next; when A and the vectors alone
+// outgrow it, A streams too.  Streamed data no longer evicts the gathered
+// vectors and those the next launch reads.  The scan block-Jacobi iteration
+// reads no triangle: its factor is two of the eight vectors.  Measured at
+// 128^3 in FP64 (A and the vectors cached, triangles streamed, against all
+// three streamed): plain iteration 127.9 -> 123.6 us, deflated 165.5 ->
+// 160.7 us; the subspace correction, whose W is read twice, keeps A
+// streamed (176.2 us with A cached against 168.8 us).
+template <typename T> void stream_policy(const esd_ctx *c, double keep, int &a_nt, int &tri_nt) {
     auto slots = [](const DevEll &e) { return (double)(e.csize ? e.csize : e.size); };
-    const double tri = c->bj_rows > 0 ? 0.0 : slots(c->L) + slots(c->U);
-    const double bytes = (slots(c->A) + tri) * sizeof(T) + 8.0 * (double)c->n * sizeof(T);
-    return bytes > kLlcBytes ? 1 : 0;
+    const double vec = 8.0 * (double)c->n * sizeof(T) + keep;
+    const double a = slots(c->A) * sizeof(T);
+    const double tri = c->bj_rows > 0 ? 0.0 : (slots(c->L) + slots(c->U)) * sizeof(T);
+    tri_nt = a + tri + vec > kLlcBytes ? 1 : 0;
+    a_nt = a + vec > kLlcBytes ? 1 : 0;
 }
 
 template <typename T> VecSet<T> vecs(esd_ctx *c);
@@ -406,7 +409,8 @@ template <> VecSet<double> vecs<double>(esd_ctx *c) {
     V.W = c->W; V.AW = c->AW; V.Wrm = c->W_rm; V.AWrm = c->AW_rm; V.dinv = c->dinv; V.lsub = c->lsub;
     V.Y = c->Y;
     V.A = c->A.it64(); V.L = c->L.it64(); V.U = c->U.it64();
-    V.A.nt = V.L.nt = V.U.nt = stream_matrix<double>(c);
+    stream_policy<double>(c, 0.0, V.A.nt, V.L.nt);
+    V.U.nt = V.L.nt;
     return V;
 }
 template <> VecSet<float> vecs<float>(esd_ctx *c) {
@@ -416,7 +420,8 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
     V.W = c->W32; V.AW = c->AW32; V.Wrm = c->W32_rm; V.AWrm = c->AW32_rm; V.dinv = c->dinv32; V.lsub = c->lsub32;
     V.Y = c->Y32;
     V.A = c->A.it32(); V.L = c->L.it32(); V.U = c->U.it32();
-    V.A.nt = V.L.nt = V.U.nt = stream_matrix<float>(c);
+    stream_policy<float>(c, 0.0, V.A.nt, V.L.nt);
+    V.U.nt = V.L.nt;
     return V;
 }
 
@@ -581,10 +586,17 @@ struct KrylovOpts {
 // residual update of the deflated PCG (P^T A = A P for symmetric A).  The
 // range(W) part of x is fixed by the final correction.
 template <typename T>
-esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iters, int *vbase) {
+esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *iters, int *vbase) {
     const int n = (int)c->n;
     const int m = (o.kind != 0) ? c->m_tilde : 0;
     const bool sc = (o.kind == 2), defl = (o.kind == 1);
+    VecSet<T> V = V0;
+    if (sc && m > 0) {
+        // the subspace correction reads W twice per iteration (W^T r in the
+        // update, W u in the sweep): it counts against the cache with A
+        stream_policy<T>(c, (double)m * n * sizeof(T), V.A.nt, V.L.nt);
+        V.U.nt = V.L.nt;
+    }
     const int gt = m > 0 ? esd::tsdot_grid(n, m) : 1;
     const int st_t = m > 0 ? esd::tsdot_stride(m) : 1;
     const int gn = esd::stream_grid<T>(n);
@@ -647,7 +659,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V, const KrylovOpts &o, int *iter
     ua.n = n; ua.S = c->S; ua.part = c->part_upd; ua.q = V.q; ua.x = V.x; ua.r = V.r; ua.tmap = c->tmap;
     ua.l0 = fuse_l0 ? (int)c->lvl[1] : 0; ua.dinv = V.dinv; ua.y = V.y;
     ua.G = G; ua.m = G ? m : 0;
-    ua.xnt = V.A.nt; // with the matrix: x then outgrows the caches as well
+    ua.xnt = V.L.nt; // x (touched once per iteration) streams whenever the working set outgrows the cache
     ua.gnt = defl ? 1 : 0; // Y is read only here; the subspace correction's W again by the sweep
     esd::FinRho fr{};
     fr.S = c->S; fr.part_upd = c->part_upd; fr.nblk_upd = gu; fr.stride_upd = su;
@@ -949,10 +961,11 @@ void get_method_b(esd_ctx *c) {
 esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol, int maxit, int kind,
                       int flags, double *xout, esd_info *info) {
     const int n = (int)c->n;
-    const int m = kind ? c->m_tilde : 0;
+    int m = kind ? c->m_tilde : 0;
     const bool sampling = c->armed;
     const bool power = (flags & ESD_FLAG_POWER) != 0;
     const bool restart = (flags & ESD_FLAG_TRUE_RES) != 0;
+    const int kind_in = kind;
     auto V = vecs<double>(c);
     clear_sweep_vectors(c);
     esd::launch_gather(n, c->p2u, b, c->b, c->stream);
@@ -975,7 +988,7 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
     const bool method_b = sampling && c->samp_method == 1;
     if (method_b) arm_method_b(c, tol);
     int total = 0, done = 0, cycles = 0;
-    double rr = 0.0, tr2 = 0.0;
+    double rr = 0.0, tr2 = 0.0, tr2_prev = -1.0;
     for (;;) {
         // r_0 = b - A x_0; deflation: r_0 = P^T r_0 = r_0 - AW C^{-1} W^T r_0;
         // subspace correction: u = C^{-1} W^T r_0 for z_0
@@ -1032,6 +1045,16 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
         ++cycles;
         // optional: restart from x while the recomputed residual misses the tolerance
         if (!restart || done != 1 || tr2 <= tol2 || cycles > 4 || total >= maxit) break;
+        // a deflated restart that did not halve the recomputed residual stops
+        // deflating: what is left is the rounding of the projection and the
+        // coarse correction, which plain PCG from this x removes in a few
+        // iterations (Q1 160^3 with 20 columns of W: one iteration from
+        // relres 3.3e-7 to 4.5e-8, where deflated restarts stayed at 2e-7)
+        if (kind == 1 && tr2_prev >= 0.0 && tr2 > 0.25 * tr2_prev) {
+            kind = 0;
+            m = 0;
+        }
+        tr2_prev = tr2;
     }
     if (power) {
         int nb = 0;
@@ -1054,9 +1077,9 @@ esd_status solve_fp64(esd_ctx *c, const double *b, const double *x0, double tol,
         info->iters = total;
         info->outer_iters = cycles;
         info->converged = (done == 1) && (!restart || tr2 <= tol2);
-        info->m_tilde = m;
+        info->m_tilde = kind_in ? c->m_tilde : 0;
         info->nsamples = sampling ? c->nsamples : 0;
-        info->mode_used = kind;
+        info->mode_used = kind_in;
         info->relres = bn2 > 0 ? std::sqrt(rr / bn2) : std::sqrt(rr);
         info->true_relres = bn2 > 0 ? std::sqrt(tr2 / bn2) : std::sqrt(tr2);
         info->lambda_max = power ? c->Sh->lam : 0.0;
@@ -1104,9 +1127,12 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     double s_in = 1.0;
     int last_in = 0;
     c->segments.clear();
+    // mode of the FP64 finish: deflated restarts that stop halving the
+    // recomputed residual continue as plain PCG (as in solve_fp64)
+    int kind_fin = kind;
     for (outer = 0; outer <= c->max_outer; ++outer) {
         // FP64 true residual; deflation: coarse correction x += W C^{-1} W^T r
-        if (kind == 1) {
+        if (kind == 1 && kind_fin == 1) {
             dev_resid(c, c->b, c->x, c->r, c->W, m, c->S->mu, nullptr, 0);
             dev_axpy(c, c->x, c->W, m, c->S->mu, 1.0, nullptr, 0);
             dev_axpy(c, c->r, c->AW, m, c->S->mu, -1.0, &c->S->out, 0);
@@ -1130,6 +1156,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
             // ESD_FLAG_TRUE_RES does); a residual at the FP64 rounding floor of
             // b - A x ends the solve there, not converged
             if (++fp64_restarts > 4) break;
+            if (kind_fin == 1 && fp64_restarts >= 2 && rn2 > 0.25 * rn2_prev) kind_fin = 0;
         } else if (rn2_prev >= 0.0 && (rn2 > 0.25 * rn2_prev || (done_in == 4 && rn2 > 1e-4 * rn2_prev))) {
             // ... or an inner run that stagnated before taking two orders of
             // magnitude off the residual: FP32 cannot resolve this operator
@@ -1150,7 +1177,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
             if ((st = put_scal(c))) return st;
             if (kind == 2) dev_tsdot(c, c->W, m, c->r, c->S->u, 1.0);
             KrylovOpts o;
-            o.kind = kind;
+            o.kind = kind_fin;
             o.noprec = (flags & ESD_FLAG_NOPREC) != 0;
             o.power = false;
             o.sampling = sampling;
@@ -1166,7 +1193,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
             total += it64;
             fp64_iters += it64;
             if (c->Sh->done == 3) return fail(c, ESD_ENUMERIC, "non-finite value in the FP64 finish");
-            if (kind == 1) {
+            if (kind_fin == 1) {
                 dev_resid(c, c->b, c->x, c->t, c->W, m, c->S->mu, nullptr, 0);
                 dev_axpy(c, c->x, c->W, m, c->S->mu, 1.0, nullptr, 0);
             }
