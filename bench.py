@@ -336,8 +336,8 @@ def config3_spec(esd, P, theta):
 
 def config4_spec(esd, P, theta):
     """Config 4 as specified: Q1 27-point on 160^3 nodes with 64 floating
-    blocks, m = 64, 20 systems, kappa per system; FP64 and FP32/FP64 mixed,
-    plain against deflated.  Every solve is driven to one true-residual
+    blocks, m = 64, 20 systems, kappa per system; FP64 and FP32/FP64 mixed
+    (adaptive: ESD_FLAG_MIXED_ADAPT), plain against deflated.  Every solve is driven to one true-residual
     target: relres 1e-8, or 3x the FP64 rounding floor of b - A x when that
     is higher (FP64 solves test the recomputed residual, ESD_FLAG_TRUE_RES;
     mixed solves test it by construction).  The mixed deflated sequence's
@@ -363,10 +363,14 @@ def config4_spec(esd, P, theta):
         tol = max(1e-8, 3.0 * floor)
         out["fp64_floor"] = floor
         out["tol_true_relres"] = tol
+        # the mixed sequences run adaptively (ESD_FLAG_MIXED_ADAPT): FP32 cannot
+        # resolve this operator, and once a mixed solve in a mode has had to
+        # finish in FP64, the later ones in that mode start there
+        adapt = esd.FLAG_MIXED | esd.FLAG_MIXED_ADAPT
         for label, mode, flags, ref in (("fp64_plain", esd.PLAIN, esd.FLAG_TRUE_RES, None),
                                         ("fp64_deflated", esd.DEFLATED, esd.FLAG_TRUE_RES, None),
-                                        ("mixed_plain", esd.PLAIN, esd.FLAG_MIXED, None),
-                                        ("mixed_deflated", esd.DEFLATED, esd.FLAG_MIXED, esd.FLAG_TRUE_RES)):
+                                        ("mixed_plain", esd.PLAIN, adapt, None),
+                                        ("mixed_deflated", esd.DEFLATED, adapt, esd.FLAG_TRUE_RES)):
             recs, wall, build, _ = run_spec_sequence(s, f, esd, K, m, theta, mode, flags, tol, 60000,
                                                      ref=ref, ref_tol=tol)
             out[label] = _seq_summary(recs, wall, build, K)

@@ -111,6 +111,12 @@ typedef struct {
                                    run's FP32 recurrence residual and the run continues with its
                                    search direction (beta recomputed from the new residual's rho).
                                    An inner run that stagnated is followed by a fresh one. */
+#define ESD_FLAG_MIXED_ADAPT 512 /* with ESD_FLAG_MIXED: the context remembers, per mode (plain,
+                                    deflated, SC), that a mixed solve of its operator had to finish
+                                    in FP64; a solve with this flag in a mode so marked runs in FP64
+                                    from the start (FP32 cannot resolve the operator).  The record
+                                    is cleared by esd_factor_ic0, esd_update_values,
+                                    esd_set_mixed_params and, for deflated and SC, a new W. */
 
 typedef struct {
     int32_t iters;        /* CG iterations (mixed: total inner iterations) */
@@ -269,7 +275,8 @@ esd_status esd_get_aux(esd_ctx *ctx, double *W, double *C);
 esd_status esd_set_power_start(esd_ctx *ctx, const double *v0);
 
 /* esd_set_mixed_params - inner relative tolerance of each FP32 inner solve
- * (default 1e-4) and the maximum number of FP64 refinement steps (default 30).
+ * (default 1e-4) and the maximum number of FP64 refinement steps (default 30);
+ * clears the record of earlier FP64 finishes (ESD_FLAG_MIXED_ADAPT).
  * With ESD_FLAG_MIXED_KEEP the inner tolerance is the reduction between two
  * residual replacements; about 1e-2 suits it: after much larger reductions the
  * FP32 recurrence has drifted far from the true residual, and replacing it

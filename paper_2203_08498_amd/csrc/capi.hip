@@ -176,6 +176,11 @@ struct esd_ctx {
     double inner_tol = 1e-4;
     int max_outer = 30;
     int stag_window = 50;
+    // per mode (plain, deflated, SC): a mixed solve of the current operator
+    // had to finish in FP64 (FP32 cannot resolve it); later mixed solves in
+    // that mode with ESD_FLAG_MIXED_ADAPT start in FP64.  Cleared by new
+    // values, a new factor, new mixed parameters and (deflated, SC) a new W.
+    bool fp32_short[3] = {false, false, false};
     bool factored = false;
     // captured iteration chunks (replayed with hipGraphLaunch), invalidated
     // whenever a buffer they reference is reallocated or the aux space changes
@@ -1119,8 +1124,12 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
     st = sync_read(c);
     if (st) return st;
     const double bn2 = c->Sh->bnorm2, tol2 = c->Sh->tol2;
-    int total = 0, outer = 0, done_in = 0, fp64_iters = 0, fp64_restarts = 0;
-    bool converged = false, fp64 = false;
+    // ESD_FLAG_MIXED_ADAPT: a context whose earlier mixed solve in this mode
+    // had to finish in FP64 starts there (its first FP64 run counts as no
+    // restart)
+    bool fp64 = (flags & ESD_FLAG_MIXED_ADAPT) != 0 && c->fp32_short[kind];
+    int total = 0, outer = 0, done_in = 0, fp64_iters = 0, fp64_restarts = fp64 ? -1 : 0;
+    bool converged = false;
     const bool method_b = sampling && c->samp_method == 1;
     if (method_b) arm_method_b(c, tol);
     double rn2 = 0.0, rn2_prev = -1.0;
@@ -1166,6 +1175,7 @@ esd_status solve_mixed(esd_ctx *c, const double *b, const double *x0, double tol
             // ... or an inner run that stagnated before taking two orders of
             // magnitude off the residual: FP32 cannot resolve this operator
             fp64 = true;
+            c->fp32_short[kind] = true;
         }
         rn2_prev = rn2;
         if (fp64) {
@@ -1357,6 +1367,7 @@ esd_status finish_aux(esd_ctx *c, int k) {
         }
     if (!esd::cholesky_inverse(k, C, Cinv)) return fail(c, ESD_ENOTSPD, "W^T A W is not positive definite");
     c->Ch = C;
+    c->fp32_short[1] = c->fp32_short[2] = false; // a new W: the deflated / SC operators changed
     HIPCHK(hipMemcpyAsync(c->Cinv, Cinv.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, c->stream));
     if (c->mixed) {
         esd::launch_cast((int64_t)k * n, c->W, c->W32, c->stream);
@@ -1656,6 +1667,7 @@ esd_status esd_factor_ic0(esd_ctx *c) {
         return fail(c, ESD_ENOTSPD, "IC(0) pivot <= 0");
     }
     c->factored = true;
+    for (bool &f : c->fp32_short) f = false;
     return refresh_y(c); // M^{-1} A W for the new factor
 }
 
@@ -1669,6 +1681,7 @@ esd_status esd_update_values(esd_ctx *c, const double *val) {
     c->factored = false;
     c->y_ok = false;
     c->lam_last = 0.0;
+    for (bool &f : c->fp32_short) f = false;
     if (c->aux_built && c->m_tilde > 0) {
         // keep W, refresh AW = A W and C = W^T A W for the new values
         esd::launch_spmm((int)c->n, c->A.e64(), c->W, c->m_tilde, c->AW, c->stream);
@@ -1713,6 +1726,7 @@ esd_status esd_set_mixed_params(esd_ctx *c, double inner_tol, int32_t max_outer)
     if (!c || !(inner_tol > 0 && inner_tol < 1) || max_outer < 1) return ESD_EINVAL;
     c->inner_tol = inner_tol;
     c->max_outer = max_outer;
+    for (bool &f : c->fp32_short) f = false;
     return ESD_OK;
 }
 

@@ -20,6 +20,7 @@ PLAIN, DEFLATED, SUBSPACE = 0, 1, 2
 FLAG_NOPREC, FLAG_POWER, FLAG_MIXED, FLAG_SYNC_EVERY, FLAG_TIMING, FLAG_TIMING_SPMV, FLAG_TRUE_RES = 1, 2, 4, 8, 16, 32, 64
 FLAG_STREAM = 128
 FLAG_MIXED_KEEP = 256
+FLAG_MIXED_ADAPT = 512
 SAMPLING_A, SAMPLING_B, SAMPLE_RESIDUALS = 0, 1, 16
 RR_A, RR_PRECONDITIONED = 0, 1
 OK, NOT_CONVERGED, AUX_EMPTY = 0, 1, 2

@@ -579,6 +579,48 @@ def test_mixed_sampling_continues_in_the_fp64_finish(method):
     s.close()
 
 
+def test_mixed_solver_remembers_an_fp64_finish():
+    """ESD_FLAG_MIXED_ADAPT: a mixed solve that had to finish in FP64 (inner
+    tolerance 0.9: the refinement stalls) makes the context's later adaptive
+    mixed solves in that mode run in FP64 from the start (every iteration
+    FP64); the deflated mode keeps its own record; a new factor clears the
+    record, and so do new mixed parameters (with the default ones FP32
+    resolves this operator); without the flag a solve ignores the record."""
+    from paper_2203_08498_amd import esd
+
+    p = CASES["fv3d_class"]
+    s = _solver(p)
+    s.factor_ic0()
+    o = _oracle(p)
+    _own_aux(p, s, o)
+    runs = []
+
+    def solve(mode, adapt=True):
+        flags = esd.FLAG_MIXED | (esd.FLAG_MIXED_ADAPT if adapt else 0)
+        x, info = s.solve(p.f, tol=1e-8, maxit=5000, mode=mode, flags=flags)
+        print("mixed mode", mode, "its", info["iters"], "fp64", info["fp64_iters"], "outer", info["outer_iters"],
+              "true relres", info["true_relres"], flush=True)
+        assert info["converged"] and info["true_relres"] <= 1e-8
+        runs.append(info)
+
+    try:
+        s.set_mixed_params(0.9, 30)
+        for mode in (esd.PLAIN, esd.PLAIN, esd.DEFLATED, esd.DEFLATED):
+            solve(mode)
+        solve(esd.PLAIN, adapt=False)
+        s.factor_ic0()
+        solve(esd.PLAIN)
+    finally:
+        s.set_mixed_params()
+    solve(esd.PLAIN)
+    a, b, c, d, g, e, f = runs
+    assert 0 < a["fp64_iters"] < a["iters"] and b["fp64_iters"] == b["iters"]
+    assert 0 < c["fp64_iters"] < c["iters"] and d["fp64_iters"] == d["iters"]
+    assert 0 < g["fp64_iters"] < g["iters"] and g["iters"] == a["iters"]
+    assert 0 < e["fp64_iters"] < e["iters"] and f["fp64_iters"] == 0
+    s.close()
+
+
 def test_power_iteration_kappa_es(case):
     from paper_2203_08498_amd import esd
 
