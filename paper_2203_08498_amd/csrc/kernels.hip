@@ -900,7 +900,18 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(FinRho f) {
         // rho partials, (r, r) and level-0 ||y||^2, and for deflation (AW)^T z
         // in one pass; tot = {(r, r), level-0 ||y||^2, preconditioner rho}
         const int nu = f.init ? 0 : f.nblk_upd;
-        if (f.m > 0) {
+        if (f.m > 0 && !f.init && f.part_s == f.part_upd && f.c0_s == 2 && f.nblk_s == f.nblk_upd &&
+            f.stride_s == f.stride_upd) {
+            // (AW)^T z rides on the update partials (columns 2 ..): one table of
+            // 2 + m columns, read once with half the threads
+            __shared__ double tu[2 + 64];
+            const ColTab tab[2] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 2},
+                                   {f.part_upd, nu, f.stride_upd, 0, 2 + f.m, tu}};
+            fin_colsums<2>(tab);
+            if (t < 2) tot[t] = tu[t];
+            if (t < f.m) sv[t] = tu[2 + t];
+            __syncthreads();
+        } else if (f.m > 0) {
             const ColTab tab[3] = {{f.part_sweep, f.nsweep, 1, 0, 1, tot + 2},
                                    {f.part_upd, nu, f.stride_upd, 0, 2, tot + 0},
                                    {f.part_s, f.nblk_s, f.stride_s, f.c0_s, f.m, sv}};
