@@ -437,7 +437,7 @@ template <> VecSet<float> vecs<float>(esd_ctx *c) {
 // launches that finish rows of z write (r, z + W u).  Returns the number of
 // partial slots.
 template <typename T>
-int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_l0 = false) {
+int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_l0 = false, bool skip_bwd0 = false) {
     esd::Sweep<T> s{};
     s.n = (int)c->n;
     s.S = c->S;
@@ -481,7 +481,9 @@ int launch_prec(esd_ctx *c, const VecSet<T> &V, bool noprec, bool sc, bool skip_
         if (last || !sc) off += g;
     }
     s.M = V.U;
-    for (int l = nl - 2; l >= 0; --l) {
+    // skip_bwd0 (no subspace correction): the first level's backward step is
+    // left to the projection launch (launch_bwd0_proj)
+    for (int l = nl - 2; l >= ((skip_bwd0 && !sc && nl >= 2) ? 1 : 0); --l) {
         s.r0 = (int)c->lvl[l]; s.r1 = (int)c->lvl[l + 1];
         s.tmap = c->tmap_lvl + c->tmap_off[l];
         const bool pair = esd::sweep_pairs(s.r1 - s.r0);
@@ -610,6 +612,10 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *ite
     ta.n = n; ta.m = m; ta.Wrm = defl ? V.AWrm : V.Wrm; ta.v = defl ? V.z : V.r; ta.part = c->part_ts; ta.S = c->S;
     esd::Proj<T> pa{};
     pa.n = n; pa.m = m; pa.S = c->S; pa.z = V.z; pa.W = V.W; pa.tmap = c->tmap;
+    // the first level's backward step inside the projection launch (see fuse_bp)
+    esd::Sweep<T> b0{};
+    b0.n = n; b0.S = c->S; b0.M = V.U; b0.dinv = V.dinv; b0.y = V.y; b0.z = V.z; b0.r = V.r; b0.zsc = V.z;
+    b0.r0 = 0; b0.r1 = c->lvl.size() > 1 ? (int)c->lvl[1] : 0;
     // z_0 = M^{-1} r_0 (+ W u), rho_0 (and p_0 = zhat_0 for deflation)
     {
         const int ns = launch_prec<T>(c, V, o.noprec, sc);
@@ -643,6 +649,16 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *ite
         else if (defl) G = o.noprec ? V.AW : (c->y_ok ? V.Y : nullptr);
     }
     const int su = esd::update_stride(G ? m : 0); // partial columns of the update launch
+    // FP64 deflation with Y^T r in the update: rho and mu are known once the
+    // forward sweep is done, so the rho finalize runs before the first
+    // level's backward step, which the projection launch then takes over
+    // (one launch fewer: 128^3 FP64 deflated iteration 156.6 -> 153.4 us, Q1
+    // 730.7 -> 726.9 us).  A first level of more than kPairTiles tiles keeps
+    // its two-row backward launch (256^3: 1687 against 1703 us fused);
+    // stream launches with per-launch timing keep the separate form, so that
+    // the timed sweeps are the whole pair.
+    const bool fuse_bp = sizeof(T) == 8 && defl && G != nullptr && !bj_fused && !o.noprec && nl >= 2 &&
+                         !o.timing_all && !esd::sweep_pairs(c->lvl[1]);
     // update launches and their partial rows.  With G^T r the one-block
     // finalize reads 2 + m columns per block, so the grid gives each block
     // about eight tiles, 1024 to 2048 blocks (128^3: 1024 blocks, FP64
@@ -722,7 +738,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *ite
                     }
                 }
                 if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 2], c->stream)) != hipSuccess) return e;
-                fr.nsweep = launch_prec<T>(c, V, o.noprec, sc, fuse_l0);
+                fr.nsweep = launch_prec<T>(c, V, o.noprec, sc, fuse_l0, fuse_bp);
                 if (o.timing_all && (e = hipEventRecord(c->ev[4 * j + 3], c->stream)) != hipSuccess) return e;
             }
             if (defl && !G) esd::launch_tsdot_rm(ta, gt, c->stream);
@@ -731,7 +747,12 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *ite
                 // direction of iteration it + 1
                 pa.pold = V.p[(it + 1) & 1];
                 pa.pnew = V.p[it & 1];
-                esd::launch_proj(pa, gn, c->stream);
+                if constexpr (sizeof(T) == 8) {
+                    if (fuse_bp) esd::launch_bwd0_proj(b0, pa, gn, c->stream);
+                    else esd::launch_proj(pa, gn, c->stream);
+                } else {
+                    esd::launch_proj(pa, gn, c->stream);
+                }
             }
         }
         return hipGetLastError();

@@ -1021,6 +1021,48 @@ __global__ __launch_bounds__(kBlock) void k_proj(Proj<T> a) {
     }
 }
 
+// The projection of k_proj over all rows, with the backward sweep of the
+// first level (rows [0, b.r1), b.M = U) done in the same launch: a row of that
+// level forms z_i as k_bwd forms it (from z of the later levels, complete) and
+// projects it at once.  Needs beta and mu before the launch, so the rho
+// finalize runs before it (rho = ||y||^2 is complete after the forward sweep;
+// mu comes from the update's Y^T r).  Tiles of the whole range are 256-row
+// aligned, so a wavefront's rows share one slice.
+template <typename T, int MT>
+__global__ __launch_bounds__(kBlock) void k_bwd0_proj(Sweep<T> b, Proj<T> a) {
+    const Scal *S = a.S;
+    if (S->done) return;
+    const bool first = (S->iter == 0);
+    const T beta = first ? T(0) : (T)S->beta;
+    double mu[MT];
+#pragma unroll
+    for (int k = 0; k < MT; ++k) mu[k] = (k < a.m) ? S->mu[k] : 0.0;
+    const int n = a.n;
+    const T *z = b.z;
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; ++t) {
+        const int i = (a.tmap ? a.tmap[t] : t) * kBlock + threadIdx.x;
+        if (i >= n) continue;
+        T w[MT];
+#pragma unroll
+        for (int k = 0; k < MT; ++k) w[k] = ld_col(&a.W[(size_t)(k < a.m ? k : a.m - 1) * n + i]);
+        const T po = first ? T(0) : a.pold[i];
+        T zi;
+        if (i < b.r1) {
+            const T sb = b.y[i] - ell_dot<true>(b.M, i, n, [&](int c) { return z[c]; });
+            zi = sb * b.dinv[i];
+            b.z[i] = zi;
+        } else {
+            zi = z[i];
+        }
+        double s = (double)zi;
+#pragma unroll
+        for (int k = 0; k < MT; ++k) s -= (double)w[k] * mu[k];
+        const T zh = (T)s;
+        a.pnew[i] = first ? zh : zh + beta * po;
+    }
+}
+
 // FP32 projection with two rows per thread (tiles t and t + 1), all loads of
 // both rows first; same arithmetic per row as k_proj
 template <typename T, int MT>
@@ -1605,6 +1647,13 @@ template <typename T> static void proj_impl(const Proj<T> &a, int grid, hipStrea
 }
 void launch_proj(const Proj<double> &a, int grid, hipStream_t s) { proj_impl(a, grid, s); }
 void launch_proj(const Proj<float> &a, int grid, hipStream_t s) { proj_impl(a, grid, s); }
+template <typename T> static void bwd0_proj_impl(const Sweep<T> &b, const Proj<T> &a, int grid, hipStream_t s) {
+    if (a.m <= 8) k_bwd0_proj<T, 8><<<grid, kBlock, 0, s>>>(b, a);
+    else k_bwd0_proj<T, 16><<<grid, kBlock, 0, s>>>(b, a);
+}
+void launch_bwd0_proj(const Sweep<double> &b, const Proj<double> &a, int grid, hipStream_t s) {
+    bwd0_proj_impl(b, a, grid, s);
+}
 
 template <typename T> static void tsdot_impl(const TsDot<T> &a, int grid, hipStream_t s) {
     switch (pow2_at_least(a.m)) {
