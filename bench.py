@@ -28,7 +28,9 @@ is measured with hipEvents on the solver's stream around every executed
 launch of system 2 of the deflated and of the plain sequence of each timed
 step (both run that system with stream launches, all other solves replay the
 captured iteration graphs).  The same events bracket the IC(0) sweep
-launches (sweeps GB/s).  `traffic` comes from the committed rocprofv3 counter
+launches (sweeps GB/s; the timed system keeps the first level's backward
+launch apart from the projection, which the other deflated FP64 solves fold
+into it, so the pair is whole).  `traffic` comes from the committed rocprofv3 counter
 summary.  `hbm_ceiling`: the library's hand-written streaming probes (copy
 and read-only reduction) beside torch's copy.  cpu_baseline: the FP64 C
 oracle, one thread.
