@@ -649,7 +649,7 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *ite
         else if (defl) G = o.noprec ? V.AW : (c->y_ok ? V.Y : nullptr);
     }
     const int su = esd::update_stride(G ? m : 0); // partial columns of the update launch
-    // FP64 deflation with Y^T r in the update: rho and mu are known once the
+    // deflation with Y^T r in the update: rho and mu are known once the
     // forward sweep is done, so the rho finalize runs before the first
     // level's backward step, which the projection launch then takes over
     // (one launch fewer: 128^3 FP64 deflated iteration 156.6 -> 153.4 us, Q1
@@ -657,8 +657,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *ite
     // its two-row backward launch (256^3: 1687 against 1703 us fused);
     // stream launches with per-launch timing keep the separate form, so that
     // the timed sweeps are the whole pair.
-    const bool fuse_bp = sizeof(T) == 8 && defl && G != nullptr && !bj_fused && !o.noprec && nl >= 2 &&
-                         !o.timing_all && !esd::sweep_pairs(c->lvl[1]);
+    const bool fuse_bp = defl && G != nullptr && !bj_fused && !o.noprec && nl >= 2 && !o.timing_all &&
+                         !esd::sweep_pairs(c->lvl[1]);
     // update launches and their partial rows.  With G^T r the one-block
     // finalize reads 2 + m columns per block, so the grid gives each block
     // about eight tiles, 1024 to 2048 blocks (128^3: 1024 blocks, FP64
@@ -747,12 +747,8 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *ite
                 // direction of iteration it + 1
                 pa.pold = V.p[(it + 1) & 1];
                 pa.pnew = V.p[it & 1];
-                if constexpr (sizeof(T) == 8) {
-                    if (fuse_bp) esd::launch_bwd0_proj(b0, pa, gn, c->stream);
-                    else esd::launch_proj(pa, gn, c->stream);
-                } else {
-                    esd::launch_proj(pa, gn, c->stream);
-                }
+                if (fuse_bp) esd::launch_bwd0_proj(b0, pa, gn, c->stream);
+                else esd::launch_proj(pa, gn, c->stream);
             }
         }
         return hipGetLastError();

@@ -244,6 +244,7 @@ void launch_proj(const Proj<float> &a, int grid, hipStream_t s);
 // the projection (m <= 16) with the backward sweep of the first level (b: rows
 // [0, b.r1), b.M = U) in the same launch; grid as for launch_proj
 void launch_bwd0_proj(const Sweep<double> &b, const Proj<double> &a, int grid, hipStream_t s);
+void launch_bwd0_proj(const Sweep<float> &b, const Proj<float> &a, int grid, hipStream_t s);
 void launch_tsdot_rm(const TsDot<double> &a, int grid, hipStream_t s);
 void launch_tsdot_rm(const TsDot<float> &a, int grid, hipStream_t s);
 int tsdot_stride(int m);

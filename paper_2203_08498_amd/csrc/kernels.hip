@@ -1063,6 +1063,62 @@ __global__ __launch_bounds__(kBlock) void k_bwd0_proj(Sweep<T> b, Proj<T> a) {
     }
 }
 
+// k_bwd0_proj with two rows per thread (tiles t and t + 1, all loads of both
+// rows first) for FP32 vectors of more than kPairTiles tiles, as k_proj2
+// does; each row computed as k_bwd0_proj computes it
+template <typename T, int MT>
+__global__ __launch_bounds__(kBlock) void k_bwd0_proj2(Sweep<T> b, Proj<T> a) {
+    const Scal *S = a.S;
+    if (S->done) return;
+    const bool first = (S->iter == 0);
+    const T beta = first ? T(0) : (T)S->beta;
+    double mu[MT];
+#pragma unroll
+    for (int k = 0; k < MT; ++k) mu[k] = (k < a.m) ? S->mu[k] : 0.0;
+    const int n = a.n;
+    const T *z = b.z;
+    const auto gz = [&](int c) { return z[c]; };
+    const Tiles tl = my_tiles(n);
+    for (int t = tl.t0; t < tl.t1; t += 2) {
+        int i[2];
+        bool h[2], l0[2];
+        T zv[2], pv[2], yv[2], dv[2], wv[2][MT];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int tt = t + u;
+            i[u] = tt < tl.t1 ? (a.tmap ? a.tmap[tt] : tt) * kBlock + threadIdx.x : n;
+            h[u] = i[u] < n;
+            l0[u] = h[u] && i[u] < b.r1;
+            const int iu = h[u] ? i[u] : 0;
+            pv[u] = (h[u] && !first) ? a.pold[i[u]] : T(0);
+            zv[u] = (h[u] && !l0[u]) ? z[i[u]] : T(0);
+            yv[u] = l0[u] ? b.y[i[u]] : T(0);
+            dv[u] = l0[u] ? b.dinv[i[u]] : T(0);
+#pragma unroll
+            for (int k = 0; k < MT; ++k) wv[u][k] = ld_col(&a.W[(size_t)(k < a.m ? k : a.m - 1) * n + iu]);
+        }
+        T s0, s1;
+        ell_dot_pair<true>(b.M, i[0], l0[0], i[1], l0[1], n, gz, s0, s1);
+        if (l0[0]) {
+            zv[0] = (yv[0] - s0) * dv[0];
+            b.z[i[0]] = zv[0];
+        }
+        if (l0[1]) {
+            zv[1] = (yv[1] - s1) * dv[1];
+            b.z[i[1]] = zv[1];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!h[u]) continue;
+            double s = (double)zv[u];
+#pragma unroll
+            for (int k = 0; k < MT; ++k) s -= (double)wv[u][k] * mu[k];
+            const T zh = (T)s;
+            a.pnew[i[u]] = first ? zh : zh + beta * pv[u];
+        }
+    }
+}
+
 // FP32 projection with two rows per thread (tiles t and t + 1), all loads of
 // both rows first; same arithmetic per row as k_proj
 template <typename T, int MT>
@@ -1648,10 +1704,14 @@ template <typename T> static void proj_impl(const Proj<T> &a, int grid, hipStrea
 void launch_proj(const Proj<double> &a, int grid, hipStream_t s) { proj_impl(a, grid, s); }
 void launch_proj(const Proj<float> &a, int grid, hipStream_t s) { proj_impl(a, grid, s); }
 template <typename T> static void bwd0_proj_impl(const Sweep<T> &b, const Proj<T> &a, int grid, hipStream_t s) {
-    if (a.m <= 8) k_bwd0_proj<T, 8><<<grid, kBlock, 0, s>>>(b, a);
+    if (stream_pairs<T>(a.n) && a.m <= 8) k_bwd0_proj2<T, 8><<<grid, kBlock, 0, s>>>(b, a);
+    else if (a.m <= 8) k_bwd0_proj<T, 8><<<grid, kBlock, 0, s>>>(b, a);
     else k_bwd0_proj<T, 16><<<grid, kBlock, 0, s>>>(b, a);
 }
 void launch_bwd0_proj(const Sweep<double> &b, const Proj<double> &a, int grid, hipStream_t s) {
+    bwd0_proj_impl(b, a, grid, s);
+}
+void launch_bwd0_proj(const Sweep<float> &b, const Proj<float> &a, int grid, hipStream_t s) {
     bwd0_proj_impl(b, a, grid, s);
 }
 

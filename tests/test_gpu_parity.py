@@ -738,10 +738,11 @@ def test_graph_replays_match_stream_launches(case):
 
 
 def test_first_level_backward_in_the_projection(case):
-    """FP64 deflation with Y^T r: the first level's backward step runs inside
-    the projection launch (rho finalized before it).  Solves with per-launch
-    timing keep the separate launches; both forms compute every row the same
-    way, so the solutions, iteration counts and kappa are bit-identical."""
+    """Deflation with Y^T r: the first level's backward step runs inside the
+    projection launch (rho finalized before it), in FP64 and in the FP32
+    inner solves.  Solves with per-launch timing keep the separate launches;
+    both forms compute every row the same way, so the solutions, iteration
+    counts and kappa are bit-identical."""
     import torch
 
     from paper_2203_08498_amd import esd
@@ -754,6 +755,10 @@ def test_first_level_backward_in_the_projection(case):
     assert i_f["iters"] == i_s["iters"] and torch.equal(xf, xs) and i_f["kappa"] == i_s["kappa"]
     y, oi = o.solve(p.f, tol=1e-8, maxit=5000, mode=O.DEFLATED)
     assert abs(i_f["iters"] - oi.iters) <= 2 and _relerr(xf, y) <= 1e-10
+    xf, i_f = s.solve(p.f, tol=1e-8, maxit=5000, mode=esd.DEFLATED, flags=esd.FLAG_MIXED)
+    xs, i_s = s.solve(p.f, tol=1e-8, maxit=5000, mode=esd.DEFLATED, flags=esd.FLAG_MIXED | esd.FLAG_TIMING)
+    print(name, "mixed deflated its fused", i_f["iters"], "separate", i_s["iters"], flush=True)
+    assert i_f["iters"] == i_s["iters"] and torch.equal(xf, xs) and i_f["kappa"] == i_s["kappa"]
 
 
 def test_gradient_values(case):
