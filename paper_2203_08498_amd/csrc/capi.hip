@@ -652,8 +652,9 @@ esd_status krylov(esd_ctx *c, const VecSet<T> &V0, const KrylovOpts &o, int *ite
     // deflation with Y^T r in the update: rho and mu are known once the
     // forward sweep is done, so the rho finalize runs before the first
     // level's backward step, which the projection launch then takes over
-    // (one launch fewer: 128^3 FP64 deflated iteration 156.6 -> 153.4 us, Q1
-    // 730.7 -> 726.9 us).  A first level of more than kPairTiles tiles keeps
+    // (one launch fewer: 128^3 FP64 deflated iteration 156.6 -> 153.4 us,
+    // FP32 with two rows per thread 103.8 -> 101.1 us; Q1 FP64 730.7 ->
+    // 726.9 us).  A first level of more than kPairTiles tiles keeps
     // its two-row backward launch (256^3: 1687 against 1703 us fused);
     // stream launches with per-launch timing keep the separate form, so that
     // the timed sweeps are the whole pair.
